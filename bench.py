@@ -1,0 +1,187 @@
+#!/usr/bin/env python3
+"""HOTRG throughput on one MI355X, with roofline and CPU-oracle baseline.
+
+One benchmark step is one full HOTRG run of the gXY workload at Dcut = 64:
+beta = 1.2, Delta = 0.7, charges |n| <= 10 (D0 = 21), 40 coarse-graining
+steps alternating y/x, both impurity chains (<cos theta>, <cos 2 theta>),
+FP64 contractions, FP64 eigensolves. The input is resident on the device
+(the initial tensor is built there from (beta, Delta)); the timed region
+covers every step of the path.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Prints one JSON line. value = coarse-graining steps per second (40 per run).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "HOTRG steps/s & MFMA util at D=64; batched (β,Δ) points/s at |δf|≤1e-9"
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def workload_point(dcut: int):
+    from paper_2609_20536_amd import workloads as W
+    return W.precision_point(dcut=dcut, prec=W.PREC_FP64, impurities=W.IMP_COS1 | W.IMP_COS2)
+
+
+def cpu_baseline(dcut: int, nimp: int, frac_cols: int = 8):
+    """Time the CPU oracle on a bounded sample of one coarse-graining step.
+
+    Sample: one y-step of the oracle on a synthetic charge-conserving
+    Dcut^4 tensor (charges -7..7): both environments, the per-sector
+    eigensolves and the projection restricted to frac_cols of the Dcut output
+    columns. One step costs env + eig + (1 + 2 nimp) full projections, the
+    projection being linear in the number of output columns.
+    """
+    import numpy as np
+    import oracle.hotrg as o
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count() or 1
+    rng = np.random.default_rng(20536)
+    D = dcut
+    mult = np.maximum(1, np.round(np.exp(-0.5 * (np.arange(-7, 8) / 3.0) ** 2) * 8)).astype(int)
+    labels = np.repeat(np.arange(-7, 8), mult)
+    labels = np.sort(np.resize(labels, D))
+    l, r, u, d = np.meshgrid(labels, labels, labels, labels, indexing="ij")
+    T = rng.standard_normal((D, D, D, D)) * ((l + d) == (r + u))
+    T /= np.sqrt(np.sum(T * T))
+    t0 = time.perf_counter()
+    EL, ER = o.environments(T)
+    t_env = time.perf_counter() - t0
+    fused = o.fuse_labels(labels, labels, o.SYM_U1)
+    t0 = time.perf_counter()
+    secL = o.sector_eigh(EL, fused)
+    secR = o.sector_eigh(ER, fused)
+    sel = o.select_states(secL, secR, D, D * D)
+    t_eig = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    o.project(sel.P[:, :frac_cols], T, T)
+    t_proj = (time.perf_counter() - t0) * (D / frac_cols)
+    per_step = t_env + t_eig + (1 + 2 * nimp) * t_proj
+    return {
+        "value": 1.0 / per_step,
+        "unit": "HOTRG steps/s",
+        "cores": int(cores),
+        "kind": "oracle",
+        "sample": (f"one y-step at Dcut={D} on a synthetic charge-conserving tensor: "
+                   f"environments {t_env:.2f}s + sector eigensolves {t_eig:.2f}s + "
+                   f"projection over {frac_cols}/{D} output columns scaled to {t_proj:.2f}s "
+                   f"x {1 + 2 * nimp} placements (pure + 2 per impurity chain)"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--dcut", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--phases", action="store_true", help="one extra untimed run with phase timers")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the HOTRG path here runs on a single MI355X "
+              "(no multi-GPU path is built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2609_20536_amd import hotrg as H
+
+    pt = workload_point(args.dcut)
+    ctx = H.Context(0)
+    ctx.reserve([pt])
+    os.environ.pop("GXY_TIMING", None)
+    def note(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    for i in range(args.warmup):
+        t1 = time.perf_counter()
+        ctx.run(pt)
+        note(f"bench: warmup run {i + 1}/{args.warmup} done in {time.perf_counter() - t1:.1f}s")
+    torch.cuda.synchronize()
+    os.environ["GXY_HOT_EVENTS"] = "1"
+    ctx.hot_kernel_stats(reset=True)
+    results = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        results.append(ctx.run(pt))
+        note(f"bench: timed run {i + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    os.environ.pop("GXY_HOT_EVENTS", None)
+    launches, ms, flops, nbytes = ctx.hot_kernel_stats(reset=True)
+    r = results[-1]
+    if r.status != 0:
+        raise SystemExit(f"run failed: status {r.status}")
+    hot_avg_ms = ms / max(launches, 1)
+    hot_tflops = (flops / max(launches, 1)) / (hot_avg_ms * 1e-3) / 1e12 if ms > 0 else 0.0
+    phases = None
+    if args.phases:
+        os.environ["GXY_TIMING"] = "1"
+        ctx.run(pt)
+        note("bench: phase-timing run done")
+        os.environ.pop("GXY_TIMING", None)
+        phases = dict(zip(["init", "environment", "eigensolve", "selection", "projection",
+                           "norm_permute"], [round(x, 2) for x in ctx.phase_times()]))
+    steps_per_run = pt.nsteps
+    value = steps_per_run * args.steps / elapsed
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "HOTRG steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1000.0 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"gxy-hotrg beta={pt.beta} Delta={pt.delta} nmax={pt.nmax} "
+                         f"Dcut={pt.dcut} {pt.nsteps} steps, cos+cos2 impurity chains, "
+                         f"FP64 contractions and eigensolves"),
+            "coarse_graining_steps_per_run": steps_per_run,
+            "lnz_per_site": r.lnz_per_site,
+            "max_trunc_err": r.max_trunc_err,
+        },
+        "roofline": {
+            "bound": "mfma",
+            "kernel": "projection D^7 GEMM (gemm_f64_kernel, Y = X T)",
+            "achieved": hot_tflops,
+            "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": hot_tflops / PEAK_FP64_TFLOPS,
+            "traffic": None,
+            "launches": int(launches),
+            "avg_launch_ms": hot_avg_ms,
+            "flops_per_launch": flops / max(launches, 1),
+        },
+        "cpu_baseline": None,
+    }
+    if phases:
+        line["phases_ms"] = phases
+    if not args.no_cpu_baseline:
+        note("bench: timing the CPU oracle sample")
+        line["cpu_baseline"] = cpu_baseline(pt.dcut, 2)
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,169 @@
+/*
+ * gxy_hotrg.h — C ABI of the MI355X (gfx950) HOTRG library for the 2D
+ * generalized XY model.
+ *
+ * A run follows the thesis's statement of the problem (Ch. 3, "Tensor
+ * Formulation" and "Derivation of Tensors for the Generalized XY Model";
+ * Ch. 2, "Higher-Order Tensor Renormalization Group Method"):
+ *   character coefficients t_n of exp(beta[Delta cos phi + (1-Delta) cos 2phi])
+ *   -> rank-4 site tensor T[l][r][u][d] (and impurity tensors for <cos theta>,
+ *      <cos 2 theta>)
+ *   -> nsteps HOTRG coarse-graining steps (fused two-site tensor M, environment
+ *      Gram matrices, FP64 eigendecomposition = HOSVD factors, truncation to
+ *      dcut, projection P^T M P), alternating vertical / horizontal
+ *   -> ln Z per site and the impurity expectation values.
+ *
+ * Conventions
+ *   - Site tensor legs are (l, r, u, d); the charge law at zero field is
+ *     q_l + q_d = q_r + q_u (the thesis's n1 + n2 - n3 - n4 = 0 with legs
+ *     (top, right, bottom, left) = (u, r, d, l)).
+ *   - Step 1 contracts the vertical bond; steps alternate.
+ *   - All functions return a gxy_status; none aborts, exits or throws.
+ *   - Host pointers are owned by the caller and only read/written during
+ *     the call. Device memory is either library-allocated (hipMalloc, freed
+ *     by gxy_destroy) or supplied by the caller through gxy_set_workspace.
+ *   - Work is issued on the stream given to gxy_create; every call that
+ *     returns results to host memory synchronises that stream before
+ *     returning. One context must not be used by two host threads at once.
+ *   - Nothing is printed unless the environment variable GXY_LOG is set.
+ */
+#ifndef GXY_HOTRG_H
+#define GXY_HOTRG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GXY_OK = 0,
+  GXY_EINVAL = 1,        /* invalid argument; no device work was issued     */
+  GXY_ENOMEM = 2,        /* device memory (or the caller's workspace) short */
+  GXY_EDEVICE = 3,       /* a HIP runtime call failed                       */
+  GXY_ENUMERIC = 4,      /* non-finite or non-positive trace, no eigen
+                            convergence                                      */
+  GXY_EUNSUPPORTED = 5,  /* valid request this build does not implement     */
+  GXY_EPARTIAL = 6       /* batch: at least one run failed (see per-run)    */
+} gxy_status;
+
+typedef enum {
+  GXY_PREC_FP64 = 0,     /* all contractions in FP64 MFMA                   */
+  GXY_PREC_FP32 = 1,     /* contractions in FP32 MFMA, FP32 accumulation    */
+  GXY_PREC_BF16X3 = 2    /* contractions as hi*hi + hi*lo + lo*hi BF16 MFMA
+                            with FP32 accumulation                          */
+} gxy_precision;
+
+enum { GXY_IMP_COS1 = 1u, GXY_IMP_COS2 = 2u };
+
+/* One HOTRG run (one point of the (beta, Delta, h, h1) parameter space). */
+typedef struct {
+  double beta;          /* inverse temperature, >= 0                         */
+  double delta;         /* deformation, 0 <= delta <= 1 (J = delta, J1 = 1-delta) */
+  double h;             /* field coupling to cos theta                       */
+  double h1;            /* field coupling to cos 2 theta                     */
+  int32_t nmax;         /* charges |n| <= nmax, initial bond D0 = 2 nmax + 1; 0..64 */
+  int32_t dcut;         /* truncation bond dimension, 1..128                 */
+  int32_t nsteps;       /* coarse-graining steps, 0..62 (lattice 2^nsteps sites) */
+  int32_t nquad;        /* quadrature points for t_n, > 2 nmax              */
+  uint32_t impurities;  /* GXY_IMP_* bitmask                                 */
+  int32_t prec;         /* gxy_precision of the contractions                 */
+  int32_t fp64_steps;   /* mixed precision: the first fp64_steps steps in FP64 */
+} gxy_point;
+
+typedef struct {
+  double lnz_per_site;  /* ln Z / 2^nsteps                                   */
+  double m_cos1;        /* <cos theta>   (NaN if not requested)              */
+  double m_cos2;        /* <cos 2 theta> (NaN if not requested)              */
+  double max_trunc_err; /* max over steps of eps_chosen / trace(E)          */
+  double min_cut_gap;   /* min over steps of (lam_D - lam_{D+1}) / lam_1     */
+  int32_t near_ties;    /* number of tie-rule activations                   */
+  int32_t status;       /* gxy_status of this run                            */
+  int32_t fail_step;    /* step at which it failed, -1 if none               */
+  int32_t nsteps_done;
+} gxy_result;
+
+/* Per-step diagnostics of the last run (or of run `run` of the last batch). */
+typedef struct {
+  double lnc;           /* ln of the Frobenius norm divided out this step    */
+  double eps_l, eps_r;  /* discarded weights of the left / right environment */
+  double lam_max;       /* largest environment eigenvalue                    */
+  double cut_gap;       /* (lam_D - lam_{D+1}) / lam_1 of the chosen side    */
+  int32_t side;         /* 0 = left factor U, 1 = right factor V             */
+  int32_t dh, dv;       /* bond dimensions after the step (l/r, u/d)         */
+  int32_t truncated;    /* 0 if the fused bond fit (P = identity)            */
+  int32_t ties;
+  int32_t pad_;
+} gxy_step_info;
+
+typedef struct gxy_ctx gxy_ctx;
+
+/* Create a context on HIP device `device`, issuing work on `hip_stream`
+ * (a hipStream_t; NULL = the null stream). */
+gxy_status gxy_create(gxy_ctx **out, int device, void *hip_stream);
+gxy_status gxy_destroy(gxy_ctx *ctx);
+
+/* Device bytes needed to run the n points (largest single run). */
+gxy_status gxy_workspace_bytes(gxy_ctx *ctx, const gxy_point *pts, int32_t n,
+                               size_t *bytes);
+/* Use caller-owned device memory (e.g. a torch tensor) as workspace. The
+ * library never frees it; the caller keeps it alive while the context uses it.
+ * Passing NULL returns to library-owned memory. */
+gxy_status gxy_set_workspace(gxy_ctx *ctx, void *dev_ptr, size_t bytes);
+
+/* Character coefficients t_n, n = -nmax..nmax (Ch. 3, eq. a_n as the
+ * Fourier integral of the bond weight), computed on the device by the
+ * nquad-point trapezoid rule; t is a host array of 2 nmax + 1 doubles. */
+gxy_status gxy_char_coeffs(gxy_ctx *ctx, double beta, double delta,
+                           int32_t nmax, int32_t nquad, double *t);
+
+/* Initial site tensor T[l][r][u][d] (Ch. 3, final site-tensor equation) or an
+ * impurity tensor (which = 0 pure, GXY_IMP_COS1, GXY_IMP_COS2; the two
+ * impure-tensor equations of Ch. 3), built on the device and copied to the
+ * host array out of (2 nmax + 1)^4 doubles. Unnormalised. */
+gxy_status gxy_initial_tensor(gxy_ctx *ctx, const gxy_point *pt, int32_t which,
+                              double *out);
+
+/* One synchronous HOTRG run. */
+gxy_status gxy_run(gxy_ctx *ctx, const gxy_point *pt, gxy_result *out);
+
+/* n runs; per-run status in out[i].status; GXY_EPARTIAL if any failed. */
+gxy_status gxy_run_batch(gxy_ctx *ctx, const gxy_point *pts, int32_t n,
+                         gxy_result *out);
+
+/* Per-step diagnostics of run `run` of the last gxy_run (run = 0) or
+ * gxy_run_batch; writes min(cap, steps) entries and the count to *count. */
+gxy_status gxy_step_log(gxy_ctx *ctx, int32_t run, gxy_step_info *out,
+                        int32_t cap, int32_t *count);
+
+/* Observables of Ch. 3 (eqs. spech, susc, mag) from the seven runs of one
+ * (beta, Delta) point: lnz[3] = ln Z/V at beta-db, beta, beta+db;
+ * m_h[2] = <cos theta> at h = hc-dh, hc+dh; m_h1[2] = <cos 2 theta> at
+ * h1 = hc-dh1, hc+dh1. out[4] = (f, C_v, chi, chi_n). Evaluated on the device. */
+gxy_status gxy_observables(gxy_ctx *ctx, int32_t npts, const double *beta,
+                           const double *lnz, const double *m_h,
+                           const double *m_h1, double dbeta, double dh,
+                           double dh1, double *out);
+
+const char *gxy_status_string(gxy_status s);
+const char *gxy_last_error(gxy_ctx *ctx);
+
+/* Last run's device timing of each phase, in milliseconds: [0] coefficients
+ * and initial tensors, [1] environments, [2] eigensolver, [3] selection and
+ * projector, [4] projection contractions, [5] norms/permutes/trace. Valid when
+ * the environment variable GXY_TIMING is set during the run. */
+gxy_status gxy_phase_times(gxy_ctx *ctx, double *ms6);
+
+/* Accumulated device timing of the dominant contraction (the D^7 product
+ * Y = X T of the projection, Ch. 2 eq. renormalizedT) over the runs issued
+ * while GXY_TIMING or GXY_HOT_EVENTS was set: out4 = (launches, total milliseconds measured with
+ * HIP events on the context's stream, algorithmic flops, algorithmic bytes).
+ * reset != 0 clears the totals after reading. */
+gxy_status gxy_hot_kernel_stats(gxy_ctx *ctx, double *out4, int32_t reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GXY_HOTRG_H */

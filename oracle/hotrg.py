@@ -333,9 +333,12 @@ def select_states(secL: List[Sector], secR: List[Sector], dcut: int,
             for k, lam in enumerate(s.lam):
                 if (si, k) not in kept:
                     eps += float(lam)
-        lam_all = np.sort(np.concatenate([s.lam for s in secs]))[::-1]
-        lam1 = float(lam_all[0])
-        gap = float((lam_all[dcut - 1] - lam_all[dcut]) / lam1) if lam1 > 0 else 0.0
+        lam1 = max(float(s.lam[0]) for s in secs)
+        kept_l = [float(secs[si].lam[k]) for si, k in picks]
+        disc_l = [float(lam) for si, s in enumerate(secs)
+                  for k, lam in enumerate(s.lam) if (si, k) not in kept]
+        # cut gap: smallest kept minus largest discarded eigenvalue
+        gap = (min(kept_l) - max(disc_l)) / lam1 if lam1 > 0 else 0.0
         res[side] = (picks, eps, lam1, gap, ties)
     epsL, epsR = res[0][1], res[1][1]
     lam_max = max(res[0][2], res[1][2])

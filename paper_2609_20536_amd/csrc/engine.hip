@@ -1,0 +1,1199 @@
+// Host orchestration of HOTRG runs and the C ABI (include/gxy_hotrg.h).
+//
+// One run (Ch. 2 HOTRG on the Ch. 3 gXY site tensor):
+//   t_n, field factors, T and impurity tensors      (device, FP64)
+//   normalise (Frobenius), log-norm accumulation   (device, FP64)
+//   for each step: [transpose for x-steps]
+//     environments E_L, E_R of the fused two-site tensor (FP64 MFMA GEMMs)
+//     per-sector block-Jacobi eigensolve (FP64), truncation with the tie
+//     rule and side choice (device), projector P
+//     T' = P^T M P in three GEMMs chunked over the output index, impurity
+//     tensors symmetrised, normalise          [transpose back]
+//   trace, ln Z / V and <cos theta>, <cos 2 theta> (device)
+// The host only plans launches: it reads back the symmetry labels of the
+// kept states after each truncation to size the next step's sectors.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace gxy {
+
+constexpr double kTieRel = 1e-12;
+constexpr double kSideTol = 1e-12;
+constexpr int kMaxSweeps = 40;
+constexpr int kLmax = 50;
+
+enum Sym { SYM_U1 = 0, SYM_NONE = 1, SYM_Z2 = 2 };
+
+static bool env_flag(const char *name) {
+  const char *v = getenv(name);
+  return v && *v && strcmp(v, "0") != 0;
+}
+
+static size_t env_size(const char *name, size_t dflt) {
+  const char *v = getenv(name);
+  if (!v || !*v) return dflt;
+  return (size_t)strtoull(v, nullptr, 10);
+}
+
+// ---------------------------------------------------------------------------
+// workspace: one device block carved into aligned pieces
+// ---------------------------------------------------------------------------
+
+struct Carver {
+  size_t off = 0;
+  char *base = nullptr;
+  template <typename T>
+  T *take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+struct StepDims {
+  int dh, dv, dn;  // in y-orientation: legs l/r = dh, u/d = dv; output dn
+  bool xstep;
+};
+
+struct Plan {
+  int d0;
+  std::vector<StepDims> steps;
+  int64_t maxT = 0;       // elements of the largest site tensor
+  int64_t maxNF = 0;      // largest fused dimension that gets truncated
+  int64_t maxNFall = 0;   // largest fused dimension
+  int64_t maxPD = 0;      // largest P (nf * dn)
+  int maxDn = 0;
+  int64_t chunk_elems = 0;  // X / Y chunk buffer elements
+  int nimp = 0;
+};
+
+static Plan make_plan(const gxy_point &p, size_t chunk_bytes) {
+  Plan pl;
+  pl.d0 = 2 * p.nmax + 1;
+  int Dh = pl.d0, Dv = pl.d0;
+  pl.nimp = ((p.impurities & GXY_IMP_COS1) ? 1 : 0) + ((p.impurities & GXY_IMP_COS2) ? 1 : 0);
+  pl.maxT = (int64_t)Dh * Dh * Dv * Dv;
+  int64_t per_a_max = 1;
+  for (int n = 1; n <= p.nsteps; ++n) {
+    const bool xs = (n % 2 == 0);
+    StepDims sd;
+    sd.xstep = xs;
+    sd.dh = xs ? Dv : Dh;
+    sd.dv = xs ? Dh : Dv;
+    const int64_t nf = (int64_t)sd.dh * sd.dh;
+    sd.dn = (int)std::min<int64_t>(p.dcut, nf);
+    pl.steps.push_back(sd);
+    const int64_t t_in = (int64_t)sd.dh * sd.dh * sd.dv * sd.dv;
+    const int64_t t_out = (int64_t)sd.dn * sd.dn * sd.dv * sd.dv;
+    pl.maxT = std::max({pl.maxT, t_in, t_out});
+    pl.maxNFall = std::max(pl.maxNFall, nf);
+    if (nf > p.dcut) pl.maxNF = std::max(pl.maxNF, nf);
+    pl.maxPD = std::max(pl.maxPD, nf * sd.dn);
+    pl.maxDn = std::max(pl.maxDn, sd.dn);
+    per_a_max = std::max(per_a_max, (int64_t)sd.dh * sd.dv * sd.dh * sd.dv);
+    if (xs)
+      Dv = sd.dn;
+    else
+      Dh = sd.dn;
+  }
+  // chunk buffers: X (pure), X (impurity) and Y, each ac * per_a elements
+  const int nbuf = pl.nimp > 0 ? 3 : 2;
+  int64_t ac = (int64_t)(chunk_bytes / (sizeof(double) * nbuf * per_a_max));
+  ac = std::max<int64_t>(1, std::min<int64_t>(ac, pl.maxDn));
+  pl.chunk_elems = ac * per_a_max;
+  return pl;
+}
+
+struct Buffers {
+  double *T, *Tn, *T2;             // site tensor, next, bottom-operand copy
+  double *TX[2], *TXn[2], *TX2[2]; // impurity tensors
+  double *envA, *envB, *E;         // environments
+  double *P;
+  double *X, *XI, *Y;              // projection chunks
+  double *eigA, *eigV, *eigQ;
+  double *eig_scale;
+  int32_t *eig_flags;
+  int32_t *ints;                   // sector / pair / tile tables
+  int64_t ints_cap;
+  double *sel_lam;
+  int32_t *sel_int;                // cand sec, rank, col, taken + side picks
+  int32_t *pick;                   // pick sec, col, label
+  double *diag;                    // 24
+  double *partial;                 // norm partials
+  double *nrm;                     // 3 * (nsteps + 1)
+  double *coef;                    // t, F, FM, FM1
+  double *scal;                    // traces and result
+  int64_t eig_elems, eig_q;
+  int64_t sel_cap;
+};
+
+static size_t carve(const gxy_point &p, const Plan &pl, Carver &c, Buffers &b) {
+  const int64_t T = pl.maxT;
+  b.T = c.take<double>(T);
+  b.Tn = c.take<double>(T);
+  b.T2 = c.take<double>(T);
+  for (int k = 0; k < 2; ++k) {
+    const bool on = k < pl.nimp;
+    b.TX[k] = on ? c.take<double>(T) : nullptr;
+    b.TXn[k] = on ? c.take<double>(T) : nullptr;
+    b.TX2[k] = on ? c.take<double>(T) : nullptr;
+  }
+  b.envA = c.take<double>(T);
+  b.envB = c.take<double>(T);
+  const int64_t nf = pl.maxNF;
+  b.E = c.take<double>(2 * nf * nf);
+  b.P = c.take<double>(std::max<int64_t>(pl.maxPD, 1));
+  b.X = c.take<double>(pl.chunk_elems);
+  b.XI = pl.nimp > 0 ? c.take<double>(pl.chunk_elems) : nullptr;
+  b.Y = c.take<double>(pl.chunk_elems);
+  // eigen: per side sum of npad^2 <= nf^2 + 1023 nf
+  b.eig_elems = 2 * (nf * nf + 1023 * nf);
+  b.eigA = c.take<double>(std::max<int64_t>(b.eig_elems, 1));
+  b.eigV = c.take<double>(std::max<int64_t>(b.eig_elems, 1));
+  b.eig_q = 2 * nf * 1024 + 1024;
+  b.eigQ = c.take<double>(b.eig_q);
+  b.eig_scale = c.take<double>(2 * nf + 2);
+  b.eig_flags = c.take<int32_t>(4 * nf + 4);
+  // tables: sec idx (nf), start/n/label (3 nf), mats (2*2nf npad + 2*2nf off
+  // as 2 ints), pairbase (2nf+1), pair_mat (<= 2 nf), tiles (4 * bound)
+  const int64_t nmat = 2 * nf;
+  const int64_t pairs = 2 * nf;
+  // update tiles per matrix: q(q-1)/2 + q^2 with q = ceil(n/32); summed over
+  // both sides q^2 <= (n/32 + 1)^2 gives <= 1.5 (2 nf^2/1024 + nf/8 + 2 nf)
+  const int64_t tiles = (3 * (2 * nf * nf / 1024 + nf / 8 + 2 * nf)) / 2 + 16;
+  b.ints_cap = nf + 3 * nf + nmat + 2 * nmat + (nmat + 1) + pairs + 4 * tiles + 64;
+  b.ints = c.take<int32_t>(b.ints_cap);
+  b.sel_cap = 2 * nf;
+  b.sel_lam = c.take<double>(2 * nf + 2);
+  b.sel_int = c.take<int32_t>(4 * 2 * nf + 6 * (int64_t)std::max(pl.maxDn, 1) + 8);
+  b.pick = c.take<int32_t>(3 * (int64_t)std::max(pl.maxDn, 1) + 8);
+  b.diag = c.take<double>(32);
+  b.partial = c.take<double>(1024);
+  b.nrm = c.take<double>(3 * (int64_t)(p.nsteps + 1));
+  const int qmax = 4 * p.nmax;
+  b.coef = c.take<double>(pl.d0 + 3 * (2 * qmax + 1));
+  b.scal = c.take<double>(16);
+  return c.off + 256;
+}
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+
+struct RunLog {
+  std::vector<gxy_step_info> steps;
+};
+
+}  // namespace gxy
+
+struct gxy_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  bool ws_owned = false;
+  std::string last_error;
+  std::vector<gxy::RunLog> logs;
+  double phase_ms[6] = {0, 0, 0, 0, 0, 0};
+  // per-launch events around the dominant contraction (the D^7 product)
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, double>> hot_launches;  // (event pair index, flops)
+  double hot_stats[4] = {0, 0, 0, 0};  // launches, ms, flops, bytes
+  bool hot_on = false;
+  void *pinned = nullptr;  // small host staging buffer
+  size_t pinned_bytes = 0;
+};
+
+namespace gxy {
+
+static void ensure_pinned(gxy_ctx *ctx, size_t bytes) {
+  if (ctx->pinned_bytes >= bytes) return;
+  if (ctx->pinned) GXY_HIP(hipHostFree(ctx->pinned));
+  ctx->pinned = nullptr;
+  ctx->pinned_bytes = 0;
+  GXY_HIP(hipHostMalloc(&ctx->pinned, bytes, hipHostMallocDefault));
+  ctx->pinned_bytes = bytes;
+}
+
+static void ensure_workspace(gxy_ctx *ctx, size_t need) {
+  if (ctx->ws && ctx->ws_bytes >= need) return;
+  if (ctx->ws && !ctx->ws_owned)
+    fail(GXY_ENOMEM, "caller workspace of " + std::to_string(ctx->ws_bytes) +
+                         " bytes is smaller than the " + std::to_string(need) +
+                         " bytes needed");
+  if (ctx->ws) GXY_HIP(hipFree(ctx->ws));
+  ctx->ws = nullptr;
+  ctx->ws_bytes = 0;
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, need);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    fail(GXY_ENOMEM, "hipMalloc of " + std::to_string(need) + " bytes failed");
+  }
+  ctx->ws = p;
+  ctx->ws_bytes = need;
+  ctx->ws_owned = true;
+}
+
+// Events around each launch of the hot contraction (enabled by GXY_TIMING).
+static void hot_begin(gxy_ctx *ctx, hipStream_t s, double flops, double bytes) {
+  if (!ctx->hot_on) return;
+  const size_t k = ctx->hot_launches.size();
+  while (ctx->ev_pool.size() < 2 * (k + 1)) {
+    hipEvent_t e;
+    GXY_HIP(hipEventCreate(&e));
+    ctx->ev_pool.push_back(e);
+  }
+  GXY_HIP(hipEventRecord(ctx->ev_pool[2 * k], s));
+  ctx->hot_launches.push_back({(int)k, flops});
+  ctx->hot_stats[3] += bytes;
+}
+
+static void hot_end(gxy_ctx *ctx, hipStream_t s) {
+  if (!ctx->hot_on) return;
+  const size_t k = ctx->hot_launches.size() - 1;
+  GXY_HIP(hipEventRecord(ctx->ev_pool[2 * k + 1], s));
+}
+
+static void hot_collect(gxy_ctx *ctx) {
+  if (!ctx->hot_on) return;
+  for (auto &pr : ctx->hot_launches) {
+    float ms = 0;
+    GXY_HIP(hipEventSynchronize(ctx->ev_pool[2 * pr.first + 1]));
+    GXY_HIP(hipEventElapsedTime(&ms, ctx->ev_pool[2 * pr.first], ctx->ev_pool[2 * pr.first + 1]));
+    ctx->hot_stats[0] += 1;
+    ctx->hot_stats[1] += ms;
+    ctx->hot_stats[2] += pr.second;
+  }
+  ctx->hot_launches.clear();
+}
+
+static void validate(const gxy_point &p) {
+  if (!(p.beta >= 0.0) || !isfinite(p.beta)) fail(GXY_EINVAL, "beta must be finite and >= 0");
+  if (!(p.delta >= 0.0 && p.delta <= 1.0)) fail(GXY_EINVAL, "delta must lie in [0, 1]");
+  if (!isfinite(p.h) || !isfinite(p.h1)) fail(GXY_EINVAL, "fields must be finite");
+  if (p.nmax < 0 || p.nmax > 64) fail(GXY_EINVAL, "nmax must lie in [0, 64]");
+  if (p.dcut < 1 || p.dcut > 128) fail(GXY_EINVAL, "dcut must lie in [1, 128]");
+  if (p.nsteps < 0 || p.nsteps > 62) fail(GXY_EINVAL, "nsteps must lie in [0, 62]");
+  if (p.nquad <= 2 * p.nmax) fail(GXY_EINVAL, "nquad must exceed 2*nmax");
+  if (p.impurities & ~3u) fail(GXY_EINVAL, "unknown impurity bits");
+  if (p.prec != GXY_PREC_FP64) fail(GXY_EUNSUPPORTED, "only FP64 contractions in this build");
+}
+
+static int sym_of(const gxy_point &p) {
+  if (p.h == 0.0 && p.h1 == 0.0) return SYM_U1;
+  if (p.h == 0.0) return SYM_Z2;
+  return SYM_NONE;
+}
+
+static int fuse(int a, int b, int sym) {
+  if (sym == SYM_U1) return a + b;
+  if (sym == SYM_Z2) return (((a + b) % 2) + 2) % 2;
+  return 0;
+}
+
+struct Timer {
+  bool on = false;
+  hipStream_t s = nullptr;
+  double *acc = nullptr;
+  hipEvent_t a{}, b{};
+  void begin() {
+    if (on) GXY_HIP(hipEventRecord(a, s));
+  }
+  void end(int phase) {
+    if (!on) return;
+    GXY_HIP(hipEventRecord(b, s));
+    GXY_HIP(hipEventSynchronize(b));
+    float ms = 0;
+    GXY_HIP(hipEventElapsedTime(&ms, a, b));
+    acc[phase] += ms;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// GEMM helpers for the contractions of one y-step
+// ---------------------------------------------------------------------------
+
+// A_env[(l1,i),(l1',i')] = sum_{r1,u} T[l1,r1,u,i] T[l1',r1,u,i']   (left)
+// B_env[(l2,i),(l2',i')] = sum_{r2,d} T[l2,r2,i,d] T[l2',r2,i',d]   (left)
+// right side: r and l exchanged.
+static void env_gemms(const double *T, int Dh, int Dv, double *envA, double *envB,
+                      double *E, bool right, hipStream_t s) {
+  const int64_t sl = (int64_t)Dh * Dv * Dv, sr = (int64_t)Dv * Dv;
+  const int32_t MN = Dh * Dv;
+  GemmDesc g{};
+  // Gram over (outer leg, u) for the top tensor: rows (x, i), x = l1 or r1
+  g.M = MN;
+  g.N = MN;
+  g.K = MN;
+  g.A = T;
+  g.B = T;
+  g.C = envA;
+  g.alpha = 1.0;
+  g.beta = 0.0;
+  if (!right) {
+    g.am = imap2(Dv, sl, 1);       // (l1, i)
+    g.ak = imap2(Dv, sr, Dv);      // (r1, u)
+  } else {
+    g.am = imap2(Dv, sr, 1);       // (r1, i)
+    g.ak = imap2(Dv, sl, Dv);      // (l1, u)
+  }
+  g.bk = g.ak;
+  g.bn = g.am;
+  g.cm = imap1(MN);
+  g.cn = imap1(1);
+  g.kfast_a = false;
+  g.nfast_b = true;
+  gemm_f64(g, s);
+  // bottom tensor: rows (x, i), reduction (other leg, d)
+  if (!right) {
+    g.am = imap2(Dv, sl, Dv);      // (l2, i)
+    g.ak = imap2(Dv, sr, 1);       // (r2, d)
+  } else {
+    g.am = imap2(Dv, sr, Dv);      // (r2, i)
+    g.ak = imap2(Dv, sl, 1);       // (l2, d)
+  }
+  g.bk = g.ak;
+  g.bn = g.am;
+  g.C = envB;
+  g.kfast_a = true;
+  g.nfast_b = false;
+  gemm_f64(g, s);
+  // E[(x1,x2),(x1',x2')] = sum_{i,i'} envA[x1,i,x1',i'] envB[x2,i,x2',i']
+  GemmDesc e{};
+  e.M = Dh * Dh;
+  e.N = Dh * Dh;
+  e.K = Dv * Dv;
+  e.A = envA;
+  e.B = envB;
+  e.C = E;
+  e.alpha = 1.0;
+  e.beta = 0.0;
+  const int64_t row = (int64_t)Dv * Dh * Dv;
+  e.am = imap2(Dh, row, Dv);                    // (x1, x1')
+  e.ak = imap2(Dv, (int64_t)Dh * Dv, 1);        // (i, i')
+  e.bk = e.ak;
+  e.bn = imap2(Dh, row, Dv);                    // (x2, x2')
+  const int64_t nf = (int64_t)Dh * Dh;
+  e.cm = imap2(Dh, nf * Dh, Dh);                // row (x1,x2), col (x1',x2')
+  e.cn = imap2(Dh, nf, 1);
+  e.kfast_a = true;
+  e.nfast_b = false;
+  gemm_f64(e, s);
+}
+
+// X[a][r1][u][l2][i] = sum_{l1} P[(l1,l2), a0 + a] A[l1][r1][u][i], a < ac
+static void proj_x(const double *P, int Dh, int Dv, int Dn, int a0, int ac,
+                   const double *A, double *X, hipStream_t s) {
+  GemmDesc g{};
+  g.M = ac * Dh;
+  g.N = Dh * Dv * Dv;
+  g.K = Dh;
+  g.A = P + a0;
+  g.am = imap2(Dh, 1, Dn);                        // (a, l2)
+  g.ak = imap1((int64_t)Dh * Dn);                 // l1
+  g.B = A;
+  g.bk = imap1((int64_t)Dh * Dv * Dv);
+  g.bn = imap1(1);                                // (r1, u, i)
+  g.C = X;
+  const int64_t per_a = (int64_t)Dh * Dv * Dh * Dv;
+  g.cm = imap2(Dh, per_a, Dv);                    // (a, l2)
+  g.cn = imap3(Dv, Dv, (int64_t)Dv * Dh * Dv, (int64_t)Dh * Dv, 1);  // (r1, u, i)
+  g.alpha = 1.0;
+  g.beta = 0.0;
+  g.kfast_a = false;
+  g.nfast_b = true;
+  gemm_f64(g, s);
+}
+
+// Y[(a,r1,u),(r2,d)] = sum_{(l2,i)} X[(a,r1,u),(l2,i)] B2[(l2,i),(r2,d)]
+static void proj_y(const double *X, const double *B2, int Dh, int Dv, int ac,
+                   double *Y, hipStream_t s) {
+  GemmDesc g{};
+  const int32_t W = Dh * Dv;
+  g.M = ac * W;
+  g.N = W;
+  g.K = W;
+  g.A = X;
+  g.am = imap1(W);
+  g.ak = imap1(1);
+  g.B = B2;
+  g.bk = imap1(W);
+  g.bn = imap1(1);
+  g.C = Y;
+  g.cm = imap1(W);
+  g.cn = imap1(1);
+  g.alpha = 1.0;
+  g.beta = 0.0;
+  g.kfast_a = true;
+  g.nfast_b = true;
+  gemm_f64(g, s);
+}
+
+// T'[a0+a][b][u][d] = alpha sum_{r1,r2} Y[a][r1][u][r2][d] P[(r1,r2), b] + beta T'
+static void proj_t(const double *Y, const double *P, int Dh, int Dv, int Dn, int a0,
+                   int ac, double alpha, double beta, double *Tout, hipStream_t s) {
+  GemmDesc g{};
+  g.M = ac * Dv * Dv;
+  g.N = Dn;
+  g.K = Dh * Dh;
+  g.A = Y;
+  const int64_t per_a = (int64_t)Dh * Dv * Dh * Dv;
+  g.am = imap3(Dv, Dv, per_a, (int64_t)Dh * Dv, 1);          // (a, u, d)
+  g.ak = imap2(Dh, (int64_t)Dv * Dh * Dv, Dv);               // (r1, r2)
+  g.B = P;
+  g.bk = imap1(Dn);
+  g.bn = imap1(1);
+  g.C = Tout + (int64_t)a0 * Dn * Dv * Dv;
+  g.cm = imap3(Dv, Dv, (int64_t)Dn * Dv * Dv, Dv, 1);        // (a, u, d)
+  g.cn = imap1((int64_t)Dv * Dv);                            // b
+  g.alpha = alpha;
+  g.beta = beta;
+  g.kfast_a = false;
+  g.nfast_b = true;
+  gemm_f64(g, s);
+}
+
+// ---------------------------------------------------------------------------
+// one run
+// ---------------------------------------------------------------------------
+
+struct Sectors {
+  std::vector<int32_t> label, start, n, idx;
+};
+
+static Sectors make_sectors(const std::vector<int> &lh, int sym) {
+  const int Dh = (int)lh.size();
+  std::map<int, std::vector<int32_t>> by;
+  for (int a = 0; a < Dh; ++a)
+    for (int b = 0; b < Dh; ++b) by[fuse(lh[a], lh[b], sym)].push_back(a * Dh + b);
+  Sectors s;
+  for (auto &kv : by) {
+    s.label.push_back(kv.first);
+    s.start.push_back((int32_t)s.idx.size());
+    s.n.push_back((int32_t)kv.second.size());
+    s.idx.insert(s.idx.end(), kv.second.begin(), kv.second.end());
+  }
+  return s;
+}
+
+struct EigMem {
+  double *A, *V, *Q, *scale;
+  int32_t *flags, *ints;
+  int64_t ints_cap, eig_elems, eig_q;
+};
+
+struct SectorSolve {
+  EigBatch eb;
+  const int32_t *d_idx, *d_start, *d_n, *d_lab;
+  int sweeps;
+};
+
+// Eigendecomposition of every label sector of E_L (E) and E_R (E + nf*nf) by
+// batched block Jacobi. hp: pinned host scratch (>= 2 * nsec ints).
+static SectorSolve solve_sectors(hipStream_t s, const double *E, int nf, const Sectors &sec,
+                                 const EigMem &m, int32_t *hp) {
+  const int nsec = (int)sec.label.size();
+  const int nmat = 2 * nsec;
+  std::vector<int32_t> npad(nmat), pairbase(nmat + 1), pair_mat, tiles;
+  std::vector<int64_t> off(nmat);
+  int64_t tot = 0;
+  int max_nb = 2;
+  for (int k = 0; k < nmat; ++k) {
+    const int nn = sec.n[k % nsec];
+    npad[k] = ((nn + 31) / 32) * 32;
+    off[k] = tot;
+    tot += (int64_t)npad[k] * npad[k];
+    const int nb = npad[k] / 16;
+    max_nb = std::max(max_nb, nb);
+    pairbase[k] = (int32_t)pair_mat.size();
+    for (int q = 0; q < nb / 2; ++q) pair_mat.push_back(k);
+  }
+  pairbase[nmat] = (int32_t)pair_mat.size();
+  if (tot > m.eig_elems) fail(GXY_ENOMEM, "eigen workspace bound exceeded");
+  if ((int64_t)pair_mat.size() * 1024 > m.eig_q) fail(GXY_ENOMEM, "rotation buffer bound exceeded");
+  for (int k = 0; k < nmat; ++k) {
+    const int np2 = npad[k] / 32;  // pairs per matrix = row blocks of 32
+    for (int x = 0; x < np2; ++x)
+      for (int y = x + 1; y < np2; ++y) tiles.insert(tiles.end(), {k, 0, x, y});
+    for (int x = 0; x < np2; ++x)
+      for (int y = 0; y < np2; ++y) tiles.insert(tiles.end(), {k, 1, x, y});
+  }
+  // pack: idx | start | n | label | npad | off (2 ints each) | pairbase | pair_mat | tiles
+  std::vector<int32_t> pack;
+  pack.reserve(sec.idx.size() + 3 * nsec + nmat * 3 + pairbase.size() + pair_mat.size() +
+               tiles.size() + 2);
+  auto put = [&](const std::vector<int32_t> &v) {
+    const size_t at = pack.size();
+    pack.insert(pack.end(), v.begin(), v.end());
+    return at;
+  };
+  const size_t o_idx = put(sec.idx), o_start = put(sec.start), o_n = put(sec.n),
+               o_lab = put(sec.label), o_npad = put(npad);
+  while (pack.size() % 2) pack.push_back(0);
+  const size_t o_off = pack.size();
+  pack.resize(pack.size() + 2 * nmat);
+  memcpy(pack.data() + o_off, off.data(), sizeof(int64_t) * nmat);
+  const size_t o_pb = put(pairbase), o_pm = put(pair_mat), o_tl = put(tiles);
+  if ((int64_t)pack.size() > m.ints_cap) fail(GXY_ENOMEM, "table workspace bound exceeded");
+  GXY_HIP(hipMemcpyAsync(m.ints, pack.data(), pack.size() * sizeof(int32_t),
+                         hipMemcpyHostToDevice, s));
+  SectorSolve r{};
+  r.d_idx = m.ints + o_idx;
+  r.d_start = m.ints + o_start;
+  r.d_n = m.ints + o_n;
+  r.d_lab = m.ints + o_lab;
+  EigBatch &eb = r.eb;
+  eb.nmat = nmat;
+  eb.d_npad = m.ints + o_npad;
+  eb.d_off = reinterpret_cast<int64_t *>(m.ints + o_off);
+  eb.d_pairbase = m.ints + o_pb;
+  eb.d_pair_mat = m.ints + o_pm;
+  eb.total_pairs = (int32_t)pair_mat.size();
+  eb.max_nb = max_nb;
+  eb.A = m.A;
+  eb.V = m.V;
+  eb.Q = m.Q;
+  eb.d_flags = m.flags;
+  eb.d_scale = m.scale;
+  eb.d_rtl = m.ints + o_tl;
+  eb.n_update_tiles = (int32_t)(tiles.size() / 4);
+  launch_eig_gather(E, nf, r.d_idx, r.d_start, r.d_n, nsec, eb, s);
+  launch_eig_scale(eb, s);
+  launch_fill_i32(eb.d_flags + nmat, nmat, 0, s);
+  bool converged = false;
+  for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
+    for (int rr = 0; rr < max_nb - 1; ++rr) launch_eig_round(eb, rr, s);
+    // flags <- next flags, next <- 0, and read them back
+    GXY_HIP(hipMemcpyAsync(eb.d_flags, eb.d_flags + nmat, nmat * sizeof(int32_t),
+                           hipMemcpyDeviceToDevice, s));
+    launch_fill_i32(eb.d_flags + nmat, nmat, 0, s);
+    GXY_HIP(hipMemcpyAsync(hp, eb.d_flags, nmat * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    GXY_HIP(hipStreamSynchronize(s));
+    bool any = false;
+    for (int k = 0; k < nmat; ++k) any |= hp[k] != 0;
+    r.sweeps = sweep + 1;
+    if (!any) {
+      converged = true;
+      break;
+    }
+  }
+  if (!converged) fail(GXY_ENUMERIC, "block-Jacobi eigensolver did not converge");
+  return r;
+}
+
+static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &log) {
+  validate(p);
+  const hipStream_t s = ctx->stream;
+  const size_t chunk_bytes = env_size("GXY_CHUNK_BYTES", (size_t)16 << 30);
+  const Plan pl = make_plan(p, chunk_bytes);
+  Buffers b{};
+  {
+    Carver c0;
+    const size_t need = carve(p, pl, c0, b);
+    ensure_workspace(ctx, need);
+    Carver c;
+    c.base = (char *)ctx->ws;
+    carve(p, pl, c, b);
+  }
+  ensure_pinned(ctx, 1 << 20);
+  Timer tm;
+  tm.on = env_flag("GXY_TIMING");
+  ctx->hot_on = tm.on || env_flag("GXY_HOT_EVENTS");
+  ctx->hot_launches.clear();
+  tm.s = s;
+  tm.acc = ctx->phase_ms;
+  for (double &v : ctx->phase_ms) v = 0.0;
+  if (tm.on) {
+    GXY_HIP(hipEventCreate(&tm.a));
+    GXY_HIP(hipEventCreate(&tm.b));
+  }
+  struct EvGuard {
+    Timer &t;
+    ~EvGuard() {
+      if (t.on) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+      }
+    }
+  } evg{tm};
+
+  const int sym = sym_of(p);
+  const int nmax = p.nmax;
+  const int D0 = pl.d0;
+  const int qmax = 4 * nmax;
+  double *t = b.coef;
+  double *F = t + D0;
+  double *FM = F + (2 * qmax + 1);
+  double *FM1 = FM + (2 * qmax + 1);
+
+  tm.begin();
+  launch_char_coeffs(p.beta, p.delta, nmax, p.nquad, t, s);
+  launch_field_factors(p.beta, p.h, p.h1, qmax, kLmax, sym == SYM_U1, F, FM, FM1, s);
+  launch_init_tensor(t, F, nmax, b.T, s);
+  int imp_which[2] = {0, 0};
+  {
+    int k = 0;
+    if (p.impurities & GXY_IMP_COS1) {
+      launch_init_tensor(t, FM, nmax, b.TX[k], s);
+      imp_which[k++] = 1;
+    }
+    if (p.impurities & GXY_IMP_COS2) {
+      launch_init_tensor(t, FM1, nmax, b.TX[k], s);
+      imp_which[k++] = 2;
+    }
+  }
+  const int nimp = pl.nimp;
+  int Dh = D0, Dv = D0;
+  int64_t nT = (int64_t)Dh * Dh * Dv * Dv;
+  launch_fro_norm(b.T, nT, b.partial, b.nrm, s);
+  launch_scale(b.T, nT, b.nrm + 2, s);
+  for (int k = 0; k < nimp; ++k) launch_scale(b.TX[k], nT, b.nrm + 2, s);
+  tm.end(0);
+
+  std::vector<int> lh(D0), lv(D0);
+  for (int i = 0; i < D0; ++i) {
+    const int q = i - nmax;
+    lh[i] = lv[i] = (sym == SYM_U1) ? q : (sym == SYM_Z2 ? (((q % 2) + 2) % 2) : 0);
+  }
+  log.steps.clear();
+  res.near_ties = 0;
+  res.max_trunc_err = 0.0;
+  res.min_cut_gap = INFINITY;
+
+  int32_t *hp = (int32_t *)ctx->pinned;
+  for (int n = 1; n <= p.nsteps; ++n) {
+    const StepDims &sd = pl.steps[n - 1];
+    if (sd.xstep) {
+      // T[l][r][u][d] -> T[u][d][l][r]
+      tm.begin();
+      launch_swap_pairs(b.T, b.Tn, Dh, Dh, Dv, Dv, s);
+      std::swap(b.T, b.Tn);
+      for (int k = 0; k < nimp; ++k) {
+        launch_swap_pairs(b.TX[k], b.TXn[k], Dh, Dh, Dv, Dv, s);
+        std::swap(b.TX[k], b.TXn[k]);
+      }
+      std::swap(Dh, Dv);
+      std::swap(lh, lv);
+      tm.end(5);
+    }
+    const int64_t nf = (int64_t)Dh * Dh;
+    const int Dn = sd.dn;
+    gxy_step_info info{};
+    std::vector<int> new_lh;
+    if (nf <= p.dcut) {
+      launch_identity(b.P, (int)nf, s);
+      new_lh.resize(nf);
+      for (int a = 0; a < Dh; ++a)
+        for (int c = 0; c < Dh; ++c) new_lh[a * Dh + c] = fuse(lh[a], lh[c], sym);
+      info.truncated = 0;
+    } else {
+      // ---- environments ----
+      tm.begin();
+      env_gemms(b.T, Dh, Dv, b.envA, b.envB, b.E, false, s);
+      env_gemms(b.T, Dh, Dv, b.envA, b.envB, b.E + nf * nf, true, s);
+      tm.end(1);
+      // ---- sectors and eigensolver tables ----
+      tm.begin();
+      const Sectors sec = make_sectors(lh, sym);
+      const int nsec = (int)sec.label.size();
+      EigMem em{b.eigA, b.eigV, b.eigQ, b.eig_scale, b.eig_flags, b.ints, b.ints_cap,
+                b.eig_elems, b.eig_q};
+      const SectorSolve sv = solve_sectors(s, b.E, (int)nf, sec, em, hp);
+      const EigBatch &eb = sv.eb;
+      const int32_t *d_idx = sv.d_idx, *d_start = sv.d_start, *d_n = sv.d_n,
+                    *d_lab = sv.d_lab;
+      tm.end(2);
+      // ---- truncation ----
+      tm.begin();
+      SelectArgs sa{};
+      sa.nsec = nsec;
+      sa.d_sec_label = d_lab;
+      sa.d_sec_n = d_n;
+      sa.d_mat_off = eb.d_off;
+      sa.d_mat_npad = eb.d_npad;
+      sa.A = b.eigA;
+      sa.dcut = Dn;
+      sa.ncand = (int32_t)nf;
+      sa.tie_rel = kTieRel;
+      sa.side_tol = kSideTol;
+      sa.d_lam = b.sel_lam;
+      sa.d_cand_sec = b.sel_int;
+      sa.d_cand_rank = b.sel_int + 2 * nf;
+      sa.d_cand_col = b.sel_int + 4 * nf;
+      sa.d_taken = b.sel_int + 6 * nf;
+      sa.d_pick_sec = b.pick;
+      sa.d_pick_col = b.pick + Dn;
+      sa.d_pick_label = b.pick + 2 * Dn;
+      sa.d_diag = b.diag;
+      launch_select(sa, s);
+      launch_build_projector(b.eigV, eb.d_off, eb.d_npad, d_idx, d_start, d_n, b.pick,
+                             b.pick + Dn, b.diag, nsec, (int)nf, Dn, b.P, s);
+      GXY_HIP(hipMemcpyAsync(hp, b.pick + 2 * Dn, Dn * sizeof(int32_t),
+                             hipMemcpyDeviceToHost, s));
+      double *hd = reinterpret_cast<double *>(hp + 512);
+      GXY_HIP(hipMemcpyAsync(hd, b.diag, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+      GXY_HIP(hipStreamSynchronize(s));
+      new_lh.assign(hp, hp + Dn);
+      info.eps_l = hd[0];
+      info.eps_r = hd[1];
+      info.side = (int)hd[2];
+      info.lam_max = hd[3];
+      info.cut_gap = hd[4];
+      info.ties = (int)hd[5];
+      info.truncated = 1;
+      const double trE = hd[6];
+      const double eps = info.side ? info.eps_r : info.eps_l;
+      if (trE > 0) res.max_trunc_err = std::max(res.max_trunc_err, eps / trE);
+      res.min_cut_gap = std::min(res.min_cut_gap, info.cut_gap);
+      res.near_ties += info.ties;
+      tm.end(3);
+    }
+    // ---- projection T' = P^T M P (and impurities), chunked over a ----
+    tm.begin();
+    launch_swap_middle(b.T, b.T2, Dh, Dh, Dv, Dv, s);
+    for (int k = 0; k < nimp; ++k) launch_swap_middle(b.TX[k], b.TX2[k], Dh, Dh, Dv, Dv, s);
+    const int64_t per_a = (int64_t)Dh * Dv * Dh * Dv;
+    const int ac_max = (int)std::max<int64_t>(1, std::min<int64_t>(Dn, pl.chunk_elems / per_a));
+    const double W = (double)Dh * Dv;
+    auto hot_y = [&](const double *Xp, const double *Bp, int ac) {
+      // algorithmic work of the dense product: 2 M N K flops, A + B + C bytes
+      const double M = (double)ac * W;
+      hot_begin(ctx, s, 2.0 * M * W * W, 8.0 * (M * W + W * W + M * W));
+      proj_y(Xp, Bp, Dh, Dv, ac, b.Y, s);
+      hot_end(ctx, s);
+    };
+    for (int a0 = 0; a0 < Dn; a0 += ac_max) {
+      const int ac = std::min(ac_max, Dn - a0);
+      proj_x(b.P, Dh, Dv, Dn, a0, ac, b.T, b.X, s);
+      hot_y(b.X, b.T2, ac);
+      proj_t(b.Y, b.P, Dh, Dv, Dn, a0, ac, 1.0, 0.0, b.Tn, s);
+      for (int k = 0; k < nimp; ++k) {
+        hot_y(b.X, b.TX2[k], ac);
+        proj_t(b.Y, b.P, Dh, Dv, Dn, a0, ac, 0.5, 0.0, b.TXn[k], s);
+        proj_x(b.P, Dh, Dv, Dn, a0, ac, b.TX[k], b.XI, s);
+        hot_y(b.XI, b.T2, ac);
+        proj_t(b.Y, b.P, Dh, Dv, Dn, a0, ac, 0.5, 1.0, b.TXn[k], s);
+      }
+    }
+    tm.end(4);
+    tm.begin();
+    Dh = Dn;
+    nT = (int64_t)Dh * Dh * Dv * Dv;
+    launch_fro_norm(b.Tn, nT, b.partial, b.nrm + 3 * n, s);
+    launch_scale(b.Tn, nT, b.nrm + 3 * n + 2, s);
+    std::swap(b.T, b.Tn);
+    for (int k = 0; k < nimp; ++k) {
+      launch_scale(b.TXn[k], nT, b.nrm + 3 * n + 2, s);
+      std::swap(b.TX[k], b.TXn[k]);
+    }
+    lh = new_lh;
+    if (sd.xstep) {
+      launch_swap_pairs(b.T, b.Tn, Dh, Dh, Dv, Dv, s);
+      std::swap(b.T, b.Tn);
+      for (int k = 0; k < nimp; ++k) {
+        launch_swap_pairs(b.TX[k], b.TXn[k], Dh, Dh, Dv, Dv, s);
+        std::swap(b.TX[k], b.TXn[k]);
+      }
+      std::swap(Dh, Dv);
+      std::swap(lh, lv);
+    }
+    tm.end(5);
+    info.dh = Dh;
+    info.dv = Dv;
+    log.steps.push_back(info);
+  }
+  // ---- trace and result ----
+  double *tr = b.scal, *tr1 = b.scal + 1, *tr2 = b.scal + 2, *rr = b.scal + 4;
+  launch_trace(b.T, Dh, Dv, tr, s);
+  const double *trk[2] = {nullptr, nullptr};
+  for (int k = 0; k < nimp; ++k) {
+    launch_trace(b.TX[k], Dh, Dv, tr1 + k, s);
+    trk[imp_which[k] - 1] = tr1 + k;
+  }
+  // lnc[n] lives at nrm[3n + 1]; gather them contiguously into the partial buffer
+  GXY_HIP(hipMemcpy2DAsync(b.partial, sizeof(double), b.nrm + 1, 3 * sizeof(double),
+                           sizeof(double), p.nsteps + 1, hipMemcpyDeviceToDevice, s));
+  launch_finish(b.partial, p.nsteps, tr, trk[0], trk[1], rr, s);
+  double *hd = reinterpret_cast<double *>(hp);
+  GXY_HIP(hipMemcpyAsync(hd, rr, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+  GXY_HIP(hipMemcpyAsync(hd + 8, b.partial, (p.nsteps + 1) * sizeof(double),
+                         hipMemcpyDeviceToHost, s));
+  GXY_HIP(hipStreamSynchronize(s));
+  hot_collect(ctx);
+  res.lnz_per_site = hd[0];
+  res.m_cos1 = hd[1];
+  res.m_cos2 = hd[2];
+  res.status = (int32_t)hd[3];
+  res.fail_step = res.status ? p.nsteps : -1;
+  res.nsteps_done = p.nsteps;
+  if (!isfinite(res.min_cut_gap)) res.min_cut_gap = 0.0;
+  for (int n = 1; n <= p.nsteps; ++n) log.steps[n - 1].lnc = hd[8 + n];
+  (void)tr2;
+}
+
+static void initial_tensor_only(gxy_ctx *ctx, const gxy_point &p, int which, double *out) {
+  validate(p);
+  const hipStream_t s = ctx->stream;
+  const int D0 = 2 * p.nmax + 1, qmax = 4 * p.nmax;
+  const int64_t n4 = (int64_t)D0 * D0 * D0 * D0;
+  const size_t need = sizeof(double) * (n4 + D0 + 3 * (2 * qmax + 1)) + 4096;
+  ensure_workspace(ctx, need);
+  double *T = (double *)ctx->ws;
+  double *t = T + n4;
+  double *F = t + D0, *FM = F + (2 * qmax + 1), *FM1 = FM + (2 * qmax + 1);
+  launch_char_coeffs(p.beta, p.delta, p.nmax, p.nquad, t, s);
+  launch_field_factors(p.beta, p.h, p.h1, qmax, kLmax, sym_of(p) == SYM_U1, F, FM, FM1, s);
+  launch_init_tensor(t, which == 0 ? F : (which == 1 ? FM : FM1), p.nmax, T, s);
+  GXY_HIP(hipMemcpyAsync(out, T, n4 * sizeof(double), hipMemcpyDeviceToHost, s));
+  GXY_HIP(hipStreamSynchronize(s));
+}
+
+static size_t workspace_for(const gxy_point &p) {
+  validate(p);
+  const Plan pl = make_plan(p, env_size("GXY_CHUNK_BYTES", (size_t)16 << 30));
+  Buffers b{};
+  Carver c;
+  return carve(p, pl, c, b);
+}
+
+}  // namespace gxy
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+using gxy::Error;
+
+#define GXY_API_BEGIN try {
+#define GXY_API_END(ctx)                                         \
+  }                                                              \
+  catch (const Error &e) {                                       \
+    if (ctx) (ctx)->last_error = e.msg;                          \
+    if (getenv("GXY_LOG")) fprintf(stderr, "gxy: %s\n", e.msg.c_str()); \
+    return e.status;                                             \
+  }                                                              \
+  catch (const std::bad_alloc &) {                               \
+    if (ctx) (ctx)->last_error = "host allocation failed";       \
+    return GXY_ENOMEM;                                           \
+  }                                                              \
+  catch (...) {                                                  \
+    if (ctx) (ctx)->last_error = "unexpected host exception";    \
+    return GXY_EDEVICE;                                          \
+  }
+
+extern "C" {
+
+gxy_status gxy_create(gxy_ctx **out, int device, void *hip_stream) {
+  if (!out) return GXY_EINVAL;
+  *out = nullptr;
+  gxy_ctx *ctx = nullptr;
+  GXY_API_BEGIN
+  int n = 0;
+  GXY_HIP(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return GXY_EINVAL;
+  GXY_HIP(hipSetDevice(device));
+  ctx = new gxy_ctx();
+  ctx->device = device;
+  ctx->stream = (hipStream_t)hip_stream;
+  *out = ctx;
+  return GXY_OK;
+  GXY_API_END(ctx)
+}
+
+gxy_status gxy_destroy(gxy_ctx *ctx) {
+  if (!ctx) return GXY_EINVAL;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->ws && ctx->ws_owned) (void)hipFree(ctx->ws);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  delete ctx;
+  return GXY_OK;
+}
+
+gxy_status gxy_workspace_bytes(gxy_ctx *ctx, const gxy_point *pts, int32_t n, size_t *bytes) {
+  if (!ctx || !pts || n <= 0 || !bytes) return GXY_EINVAL;
+  GXY_API_BEGIN
+  size_t m = 0;
+  for (int i = 0; i < n; ++i) m = std::max(m, gxy::workspace_for(pts[i]));
+  *bytes = m;
+  return GXY_OK;
+  GXY_API_END(ctx)
+}
+
+gxy_status gxy_set_workspace(gxy_ctx *ctx, void *dev_ptr, size_t bytes) {
+  if (!ctx) return GXY_EINVAL;
+  if (dev_ptr && bytes == 0) return GXY_EINVAL;
+  GXY_API_BEGIN
+  GXY_HIP(hipSetDevice(ctx->device));
+  if (ctx->ws && ctx->ws_owned) GXY_HIP(hipFree(ctx->ws));
+  ctx->ws = dev_ptr;
+  ctx->ws_bytes = dev_ptr ? bytes : 0;
+  ctx->ws_owned = false;
+  return GXY_OK;
+  GXY_API_END(ctx)
+}
+
+gxy_status gxy_char_coeffs(gxy_ctx *ctx, double beta, double delta, int32_t nmax,
+                           int32_t nquad, double *t) {
+  if (!ctx || !t || nmax < 0 || nmax > 64 || nquad <= 2 * nmax || !(beta >= 0.0) ||
+      !(delta >= 0.0 && delta <= 1.0))
+    return GXY_EINVAL;
+  GXY_API_BEGIN
+  GXY_HIP(hipSetDevice(ctx->device));
+  gxy::ensure_workspace(ctx, sizeof(double) * (2 * nmax + 1) + 256);
+  double *d = (double *)ctx->ws;
+  gxy::launch_char_coeffs(beta, delta, nmax, nquad, d, ctx->stream);
+  GXY_HIP(hipMemcpyAsync(t, d, sizeof(double) * (2 * nmax + 1), hipMemcpyDeviceToHost,
+                         ctx->stream));
+  GXY_HIP(hipStreamSynchronize(ctx->stream));
+  return GXY_OK;
+  GXY_API_END(ctx)
+}
+
+gxy_status gxy_initial_tensor(gxy_ctx *ctx, const gxy_point *pt, int32_t which, double *out) {
+  if (!ctx || !pt || !out || which < 0 || which > 2) return GXY_EINVAL;
+  GXY_API_BEGIN
+  GXY_HIP(hipSetDevice(ctx->device));
+  gxy::initial_tensor_only(ctx, *pt, which, out);
+  return GXY_OK;
+  GXY_API_END(ctx)
+}
+
+gxy_status gxy_run(gxy_ctx *ctx, const gxy_point *pt, gxy_result *out) {
+  if (!ctx || !pt || !out) return GXY_EINVAL;
+  GXY_API_BEGIN
+  GXY_HIP(hipSetDevice(ctx->device));
+  ctx->logs.assign(1, gxy::RunLog{});
+  gxy_result r{};
+  r.status = GXY_OK;
+  r.fail_step = -1;
+  gxy::run_one(ctx, *pt, r, ctx->logs[0]);
+  *out = r;
+  return (gxy_status)r.status;
+  GXY_API_END(ctx)
+}
+
+gxy_status gxy_run_batch(gxy_ctx *ctx, const gxy_point *pts, int32_t n, gxy_result *out) {
+  if (!ctx || !pts || !out || n <= 0) return GXY_EINVAL;
+  bool any_fail = false;
+  try {
+    GXY_HIP(hipSetDevice(ctx->device));
+  } catch (const Error &e) {
+    ctx->last_error = e.msg;
+    return e.status;
+  }
+  ctx->logs.assign(n, gxy::RunLog{});
+  for (int i = 0; i < n; ++i) {
+    gxy_result r{};
+    r.fail_step = -1;
+    try {
+      gxy::run_one(ctx, pts[i], r, ctx->logs[i]);
+    } catch (const Error &e) {
+      ctx->last_error = e.msg;
+      r.status = e.status;
+      r.lnz_per_site = r.m_cos1 = r.m_cos2 = NAN;
+      if (e.status == GXY_EDEVICE) {
+        out[i] = r;
+        for (int j = i + 1; j < n; ++j) {
+          out[j] = r;
+        }
+        return GXY_EDEVICE;
+      }
+    }
+    out[i] = r;
+    any_fail |= r.status != GXY_OK;
+  }
+  return any_fail ? GXY_EPARTIAL : GXY_OK;
+}
+
+gxy_status gxy_step_log(gxy_ctx *ctx, int32_t run, gxy_step_info *out, int32_t cap,
+                        int32_t *count) {
+  if (!ctx || !count || run < 0 || run >= (int32_t)ctx->logs.size() || cap < 0 ||
+      (cap > 0 && !out))
+    return GXY_EINVAL;
+  const auto &st = ctx->logs[run].steps;
+  const int32_t m = std::min<int32_t>(cap, (int32_t)st.size());
+  for (int i = 0; i < m; ++i) out[i] = st[i];
+  *count = (int32_t)st.size();
+  return GXY_OK;
+}
+
+gxy_status gxy_observables(gxy_ctx *ctx, int32_t npts, const double *beta, const double *lnz,
+                           const double *m_h, const double *m_h1, double dbeta, double dh,
+                           double dh1, double *out) {
+  if (!ctx || npts <= 0 || !beta || !lnz || !m_h || !m_h1 || !out || !(dbeta > 0) ||
+      !(dh > 0) || !(dh1 > 0))
+    return GXY_EINVAL;
+  GXY_API_BEGIN
+  GXY_HIP(hipSetDevice(ctx->device));
+  const size_t n = (size_t)npts;
+  const size_t need = sizeof(double) * (n + 3 * n + 2 * n + 2 * n + 4 * n) + 1024;
+  gxy::ensure_workspace(ctx, need);
+  double *d = (double *)ctx->ws;
+  double *db = d, *dl = db + n, *dm = dl + 3 * n, *dm1 = dm + 2 * n, *dout = dm1 + 2 * n;
+  hipStream_t s = ctx->stream;
+  GXY_HIP(hipMemcpyAsync(db, beta, n * sizeof(double), hipMemcpyHostToDevice, s));
+  GXY_HIP(hipMemcpyAsync(dl, lnz, 3 * n * sizeof(double), hipMemcpyHostToDevice, s));
+  GXY_HIP(hipMemcpyAsync(dm, m_h, 2 * n * sizeof(double), hipMemcpyHostToDevice, s));
+  GXY_HIP(hipMemcpyAsync(dm1, m_h1, 2 * n * sizeof(double), hipMemcpyHostToDevice, s));
+  gxy::launch_observables(npts, db, dl, dm, dm1, dbeta, dh, dh1, dout, s);
+  GXY_HIP(hipMemcpyAsync(out, dout, 4 * n * sizeof(double), hipMemcpyDeviceToHost, s));
+  GXY_HIP(hipStreamSynchronize(s));
+  return GXY_OK;
+  GXY_API_END(ctx)
+}
+
+const char *gxy_status_string(gxy_status s) {
+  switch (s) {
+    case GXY_OK: return "ok";
+    case GXY_EINVAL: return "invalid argument";
+    case GXY_ENOMEM: return "out of device memory";
+    case GXY_EDEVICE: return "HIP runtime error";
+    case GXY_ENUMERIC: return "numerical failure";
+    case GXY_EUNSUPPORTED: return "unsupported request";
+    case GXY_EPARTIAL: return "some runs of the batch failed";
+  }
+  return "unknown status";
+}
+
+const char *gxy_last_error(gxy_ctx *ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+gxy_status gxy_hot_kernel_stats(gxy_ctx *ctx, double *out4, int32_t reset) {
+  if (!ctx || !out4) return GXY_EINVAL;
+  for (int i = 0; i < 4; ++i) out4[i] = ctx->hot_stats[i];
+  if (reset)
+    for (double &v : ctx->hot_stats) v = 0.0;
+  return GXY_OK;
+}
+
+gxy_status gxy_phase_times(gxy_ctx *ctx, double *ms6) {
+  if (!ctx || !ms6) return GXY_EINVAL;
+  for (int i = 0; i < 6; ++i) ms6[i] = ctx->phase_ms[i];
+  return GXY_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// unit-test entry points (include/gxy_hotrg_testing.h)
+// ===========================================================================
+
+extern "C" {
+
+gxy_status gxy_test_gemm_f64(gxy_ctx *ctx, int32_t M, int32_t N, int32_t K, const double *A,
+                             int32_t a_trans, const double *B, int32_t b_trans, double *Cout) {
+  if (!ctx || M <= 0 || N <= 0 || K < 0 || !A || !B || !Cout) return GXY_EINVAL;
+  GXY_API_BEGIN
+  GXY_HIP(hipSetDevice(ctx->device));
+  const size_t na = (size_t)M * K, nb = (size_t)K * N, nc = (size_t)M * N;
+  gxy::ensure_workspace(ctx, sizeof(double) * (na + nb + nc) + 1024);
+  double *dA = (double *)ctx->ws, *dB = dA + na, *dC = dB + nb;
+  hipStream_t s = ctx->stream;
+  GXY_HIP(hipMemcpyAsync(dA, A, na * sizeof(double), hipMemcpyHostToDevice, s));
+  GXY_HIP(hipMemcpyAsync(dB, B, nb * sizeof(double), hipMemcpyHostToDevice, s));
+  gxy::GemmDesc g{};
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.A = dA;
+  g.B = dB;
+  g.C = dC;
+  g.alpha = 1.0;
+  g.beta = 0.0;
+  g.am = a_trans ? gxy::imap1(1) : gxy::imap1(K);
+  g.ak = a_trans ? gxy::imap1(M) : gxy::imap1(1);
+  g.kfast_a = !a_trans;
+  g.bk = b_trans ? gxy::imap1(1) : gxy::imap1(N);
+  g.bn = b_trans ? gxy::imap1(K) : gxy::imap1(1);
+  g.nfast_b = !b_trans;
+  g.cm = gxy::imap1(N);
+  g.cn = gxy::imap1(1);
+  gxy::gemm_f64(g, s);
+  GXY_HIP(hipMemcpyAsync(Cout, dC, nc * sizeof(double), hipMemcpyDeviceToHost, s));
+  GXY_HIP(hipStreamSynchronize(s));
+  return GXY_OK;
+  GXY_API_END(ctx)
+}
+
+gxy_status gxy_test_eigh(gxy_ctx *ctx, int32_t n, const double *A, double *w, double *V,
+                         int32_t *sweeps) {
+  if (!ctx || n <= 0 || n > 8192 || !A || !w || !V) return GXY_EINVAL;
+  GXY_API_BEGIN
+  GXY_HIP(hipSetDevice(ctx->device));
+  using namespace gxy;
+  // one sector holding every index, on both "sides" (the second copy is unused)
+  Sectors sec;
+  sec.label = {0};
+  sec.start = {0};
+  sec.n = {n};
+  sec.idx.resize(n);
+  for (int i = 0; i < n; ++i) sec.idx[i] = i;
+  const int64_t np = ((n + 31) / 32) * 32;
+  const int64_t nn = (int64_t)n * n;
+  EigMem m{};
+  m.eig_elems = 2 * np * np;
+  m.eig_q = 2 * (np / 32) * 1024 + 1024;
+  const int64_t tiles = 2 * (3 * (np / 32) * (np / 32) / 2 + 4);
+  m.ints_cap = n + 8 + 12 + 4 + 2 * (np / 32) + 4 * tiles + 64;
+  Carver c;
+  for (int pass = 0; pass < 2; ++pass) {
+    double *E = c.take<double>(2 * nn);
+    m.A = c.take<double>(m.eig_elems);
+    m.V = c.take<double>(m.eig_elems);
+    m.Q = c.take<double>(m.eig_q);
+    m.scale = c.take<double>(8);
+    m.flags = c.take<int32_t>(16);
+    m.ints = c.take<int32_t>(m.ints_cap);
+    if (pass == 0) {
+      ensure_workspace(ctx, c.off + 256);
+      c = Carver{};
+      c.base = (char *)ctx->ws;
+      continue;
+    }
+    ensure_pinned(ctx, 1 << 20);
+    hipStream_t s = ctx->stream;
+    GXY_HIP(hipMemcpyAsync(E, A, nn * sizeof(double), hipMemcpyHostToDevice, s));
+    GXY_HIP(hipMemcpyAsync(E + nn, A, nn * sizeof(double), hipMemcpyHostToDevice, s));
+    const SectorSolve sv = solve_sectors(s, E, n, sec, m, (int32_t *)ctx->pinned);
+    if (sweeps) *sweeps = sv.sweeps;
+    // eigenvalues: diagonal of the converged matrix; vectors: first n rows/cols
+    GXY_HIP(hipMemcpy2DAsync(V, n * sizeof(double), m.V, np * sizeof(double),
+                             n * sizeof(double), n, hipMemcpyDeviceToHost, s));
+    GXY_HIP(hipMemcpy2DAsync(w, sizeof(double), m.A, (np + 1) * sizeof(double),
+                             sizeof(double), n, hipMemcpyDeviceToHost, s));
+    GXY_HIP(hipStreamSynchronize(s));
+  }
+  return GXY_OK;
+  GXY_API_END(ctx)
+}
+
+gxy_status gxy_test_mfma_layout(gxy_ctx *ctx, const double *a, const double *b, double *out) {
+  if (!ctx || !a || !b || !out) return GXY_EINVAL;
+  GXY_API_BEGIN
+  GXY_HIP(hipSetDevice(ctx->device));
+  gxy::ensure_workspace(ctx, sizeof(double) * 384 + 256);
+  double *da = (double *)ctx->ws, *db = da + 64, *dout = db + 64;
+  hipStream_t s = ctx->stream;
+  GXY_HIP(hipMemcpyAsync(da, a, 64 * sizeof(double), hipMemcpyHostToDevice, s));
+  GXY_HIP(hipMemcpyAsync(db, b, 64 * sizeof(double), hipMemcpyHostToDevice, s));
+  gxy::launch_mfma_probe(da, db, dout, s);
+  GXY_HIP(hipMemcpyAsync(out, dout, 256 * sizeof(double), hipMemcpyDeviceToHost, s));
+  GXY_HIP(hipStreamSynchronize(s));
+  return GXY_OK;
+  GXY_API_END(ctx)
+}
+
+}  // extern "C"

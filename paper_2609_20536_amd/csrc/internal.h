@@ -1,0 +1,199 @@
+// Internal declarations shared by the HIP sources of libgxyhotrg.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/gxy_hotrg.h"
+
+namespace gxy {
+
+// --------------------------------------------------------------------------
+// errors
+// --------------------------------------------------------------------------
+
+struct Error {
+  gxy_status status;
+  std::string msg;
+};
+
+#define GXY_HIP(call)                                                        \
+  do {                                                                       \
+    hipError_t e_ = (call);                                                  \
+    if (e_ != hipSuccess)                                                    \
+      throw ::gxy::Error{GXY_EDEVICE, std::string(#call) + ": " +            \
+                                          hipGetErrorString(e_)};            \
+  } while (0)
+
+#define GXY_CHECK_LAUNCH() GXY_HIP(hipGetLastError())
+
+[[noreturn]] inline void fail(gxy_status s, const std::string &m) {
+  throw Error{s, m};
+}
+
+// --------------------------------------------------------------------------
+// Mixed-radix index maps: a fused index x = ((d0 * e1 + d1) * e2 + d2) * e3 + d3
+// is sent to the element offset d0*s0 + d1*s1 + d2*s2 + d3*s3. Unused
+// trailing dimensions have extent 1 and stride 0.
+// --------------------------------------------------------------------------
+
+struct IdxMap {
+  int32_t e1, e2, e3;      // extents of dims 1..3 (dim 0 is implicit)
+  int32_t pad_;
+  int64_t s0, s1, s2, s3;  // strides in elements
+};
+
+inline IdxMap imap1(int64_t s0) { return IdxMap{1, 1, 1, 0, s0, 0, 0, 0}; }
+inline IdxMap imap2(int32_t e1, int64_t s0, int64_t s1) {
+  return IdxMap{e1, 1, 1, 0, s0, s1, 0, 0};
+}
+inline IdxMap imap3(int32_t e1, int32_t e2, int64_t s0, int64_t s1, int64_t s2) {
+  return IdxMap{e1, e2, 1, 0, s0, s1, s2, 0};
+}
+
+__host__ __device__ inline int64_t imap_off(const IdxMap &m, int32_t x) {
+  int32_t d3 = x % m.e3;
+  x /= m.e3;
+  int32_t d2 = x % m.e2;
+  x /= m.e2;
+  int32_t d1 = x % m.e1;
+  int32_t d0 = x / m.e1;
+  return d0 * m.s0 + d1 * m.s1 + d2 * m.s2 + d3 * m.s3;
+}
+
+// C(m, n) = alpha * sum_k A(m, k) B(k, n) + beta * C(m, n), FP64 MFMA.
+// Element (m, k) of A is A[imap_off(am, m) + imap_off(ak, k)], and so on.
+// kfast_a: neighbouring k of A are adjacent in memory (else neighbouring m);
+// nfast_b: neighbouring n of B are adjacent (else neighbouring k).
+struct GemmDesc {
+  int32_t M, N, K;
+  const double *A;
+  IdxMap am, ak;
+  const double *B;
+  IdxMap bk, bn;
+  double *C;
+  IdxMap cm, cn;
+  double alpha, beta;
+  bool kfast_a, nfast_b;
+};
+
+void gemm_f64(const GemmDesc &g, hipStream_t s);
+// raw register layout of one v_mfma_f64_16x16x4_f64 (a[64], b[64] -> out[256])
+void launch_mfma_probe(const double *a, const double *b, double *out, hipStream_t s);
+
+// --------------------------------------------------------------------------
+// coefficients and initial tensors (FP64)
+// --------------------------------------------------------------------------
+
+// t[0..2nmax] for n = -nmax..nmax.
+void launch_char_coeffs(double beta, double delta, int nmax, int nquad,
+                        double *t, hipStream_t s);
+// F, FM, FM1 for Q in [-qmax, qmax]; zero_field selects the exact deltas.
+void launch_field_factors(double beta, double h, double h1, int qmax,
+                          int lmax, bool zero_field, double *F, double *FM,
+                          double *FM1, hipStream_t s);
+// T[l][r][u][d] = sqrt(t_l t_r t_u t_d) * F(n_u + n_r - n_d - n_l).
+void launch_init_tensor(const double *t, const double *F, int nmax, double *T,
+                        hipStream_t s);
+
+// --------------------------------------------------------------------------
+// element-wise, reductions, permutations (FP64)
+// --------------------------------------------------------------------------
+
+// partial[] <- blockwise sums of x^2; final: out[0] = sqrt(sum), out[1] = ln,
+// out[2] = 1/norm. Deterministic (fixed tree, no atomics).
+void launch_fro_norm(const double *x, int64_t n, double *partial,
+                     double *out3, hipStream_t s);
+// x[i] *= *scale (device scalar)
+void launch_scale(double *x, int64_t n, const double *scale, hipStream_t s);
+// out[c][d][a][b] = in[a][b][c][d] with dims (A, B, C, D) -> (C, D, A, B)
+void launch_swap_pairs(const double *in, double *out, int A, int B, int C,
+                       int D, hipStream_t s);
+// out[a][c][b][d] = in[a][b][c][d]
+void launch_swap_middle(const double *in, double *out, int A, int B, int C,
+                        int D, hipStream_t s);
+// out[0] += sum_{l,u} T[l][l][u][u] (out zeroed first)
+void launch_trace(const double *T, int Dh, int Dv, double *out, hipStream_t s);
+// fill
+void launch_fill(double *x, int64_t n, double v, hipStream_t s);
+void launch_fill_i32(int32_t *x, int64_t n, int32_t v, hipStream_t s);
+void launch_identity(double *P, int n, hipStream_t s);
+
+// --------------------------------------------------------------------------
+// eigensolver: batched block-Jacobi on symmetric matrices padded to
+// multiples of 32 rows.
+// --------------------------------------------------------------------------
+
+struct EigBatch {
+  int32_t nmat;
+  int32_t *d_npad;     // padded size per matrix
+  int64_t *d_off;      // element offset of each matrix in A and V
+  int32_t *d_pairbase; // first pair index of each matrix (size nmat+1)
+  int32_t *d_pair_mat; // matrix of each pair
+  int32_t total_pairs;
+  int32_t max_nb;      // largest number of 16-row blocks
+  double *A, *V, *Q;   // matrices, eigenvectors, 32x32 rotations per pair
+  int32_t *d_flags;    // per matrix: 1 if a rotation was applied this sweep
+  double *d_scale;     // per matrix: absolute threshold scale
+  int32_t *d_rtl;      // per-update-tile descriptors
+  int32_t n_update_tiles;
+};
+
+// Gathers E[idx[i]][idx[j]] of every sector into the padded matrices;
+// padding rows get -1 on the diagonal. V <- identity.
+void launch_eig_gather(const double *E, int nfused, const int32_t *d_sec_idx,
+                       const int32_t *d_sec_start, const int32_t *d_sec_n,
+                       int nsec, const EigBatch &b, hipStream_t s);
+// One outer round of block Jacobi for every matrix.
+void launch_eig_round(const EigBatch &b, int round, hipStream_t s);
+void launch_eig_scale(const EigBatch &b, hipStream_t s);
+
+// --------------------------------------------------------------------------
+// selection and projector
+// --------------------------------------------------------------------------
+
+struct SelectArgs {
+  // both sides: sectors 0..nsec-1 are left, nsec..2nsec-1 right
+  int32_t nsec;
+  const int32_t *d_sec_label;  // [nsec]
+  const int32_t *d_sec_n;      // [nsec]
+  const int64_t *d_mat_off;    // [2 nsec] offsets of the padded matrices
+  const int32_t *d_mat_npad;   // [2 nsec]
+  const double *A;             // converged matrices (eigenvalues on diagonal)
+  int32_t dcut;
+  int32_t ncand;               // total candidates per side (sum of sec_n)
+  double tie_rel, side_tol;
+  // workspace
+  double *d_lam;               // [2 * ncand]
+  int32_t *d_cand_sec;         // [2 * ncand]
+  int32_t *d_cand_rank;        // [2 * ncand]
+  int32_t *d_cand_col;         // [2 * ncand] column in the padded matrix
+  int32_t *d_taken;            // [2 * ncand]
+  // outputs
+  int32_t *d_pick_sec;         // [dcut] sector (0..nsec-1) of each new state
+  int32_t *d_pick_col;         // [dcut] eigenvector column
+  int32_t *d_pick_label;       // [dcut]
+  double *d_diag;              // [8]: epsL, epsR, side, lam_max, gap, ties, trE
+};
+
+void launch_select(const SelectArgs &a, hipStream_t s);
+// P[nfused x dcut] from the chosen side's eigenvectors.
+void launch_build_projector(const double *V, const int64_t *d_mat_off,
+                            const int32_t *d_mat_npad, const int32_t *d_sec_idx,
+                            const int32_t *d_sec_start, const int32_t *d_sec_n,
+                            const int32_t *d_pick_sec, const int32_t *d_pick_col,
+                            const double *d_diag, int nsec, int nfused,
+                            int dcut, double *P, hipStream_t s);
+
+// final: res[0] = lnz, res[1] = m1, res[2] = m2 (NaN if absent), res[3] = status
+void launch_finish(const double *lnc, int nsteps, const double *tr,
+                   const double *tr1, const double *tr2, double *res,
+                   hipStream_t s);
+void launch_observables(int npts, const double *beta, const double *lnz,
+                        const double *mh, const double *mh1, double dbeta,
+                        double dh, double dh1, double *out, hipStream_t s);
+
+}  // namespace gxy

@@ -1,0 +1,305 @@
+"""ctypes binding of libgxyhotrg.so (include/gxy_hotrg.h).
+
+Argument marshalling only: every step of a run executes in the library's
+HIP kernels. torch supplies the device workspace and the HIP stream. There
+is no CPU fallback: if the library is missing, loading raises.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgxyhotrg.so")
+
+GXY_OK = 0
+STATUS = {0: "ok", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENUMERIC",
+          5: "EUNSUPPORTED", 6: "EPARTIAL"}
+
+
+class GxyError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Point(C.Structure):
+    _fields_ = [("beta", C.c_double), ("delta", C.c_double), ("h", C.c_double),
+                ("h1", C.c_double), ("nmax", C.c_int32), ("dcut", C.c_int32),
+                ("nsteps", C.c_int32), ("nquad", C.c_int32),
+                ("impurities", C.c_uint32), ("prec", C.c_int32),
+                ("fp64_steps", C.c_int32)]
+
+
+class Result(C.Structure):
+    _fields_ = [("lnz_per_site", C.c_double), ("m_cos1", C.c_double),
+                ("m_cos2", C.c_double), ("max_trunc_err", C.c_double),
+                ("min_cut_gap", C.c_double), ("near_ties", C.c_int32),
+                ("status", C.c_int32), ("fail_step", C.c_int32),
+                ("nsteps_done", C.c_int32)]
+
+
+class StepInfo(C.Structure):
+    _fields_ = [("lnc", C.c_double), ("eps_l", C.c_double), ("eps_r", C.c_double),
+                ("lam_max", C.c_double), ("cut_gap", C.c_double), ("side", C.c_int32),
+                ("dh", C.c_int32), ("dv", C.c_int32), ("truncated", C.c_int32),
+                ("ties", C.c_int32), ("pad_", C.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build()")
+    lib = C.CDLL(path)
+    P = C.POINTER
+    sigs = {
+        "gxy_create": [P(C.c_void_p), C.c_int, C.c_void_p],
+        "gxy_destroy": [C.c_void_p],
+        "gxy_workspace_bytes": [C.c_void_p, P(Point), C.c_int32, P(C.c_size_t)],
+        "gxy_set_workspace": [C.c_void_p, C.c_void_p, C.c_size_t],
+        "gxy_char_coeffs": [C.c_void_p, C.c_double, C.c_double, C.c_int32, C.c_int32,
+                            P(C.c_double)],
+        "gxy_initial_tensor": [C.c_void_p, P(Point), C.c_int32, P(C.c_double)],
+        "gxy_run": [C.c_void_p, P(Point), P(Result)],
+        "gxy_run_batch": [C.c_void_p, P(Point), C.c_int32, P(Result)],
+        "gxy_step_log": [C.c_void_p, C.c_int32, P(StepInfo), C.c_int32, P(C.c_int32)],
+        "gxy_observables": [C.c_void_p, C.c_int32, P(C.c_double), P(C.c_double),
+                            P(C.c_double), P(C.c_double), C.c_double, C.c_double,
+                            C.c_double, P(C.c_double)],
+        "gxy_phase_times": [C.c_void_p, P(C.c_double)],
+        "gxy_hot_kernel_stats": [C.c_void_p, P(C.c_double), C.c_int32],
+        "gxy_test_gemm_f64": [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, P(C.c_double),
+                              C.c_int32, P(C.c_double), C.c_int32, P(C.c_double)],
+        "gxy_test_eigh": [C.c_void_p, C.c_int32, P(C.c_double), P(C.c_double),
+                          P(C.c_double), P(C.c_int32)],
+        "gxy_test_mfma_layout": [C.c_void_p, P(C.c_double), P(C.c_double), P(C.c_double)],
+    }
+    for name, args in sigs.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    lib.gxy_status_string.argtypes = [C.c_int]
+    lib.gxy_status_string.restype = C.c_char_p
+    lib.gxy_last_error.argtypes = [C.c_void_p]
+    lib.gxy_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def make_point(beta, delta, h=0.0, h1=0.0, nmax=3, dcut=12, nsteps=30, nquad=4096,
+               impurities=3, prec=0, fp64_steps=0, **_ignored) -> Point:
+    return Point(float(beta), float(delta), float(h), float(h1), int(nmax), int(dcut),
+                 int(nsteps), int(nquad), int(impurities), int(prec), int(fp64_steps))
+
+
+def point_from(obj) -> Point:
+    if isinstance(obj, Point):
+        return obj
+    if isinstance(obj, dict):
+        return make_point(**obj)
+    return make_point(**obj.as_dict())
+
+
+@dataclass
+class RunResult:
+    lnz_per_site: float
+    m_cos1: float
+    m_cos2: float
+    max_trunc_err: float
+    min_cut_gap: float
+    near_ties: int
+    status: int
+    steps: list
+
+
+class Context:
+    """A library context bound to a device and torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None, torch_workspace: bool = True):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible")
+        self.device = device
+        torch.cuda.set_device(device)
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = C.c_void_p()
+        self._check(self.lib.gxy_create(C.byref(h), device, C.c_void_p(stream.cuda_stream)),
+                    None)
+        self.handle = h
+        self.torch_workspace = torch_workspace
+        self._ws = None
+
+    def _check(self, st, handle=None):
+        if st != GXY_OK:
+            msg = self.lib.gxy_last_error(handle if handle is not None else getattr(self, "handle", None))
+            raise GxyError(st, (msg or b"").decode())
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.gxy_destroy(self.handle)
+            self.handle = None
+            self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- workspace -------------------------------------------------------
+    def reserve(self, points: Sequence) -> int:
+        """Allocate (through torch) the device workspace for these points."""
+        arr = (Point * len(points))(*[point_from(p) for p in points])
+        nb = C.c_size_t()
+        self._check(self.lib.gxy_workspace_bytes(self.handle, arr, len(points), C.byref(nb)),
+                    self.handle)
+        self._reserve_bytes(nb.value)
+        return nb.value
+
+    def _reserve_bytes(self, nbytes: int):
+        if not self.torch_workspace:
+            return
+        if self._ws is None or self._ws.numel() < nbytes:
+            self.lib.gxy_set_workspace(self.handle, None, 0)
+            self._ws = None
+            self._ws = self.torch.empty(int(nbytes), dtype=self.torch.uint8,
+                                        device=f"cuda:{self.device}")
+            self._check(self.lib.gxy_set_workspace(self.handle, C.c_void_p(self._ws.data_ptr()),
+                                                   int(nbytes)), self.handle)
+
+    # -- calls ---------------------------------------------------------------
+    def char_coeffs(self, beta, delta, nmax, nquad=4096):
+        import numpy as np
+        out = (C.c_double * (2 * nmax + 1))()
+        self.reserve([make_point(beta, delta, nmax=nmax, dcut=1, nsteps=0, nquad=nquad,
+                                 impurities=0)])
+        self._check(self.lib.gxy_char_coeffs(self.handle, beta, delta, nmax, nquad, out),
+                    self.handle)
+        return np.array(out[:])
+
+    def initial_tensor(self, point, which=0):
+        import numpy as np
+        p = point_from(point)
+        D = 2 * p.nmax + 1
+        out = np.empty(D ** 4, dtype=np.float64)
+        self.reserve([p])
+        self._check(self.lib.gxy_initial_tensor(self.handle, C.byref(p), which,
+                                                out.ctypes.data_as(C.POINTER(C.c_double))),
+                    self.handle)
+        return out.reshape(D, D, D, D)
+
+    def run(self, point) -> RunResult:
+        p = point_from(point)
+        self.reserve([p])
+        r = Result()
+        st = self.lib.gxy_run(self.handle, C.byref(p), C.byref(r))
+        if st != GXY_OK and r.status == 0:
+            self._check(st, self.handle)
+        return self._result(r, 0)
+
+    def run_batch(self, points) -> List[RunResult]:
+        pts = [point_from(p) for p in points]
+        self.reserve(pts)
+        arr = (Point * len(pts))(*pts)
+        res = (Result * len(pts))()
+        st = self.lib.gxy_run_batch(self.handle, arr, len(pts), res)
+        if st not in (GXY_OK, 6):
+            self._check(st, self.handle)
+        return [self._result(res[i], i) for i in range(len(pts))]
+
+    def step_log(self, run=0):
+        cnt = C.c_int32()
+        self._check(self.lib.gxy_step_log(self.handle, run, None, 0, C.byref(cnt)), self.handle)
+        arr = (StepInfo * max(cnt.value, 1))()
+        self._check(self.lib.gxy_step_log(self.handle, run, arr, cnt.value, C.byref(cnt)),
+                    self.handle)
+        return [dict((f, getattr(arr[i], f)) for f, _ in StepInfo._fields_ if f != "pad_")
+                for i in range(cnt.value)]
+
+    def _result(self, r: Result, run: int) -> RunResult:
+        steps = self.step_log(run) if r.status == 0 else []
+        return RunResult(r.lnz_per_site, r.m_cos1, r.m_cos2, r.max_trunc_err,
+                         r.min_cut_gap, r.near_ties, r.status, steps)
+
+    def observables(self, beta, lnz, m_h, m_h1, dbeta, dh, dh1):
+        import numpy as np
+        beta = np.ascontiguousarray(beta, dtype=np.float64)
+        lnz = np.ascontiguousarray(lnz, dtype=np.float64)
+        m_h = np.ascontiguousarray(m_h, dtype=np.float64)
+        m_h1 = np.ascontiguousarray(m_h1, dtype=np.float64)
+        n = len(beta)
+        out = np.empty((n, 4))
+        self._reserve_bytes(8 * 12 * n + 4096)
+        dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))  # noqa: E731
+        self._check(self.lib.gxy_observables(self.handle, n, dp(beta), dp(lnz), dp(m_h),
+                                             dp(m_h1), dbeta, dh, dh1, dp(out)), self.handle)
+        return out
+
+    # -- single-kernel checks (include/gxy_hotrg_testing.h) -------------------
+    def test_gemm(self, A, B, a_trans=False, b_trans=False):
+        """C = A @ B through the FP64 MFMA GEMM; A (M,K), B (K,N) as numpy."""
+        import numpy as np
+        M, K = A.shape
+        K2, N = B.shape
+        assert K == K2
+        Ah = np.ascontiguousarray(A.T if a_trans else A, dtype=np.float64)
+        Bh = np.ascontiguousarray(B.T if b_trans else B, dtype=np.float64)
+        out = np.empty((M, N))
+        self._reserve_bytes(8 * (M * K + K * N + M * N) + 4096)
+        dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))  # noqa: E731
+        self._check(self.lib.gxy_test_gemm_f64(self.handle, M, N, K, dp(Ah), int(a_trans),
+                                               dp(Bh), int(b_trans), dp(out)), self.handle)
+        return out
+
+    def test_eigh(self, A):
+        import numpy as np
+        A = np.ascontiguousarray(A, dtype=np.float64)
+        n = A.shape[0]
+        w = np.empty(n)
+        V = np.empty((n, n))
+        npad = (n + 31) // 32 * 32
+        q = npad // 32
+        self._reserve_bytes(8 * (2 * n * n + 4 * npad * npad + 2 * q * 1024 + 1024)
+                            + 4 * (n + 16 * q * q + 256) + 65536)
+        dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))  # noqa: E731
+        sw = C.c_int32(0)
+        self._check(self.lib.gxy_test_eigh(self.handle, n, dp(A), dp(w), dp(V), C.byref(sw)),
+                    self.handle)
+        self.last_sweeps = sw.value
+        return w, V
+
+    def test_mfma_layout(self, a, b):
+        import numpy as np
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        out = np.empty(256)
+        self._reserve_bytes(8 * 384 + 4096)
+        dp = lambda x: x.ctypes.data_as(C.POINTER(C.c_double))  # noqa: E731
+        self._check(self.lib.gxy_test_mfma_layout(self.handle, dp(a), dp(b), dp(out)),
+                    self.handle)
+        return out.reshape(64, 4)
+
+    def hot_kernel_stats(self, reset=True):
+        """(launches, total ms, algorithmic flops, algorithmic bytes) of the D^7 GEMM."""
+        out = (C.c_double * 4)()
+        self._check(self.lib.gxy_hot_kernel_stats(self.handle, out, int(reset)), self.handle)
+        return list(out)
+
+    def phase_times(self):
+        out = (C.c_double * 6)()
+        self._check(self.lib.gxy_phase_times(self.handle, out), self.handle)
+        return list(out)

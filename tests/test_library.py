@@ -1,0 +1,59 @@
+"""Host-side checks of the C-ABI library (no GPU needed)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2609_20536_amd", "libgxyhotrg.so")
+HEADERS = [os.path.join(ROOT, "include", f) for f in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if f.endswith(".h")]
+
+
+def declared_symbols():
+    names = set()
+    for h in HEADERS:
+        txt = open(h).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_ \*]*?\b(gxy_[a-z0-9_]+)\s*\(",
+                             txt, flags=re.M):
+            names.add(m.group(1))
+    return names
+
+
+def test_headers_declare_the_api():
+    names = declared_symbols()
+    for n in ["gxy_create", "gxy_destroy", "gxy_run", "gxy_run_batch", "gxy_char_coeffs",
+              "gxy_initial_tensor", "gxy_step_log", "gxy_observables", "gxy_workspace_bytes",
+              "gxy_set_workspace", "gxy_status_string", "gxy_last_error"]:
+        assert n in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in sorted(declared_symbols()) if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_status_strings_and_null_arguments():
+    lib = ctypes.CDLL(LIB)
+    lib.gxy_status_string.restype = ctypes.c_char_p
+    assert lib.gxy_status_string(0) == b"ok"
+    assert lib.gxy_status_string(4) == b"numerical failure"
+    # every entry point rejects null handles without touching a device
+    assert lib.gxy_run(None, None, None) == 1
+    assert lib.gxy_run_batch(None, None, 0, None) == 1
+    assert lib.gxy_destroy(None) == 1
+    assert lib.gxy_create(None, 0, None) == 1
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    from paper_2609_20536_amd import hotrg
+    with pytest.raises(RuntimeError):
+        hotrg._lib = None
+        hotrg.load_library(str(tmp_path / "missing.so"))
+    hotrg._lib = None

@@ -354,3 +354,19 @@ def test_free_energy_plausible_against_thesis_table():
     F = -r.lnz_per_site / beta
     assert F >= -0.5436066 - 1e-3
     assert abs(F - (-0.5436043)) < 0.03
+
+
+def test_conditioning_spread_of_single_point():
+    """At beta=1, Delta=0.5, Dcut=12 the truncated flow amplifies rounding:
+    1-ulp relative perturbations of the initial tensor move ln Z/V by up to
+    ~1e-10, which bounds any parity claim at this point (the GPU parity
+    test compares it at 1e-9 and its first ten steps at 1e-11)."""
+    T, _ = o.initial_tensors(1.0, 0.5, 0.0, 0.0, 3)
+    lab = o.leg_labels(3, o.SYM_U1)
+    base = o.hotrg_run(T, {}, lab, lab, o.SYM_U1, 12, 30).lnz_per_site
+    rng = np.random.default_rng(1)
+    spread = 0.0
+    for _ in range(3):
+        Tp = T * (1 + 2.0 ** -52 * rng.standard_normal(T.shape))
+        spread = max(spread, abs(o.hotrg_run(Tp, {}, lab, lab, o.SYM_U1, 12, 30).lnz_per_site - base))
+    assert 1e-12 < spread < 1e-9
