@@ -94,7 +94,7 @@ typedef struct {
   int32_t dh, dv;       /* bond dimensions after the step (l/r, u/d)         */
   int32_t truncated;    /* 0 if the fused bond fit (P = identity)            */
   int32_t ties;
-  int32_t pad_;
+  int32_t eig_sweeps;   /* block-Jacobi sweeps: first stage + 100 * refinement */
 } gxy_step_info;
 
 typedef struct gxy_ctx gxy_ctx;

@@ -42,7 +42,10 @@ design notes):
   remaining eigenvalues within TIE_REL * lambda_max of the largest
   remaining one, the state with the smallest (|q|, q, rank in its sector).
   eps = sum of the eigenvalues not kept. The right side is used only if
-  eps_R < eps_L - SIDE_TOL * lambda_max; ties go to the left side.
+  eps_R < eps_L - SIDE_TOL * lambda_max; ties go to the left side. The
+  model's reflection symmetry makes eps_L = eps_R exactly at many steps, and
+  two FP64 evaluations of these sums over ~Dh^2 eigenvalues differ by up to
+  ~Dh^2 eps lambda_max, so SIDE_TOL (1e-10) sits well above that level.
 * The impurity tensor is updated as 1/2 [Proj(T_X, T) + Proj(T, T_X)] with
   the pure tensor's projector and norm.
 * The normalisation constant is the Frobenius norm.
@@ -57,7 +60,7 @@ from typing import Dict, List, Optional, Sequence, Tuple
 import numpy as np
 
 TIE_REL = 1e-12
-SIDE_TOL = 1e-12
+SIDE_TOL = 1e-10
 
 IMP_COS1 = 1
 IMP_COS2 = 2
@@ -259,7 +262,8 @@ class Sector:
     vec: np.ndarray        # eigenvectors as columns, same order
 
 
-def sector_eigh(E: np.ndarray, labels: np.ndarray) -> List[Sector]:
+def sector_eigh(E: np.ndarray, labels: np.ndarray,
+                basis_rng: Optional[np.random.Generator] = None) -> List[Sector]:
     """Eigendecomposition of the symmetric E restricted to each label sector.
 
     E commutes with the symmetry, so it is block diagonal in the fused label;
@@ -267,11 +271,24 @@ def sector_eigh(E: np.ndarray, labels: np.ndarray) -> List[Sector]:
     decreasing eigenvalue. Eigenvector signs are fixed so the entry of
     largest magnitude is positive (a gauge choice that does not enter any
     output).
+
+    basis_rng (test option): diagonalise Q^T E_s Q for a random orthogonal Q
+    and rotate back. This is an equally valid backward-stable FP64 eigensolve
+    with a different rounding pattern; comparing runs with and without it
+    measures how far the run is fixed by FP64 eigensolver rounding at all
+    (near-degenerate eigenvalues at the cut make the kept vectors
+    ill-determined).
     """
     out = []
     for s in np.unique(labels):
         idx = np.nonzero(labels == s)[0]
-        w, v = np.linalg.eigh(E[np.ix_(idx, idx)])
+        Es = E[np.ix_(idx, idx)]
+        if basis_rng is not None and len(idx) > 1:
+            Q = np.linalg.qr(basis_rng.standard_normal((len(idx), len(idx))))[0]
+            w, v = np.linalg.eigh(Q.T @ Es @ Q)
+            v = Q @ v
+        else:
+            w, v = np.linalg.eigh(Es)
         order = np.argsort(-w, kind="stable")
         w, v = w[order], v[:, order]
         big = np.argmax(np.abs(v), axis=0)
@@ -414,7 +431,8 @@ def _norm(T: np.ndarray, kind: str) -> float:
 
 def hotrg_run(T: np.ndarray, imps: Dict[int, np.ndarray], lab_h: np.ndarray,
               lab_v: np.ndarray, sym: int, dcut: int, nsteps: int,
-              first: str = "y", norm: str = "fro") -> RunResult:
+              first: str = "y", norm: str = "fro",
+              basis_seed: Optional[int] = None) -> RunResult:
     """Coarse-grain T (and impurity tensors) nsteps times; ln Z per site.
 
     ln Z / 2^N = ln c_0 + sum_n ln c_n / 2^n + ln Tr T_N / 2^N, where c_n is
@@ -427,6 +445,7 @@ def hotrg_run(T: np.ndarray, imps: Dict[int, np.ndarray], lab_h: np.ndarray,
     """
     T = np.array(T, dtype=np.float64)
     imps = {k: np.array(v, dtype=np.float64) for k, v in imps.items()}
+    brng = None if basis_seed is None else np.random.default_rng(basis_seed)
     lab_h = np.asarray(lab_h)
     lab_v = np.asarray(lab_v)
     c0 = _norm(T, norm)
@@ -450,7 +469,7 @@ def hotrg_run(T: np.ndarray, imps: Dict[int, np.ndarray], lab_h: np.ndarray,
             truncated = False
         else:
             EL, ER = environments(T)
-            sel = select_states(sector_eigh(EL, fused), sector_eigh(ER, fused),
+            sel = select_states(sector_eigh(EL, fused, brng), sector_eigh(ER, fused, brng),
                                 dcut, Dh * Dh)
             P = sel.P
             new_h = sel.labels
@@ -483,12 +502,14 @@ def hotrg_run(T: np.ndarray, imps: Dict[int, np.ndarray], lab_h: np.ndarray,
 def run_point(beta: float, delta: float, h: float = 0.0, h1: float = 0.0,
               nmax: int = 3, dcut: int = 12, nsteps: int = 30,
               nquad: int = 4096, impurities: int = IMP_COS1 | IMP_COS2,
-              first: str = "y", norm: str = "fro", **_ignored) -> RunResult:
+              first: str = "y", norm: str = "fro", basis_seed: Optional[int] = None,
+              **_ignored) -> RunResult:
     """One HOTRG run from the gXY parameters (the full problem statement)."""
     sym = symmetry_of(h, h1)
     T, imps = initial_tensors(beta, delta, h, h1, nmax, nquad, impurities)
     lab = leg_labels(nmax, sym)
-    return hotrg_run(T, imps, lab, lab, sym, dcut, nsteps, first=first, norm=norm)
+    return hotrg_run(T, imps, lab, lab, sym, dcut, nsteps, first=first, norm=norm,
+                     basis_seed=basis_seed)
 
 
 def observables_from_runs(beta: float, lnz: Sequence[float], m_h: Sequence[float],

@@ -24,11 +24,12 @@
 #include <vector>
 
 #include "internal.h"
+#include "plan.h"
 
 namespace gxy {
 
 constexpr double kTieRel = 1e-12;
-constexpr double kSideTol = 1e-12;
+constexpr double kSideTol = 1e-10;
 constexpr int kMaxSweeps = 40;
 constexpr int kLmax = 50;
 
@@ -76,6 +77,8 @@ struct Plan {
   int maxDn = 0;
   int64_t chunk_elems = 0;  // X / Y chunk buffer elements
   int nimp = 0;
+  int64_t tab_env = 0, tab_proj = 0;  // offset-table entries (bounds)
+  int64_t grp_env = 0, grp_proj = 0;  // group descriptors (bounds)
 };
 
 static Plan make_plan(const gxy_point &p, size_t chunk_bytes) {
@@ -112,6 +115,22 @@ static Plan make_plan(const gxy_point &p, size_t chunk_bytes) {
   int64_t ac = (int64_t)(chunk_bytes / (sizeof(double) * nbuf * per_a_max));
   ac = std::max<int64_t>(1, std::min<int64_t>(ac, pl.maxDn));
   pl.chunk_elems = ac * per_a_max;
+  // bounds of the charge-block tables of one step (see plan.hip): every row,
+  // reduction and column index appears in at most |S| <= 2 groups per table
+  const int64_t nvar = 1 + 2 * pl.nimp;
+  for (const StepDims &sd : pl.steps) {
+    const int64_t Dh = sd.dh, Dv = sd.dv, Dn = sd.dn, MN = Dh * Dv;
+    const int64_t nch = (Dn + ac - 1) / ac;
+    const int64_t env = 2 * (8 * MN + 4 * Dh * Dh + Dv * Dv) + 64;
+    const int64_t proj = nch * nvar *
+                             (2 * (2 * Dn * Dh + 2 * Dh + 4 * Dh * Dv * Dv) +
+                              2 * (Dn * Dh * Dv + 2 * MN + MN) +
+                              2 * (2 * Dn * Dv * Dv + 2 * Dh * Dh + 2 * Dn)) + 64;
+    pl.tab_env = std::max(pl.tab_env, env);
+    pl.tab_proj = std::max(pl.tab_proj, proj);
+    pl.grp_env = std::max(pl.grp_env, 2 * (2 * MN + Dh * Dh) + 16);
+    pl.grp_proj = std::max(pl.grp_proj, nch * nvar * (Dn * Dh + 2 * MN + Dn + 16));
+  }
   return pl;
 }
 
@@ -121,7 +140,10 @@ struct Buffers {
   double *envA, *envB, *E;         // environments
   double *P;
   double *X, *XI, *Y;              // projection chunks
-  double *eigA, *eigV, *eigQ;
+  double *eigA, *eigV, *eigQ, *eigB1, *eigB2;
+  int64_t *gtab;
+  GGroup *ggrp;
+  int64_t gtab_cap, ggrp_cap;
   double *eig_scale;
   int32_t *eig_flags;
   int32_t *ints;                   // sector / pair / tile tables
@@ -134,6 +156,8 @@ struct Buffers {
   double *nrm;                     // 3 * (nsteps + 1)
   double *coef;                    // t, F, FM, FM1
   double *scal;                    // traces and result
+  int64_t *tab_env, *tab_proj;     // charge-block offset tables
+  GGroup *grp_env, *grp_proj;
   int64_t eig_elems, eig_q;
   int64_t sel_cap;
 };
@@ -161,10 +185,17 @@ static size_t carve(const gxy_point &p, const Plan &pl, Carver &c, Buffers &b) {
   b.eig_elems = 2 * (nf * nf + 1023 * nf);
   b.eigA = c.take<double>(std::max<int64_t>(b.eig_elems, 1));
   b.eigV = c.take<double>(std::max<int64_t>(b.eig_elems, 1));
+  b.eigB1 = c.take<double>(std::max<int64_t>(b.eig_elems, 1));
+  b.eigB2 = c.take<double>(std::max<int64_t>(b.eig_elems, 1));
+  // batched-product tables: 4 entries per padded row, 2 groups per matrix
+  b.gtab_cap = 256 * nf + 64;
+  b.ggrp_cap = 2 * 2 * nf + 8;
+  b.gtab = c.take<int64_t>(b.gtab_cap);
+  b.ggrp = c.take<GGroup>(b.ggrp_cap);
   b.eig_q = 2 * nf * 1024 + 1024;
   b.eigQ = c.take<double>(b.eig_q);
   b.eig_scale = c.take<double>(2 * nf + 2);
-  b.eig_flags = c.take<int32_t>(4 * nf + 4);
+  b.eig_flags = c.take<int32_t>(4 * nf + 4 + 2 * nf + 4);  // flags, next flags, pair_rot
   // tables: sec idx (nf), start/n/label (3 nf), mats (2*2nf npad + 2*2nf off
   // as 2 ints), pairbase (2nf+1), pair_mat (<= 2 nf), tiles (4 * bound)
   const int64_t nmat = 2 * nf;
@@ -184,6 +215,10 @@ static size_t carve(const gxy_point &p, const Plan &pl, Carver &c, Buffers &b) {
   const int qmax = 4 * p.nmax;
   b.coef = c.take<double>(pl.d0 + 3 * (2 * qmax + 1));
   b.scal = c.take<double>(16);
+  b.tab_env = c.take<int64_t>(pl.tab_env);
+  b.tab_proj = c.take<int64_t>(pl.tab_proj);
+  b.grp_env = c.take<GGroup>(pl.grp_env);
+  b.grp_proj = c.take<GGroup>(pl.grp_proj);
   return c.off + 256;
 }
 
@@ -213,6 +248,11 @@ struct gxy_ctx {
   bool hot_on = false;
   void *pinned = nullptr;  // small host staging buffer
   size_t pinned_bytes = 0;
+  // two pinned staging buffers for table uploads, each guarded by an event
+  void *stage[3] = {nullptr, nullptr, nullptr};
+  size_t stage_bytes[3] = {0, 0, 0};
+  hipEvent_t stage_ev[3] = {nullptr, nullptr, nullptr};
+  bool stage_used[3] = {false, false, false};
 };
 
 namespace gxy {
@@ -224,6 +264,50 @@ static void ensure_pinned(gxy_ctx *ctx, size_t bytes) {
   ctx->pinned_bytes = 0;
   GXY_HIP(hipHostMalloc(&ctx->pinned, bytes, hipHostMallocDefault));
   ctx->pinned_bytes = bytes;
+}
+
+// Copy a table plan to the device through pinned staging buffer j; the
+// buffer is reused only after its previous copy has completed.
+static void upload_plan(gxy_ctx *ctx, int j, const TablePlan &tp, int64_t *d_tab,
+                        int64_t tab_cap, GGroup *d_grp, int64_t grp_cap, hipStream_t s) {
+  if ((int64_t)tp.tab.size() > tab_cap || (int64_t)tp.groups.size() > grp_cap)
+    fail(GXY_ENOMEM, "charge-block table bound exceeded");
+  const size_t tb = tp.tab.size() * sizeof(int64_t), gb = tp.groups.size() * sizeof(GGroup);
+  const size_t need = tb + gb + 64;
+  if (ctx->stage_used[j]) GXY_HIP(hipEventSynchronize(ctx->stage_ev[j]));
+  if (ctx->stage_bytes[j] < need) {
+    if (ctx->stage[j]) GXY_HIP(hipHostFree(ctx->stage[j]));
+    ctx->stage[j] = nullptr;
+    GXY_HIP(hipHostMalloc(&ctx->stage[j], need + need / 2, hipHostMallocDefault));
+    ctx->stage_bytes[j] = need + need / 2;
+  }
+  if (!ctx->stage_ev[j]) GXY_HIP(hipEventCreateWithFlags(&ctx->stage_ev[j], hipEventDisableTiming));
+  char *h = (char *)ctx->stage[j];
+  memcpy(h, tp.tab.data(), tb);
+  memcpy(h + tb, tp.groups.data(), gb);
+  if (tb) GXY_HIP(hipMemcpyAsync(d_tab, h, tb, hipMemcpyHostToDevice, s));
+  if (gb) GXY_HIP(hipMemcpyAsync(d_grp, h + tb, gb, hipMemcpyHostToDevice, s));
+  GXY_HIP(hipEventRecord(ctx->stage_ev[j], s));
+  ctx->stage_used[j] = true;
+}
+
+static void run_launch(const Launch &L, const GGroup *d_grp, const int64_t *d_tab,
+                       const double *A, const double *B, double *C, double alpha, double beta,
+                       hipStream_t s) {
+  GroupedGemm g{};
+  g.ngroups = L.ngroups;
+  g.total_tiles = L.total_tiles;
+  g.tile = L.tile;
+  g.groups = d_grp + L.first_group;
+  g.tab = d_tab;
+  g.A = A;
+  g.B = B;
+  g.C = C;
+  g.alpha = alpha;
+  g.beta = beta;
+  g.kfast_a = L.kfast_a;
+  g.nfast_b = L.nfast_b;
+  grouped_gemm_f64(g, s);
 }
 
 static void ensure_workspace(gxy_ctx *ctx, size_t need) {
@@ -492,18 +576,57 @@ struct EigMem {
   double *A, *V, *Q, *scale;
   int32_t *flags, *ints;
   int64_t ints_cap, eig_elems, eig_q;
+  double *B1, *B2;        // scratch matrices of the refinement stage
+  int64_t *gtab;          // offset tables of the batched matrix products
+  GGroup *ggrp;
+  int64_t gtab_cap, ggrp_cap;
 };
+
+// Stage tolerances of the block-Jacobi solver (scale = max |E_ii| of the
+// batch). Stage 1 removes couplings above 1e-9 scale. The refinement removes
+// couplings above 64 eps scale, and also smaller ones between nearly
+// degenerate states whose rotation angle |a_pq / (a_pp - a_qq)| exceeds 1e-6
+// (these decide which of two close states is kept at the cut), but never
+// couplings below 8 eps sqrt(|a_pp a_qq|), the rounding noise the 32 x 32
+// block updates regenerate.
+constexpr double kEps = 2.220446049250313e-16;
+constexpr double kStage1Abs = 1e-9;
+constexpr double kStage2Abs = 64 * kEps;
+constexpr double kStage2Rel = 8 * kEps;
+constexpr double kStage2Gap = 1e-6;
+
+// Sweeps until no pair has a significant coupling; returns the sweep count.
+static int jacobi_sweeps(const EigBatch &eb, double abs_tol, double rel_tol, double gap_tol,
+                         hipStream_t s, int32_t *hp) {
+  const int nmat = eb.nmat;
+  launch_eig_scale(eb, s);
+  launch_fill_i32(eb.d_flags + nmat, nmat, 0, s);
+  for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
+    for (int rr = 0; rr < eb.max_nb - 1; ++rr)
+      launch_eig_round(eb, rr, abs_tol, rel_tol, gap_tol, 1, s);
+    // flags <- next flags, next <- 0, and read them back
+    GXY_HIP(hipMemcpyAsync(eb.d_flags, eb.d_flags + nmat, nmat * sizeof(int32_t),
+                           hipMemcpyDeviceToDevice, s));
+    launch_fill_i32(eb.d_flags + nmat, nmat, 0, s);
+    GXY_HIP(hipMemcpyAsync(hp, eb.d_flags, nmat * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    GXY_HIP(hipStreamSynchronize(s));
+    bool any = false;
+    for (int k = 0; k < nmat; ++k) any |= hp[k] != 0;
+    if (!any) return sweep + 1;
+  }
+  fail(GXY_ENUMERIC, "block-Jacobi eigensolver did not converge");
+}
 
 struct SectorSolve {
   EigBatch eb;
   const int32_t *d_idx, *d_start, *d_n, *d_lab;
-  int sweeps;
+  int sweeps, sweeps2;  // block-Jacobi sweeps of the two stages
 };
 
 // Eigendecomposition of every label sector of E_L (E) and E_R (E + nf*nf) by
 // batched block Jacobi. hp: pinned host scratch (>= 2 * nsec ints).
-static SectorSolve solve_sectors(hipStream_t s, const double *E, int nf, const Sectors &sec,
-                                 const EigMem &m, int32_t *hp) {
+static SectorSolve solve_sectors(gxy_ctx *ctx, hipStream_t s, const double *E, int nf,
+                                 const Sectors &sec, const EigMem &m, int32_t *hp) {
   const int nsec = (int)sec.label.size();
   const int nmat = 2 * nsec;
   std::vector<int32_t> npad(nmat), pairbase(nmat + 1), pair_mat, tiles;
@@ -569,27 +692,77 @@ static SectorSolve solve_sectors(hipStream_t s, const double *E, int nf, const S
   eb.d_scale = m.scale;
   eb.d_rtl = m.ints + o_tl;
   eb.n_update_tiles = (int32_t)(tiles.size() / 4);
-  launch_eig_gather(E, nf, r.d_idx, r.d_start, r.d_n, nsec, eb, s);
-  launch_eig_scale(eb, s);
-  launch_fill_i32(eb.d_flags + nmat, nmat, 0, s);
-  bool converged = false;
-  for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
-    for (int rr = 0; rr < max_nb - 1; ++rr) launch_eig_round(eb, rr, s);
-    // flags <- next flags, next <- 0, and read them back
-    GXY_HIP(hipMemcpyAsync(eb.d_flags, eb.d_flags + nmat, nmat * sizeof(int32_t),
-                           hipMemcpyDeviceToDevice, s));
-    launch_fill_i32(eb.d_flags + nmat, nmat, 0, s);
-    GXY_HIP(hipMemcpyAsync(hp, eb.d_flags, nmat * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    GXY_HIP(hipStreamSynchronize(s));
-    bool any = false;
-    for (int k = 0; k < nmat; ++k) any |= hp[k] != 0;
-    r.sweeps = sweep + 1;
-    if (!any) {
-      converged = true;
-      break;
+  eb.d_pair_rot = m.flags + 2 * nmat;
+  // batched products over the padded matrices: C = A B and C = A^T B
+  TablePlan tp;
+  Launch L_nn, L_tn;
+  {
+    std::vector<GGroup> nn, tn;
+    L_nn.first_group = 0;
+    for (int k = 0; k < nmat; ++k) {
+      const int np = npad[k];
+      std::vector<int64_t> R(np), I(np), RT(np), IT(np);
+      for (int i = 0; i < np; ++i) {
+        R[i] = off[k] + (int64_t)i * np;
+        I[i] = i;
+        RT[i] = off[k] + i;
+        IT[i] = (int64_t)i * np;
+      }
+      const int64_t oR = (int64_t)tp.tab.size();
+      tp.tab.insert(tp.tab.end(), R.begin(), R.end());
+      const int64_t oI = (int64_t)tp.tab.size();
+      tp.tab.insert(tp.tab.end(), I.begin(), I.end());
+      const int64_t oRT = (int64_t)tp.tab.size();
+      tp.tab.insert(tp.tab.end(), RT.begin(), RT.end());
+      const int64_t oIT = (int64_t)tp.tab.size();
+      tp.tab.insert(tp.tab.end(), IT.begin(), IT.end());
+      nn.push_back(GGroup{np, np, np, 0, oR, oI, oR, oI, oR, oI});
+      tn.push_back(GGroup{np, np, np, 0, oRT, oIT, oR, oI, oR, oI});
     }
+    auto finish = [&](std::vector<GGroup> &gs, Launch &L, bool kfa) {
+      L.first_group = (int32_t)tp.groups.size();
+      L.tile = 64;
+      L.kfast_a = kfa;
+      L.nfast_b = true;
+      for (GGroup g : gs) {
+        g.tile_start = L.total_tiles;
+        L.total_tiles += ((g.M + 63) / 64) * ((g.N + 63) / 64);
+        tp.groups.push_back(g);
+        ++L.ngroups;
+      }
+    };
+    finish(nn, L_nn, true);
+    finish(tn, L_tn, false);
   }
-  if (!converged) fail(GXY_ENUMERIC, "block-Jacobi eigensolver did not converge");
+  upload_plan(ctx, 2, tp, m.gtab, m.gtab_cap, m.ggrp, m.ggrp_cap, s);
+  auto mm = [&](const Launch &L, const double *A, const double *B, double *C, double alpha,
+                double beta) { run_launch(L, m.ggrp, m.gtab, A, B, C, alpha, beta, s); };
+
+  // stage 1: block Jacobi on the sectors of E to a loose tolerance
+  launch_eig_gather(E, nf, r.d_idx, r.d_start, r.d_n, nsec, eb, s);
+  r.sweeps = jacobi_sweeps(eb, kStage1Abs, 0.0, 1e300, s, hp);
+  // re-orthonormalise the accumulated rotations (one Newton-Schulz step):
+  // V2 = V (3 I - V^T V) / 2
+  mm(L_tn, m.V, m.V, m.B1, 1.0, 0.0);
+  launch_eig_scaled_copy(tot, 1.5, m.V, m.B2, s);
+  mm(L_nn, m.V, m.B1, m.B2, -0.5, 1.0);
+  // Rayleigh-Ritz with the original sector matrices: R = V2^T E_s V2
+  EigBatch e_orig = eb;
+  e_orig.A = m.B1;
+  e_orig.V = nullptr;
+  launch_eig_gather(E, nf, r.d_idx, r.d_start, r.d_n, nsec, e_orig, s);
+  mm(L_nn, m.B1, m.B2, m.A, 1.0, 0.0);
+  mm(L_tn, m.B2, m.A, m.B1, 1.0, 0.0);
+  // stage 2: R is nearly diagonal; Jacobi to rounding level
+  EigBatch e2 = eb;
+  e2.A = m.B1;
+  e2.V = m.A;
+  launch_eig_identity(e2, m.A, s);
+  r.sweeps2 = jacobi_sweeps(e2, kStage2Abs, kStage2Rel, kStage2Gap, s, hp);
+  // eigenvectors V = V2 W, eigenvalues on the diagonal of the final R
+  mm(L_nn, m.B2, m.A, m.V, 1.0, 0.0);
+  r.eb.A = m.B1;
+  r.eb.V = m.V;
   return r;
 }
 
@@ -662,6 +835,18 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
   for (int k = 0; k < nimp; ++k) launch_scale(b.TX[k], nT, b.nrm + 2, s);
   tm.end(0);
 
+  const int mod = (sym == SYM_U1) ? 0 : (sym == SYM_Z2 ? 2 : 1);
+  // allowed Q = q_l + q_d - q_r - q_u of each impurity tensor
+  QSet imp_set[2];
+  for (int k = 0; k < nimp; ++k) {
+    const bool cos1 = imp_which[k] == 1;
+    if (sym == SYM_U1)
+      imp_set[k] = cos1 ? QSet{-1, 1} : QSet{-2, 2};
+    else if (sym == SYM_Z2)
+      imp_set[k] = cos1 ? QSet{1} : QSet{0};
+    else
+      imp_set[k] = QSet{0};
+  }
   std::vector<int> lh(D0), lv(D0);
   for (int i = 0; i < D0; ++i) {
     const int q = i - nmax;
@@ -686,6 +871,7 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
       }
       std::swap(Dh, Dv);
       std::swap(lh, lv);
+      for (int k = 0; k < nimp; ++k) imp_set[k] = qset_negate(imp_set[k], mod);
       tm.end(5);
     }
     const int64_t nf = (int64_t)Dh * Dh;
@@ -701,17 +887,34 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
     } else {
       // ---- environments ----
       tm.begin();
-      env_gemms(b.T, Dh, Dv, b.envA, b.envB, b.E, false, s);
-      env_gemms(b.T, Dh, Dv, b.envA, b.envB, b.E + nf * nf, true, s);
+      if (sym == SYM_NONE) {
+        env_gemms(b.T, Dh, Dv, b.envA, b.envB, b.E, false, s);
+        env_gemms(b.T, Dh, Dv, b.envA, b.envB, b.E + nf * nf, true, s);
+      } else {
+        StepLegs SL{Dh, Dv, Dn, mod, lh, lv, {}};
+        TablePlan tp;
+        Launch le[3], re[3];
+        plan_env(SL, false, tp, le);
+        plan_env(SL, true, tp, re);
+        upload_plan(ctx, 0, tp, b.tab_env, pl.tab_env, b.grp_env, pl.grp_env, s);
+        run_launch(le[0], b.grp_env, b.tab_env, b.T, b.T, b.envA, 1.0, 0.0, s);
+        run_launch(le[1], b.grp_env, b.tab_env, b.T, b.T, b.envB, 1.0, 0.0, s);
+        run_launch(le[2], b.grp_env, b.tab_env, b.envA, b.envB, b.E, 1.0, 0.0, s);
+        run_launch(re[0], b.grp_env, b.tab_env, b.T, b.T, b.envA, 1.0, 0.0, s);
+        run_launch(re[1], b.grp_env, b.tab_env, b.T, b.T, b.envB, 1.0, 0.0, s);
+        run_launch(re[2], b.grp_env, b.tab_env, b.envA, b.envB, b.E + nf * nf, 1.0, 0.0, s);
+      }
       tm.end(1);
       // ---- sectors and eigensolver tables ----
       tm.begin();
       const Sectors sec = make_sectors(lh, sym);
       const int nsec = (int)sec.label.size();
       EigMem em{b.eigA, b.eigV, b.eigQ, b.eig_scale, b.eig_flags, b.ints, b.ints_cap,
-                b.eig_elems, b.eig_q};
-      const SectorSolve sv = solve_sectors(s, b.E, (int)nf, sec, em, hp);
+                b.eig_elems, b.eig_q, b.eigB1, b.eigB2, b.gtab, b.ggrp, b.gtab_cap,
+                b.ggrp_cap};
+      const SectorSolve sv = solve_sectors(ctx, s, b.E, (int)nf, sec, em, hp);
       const EigBatch &eb = sv.eb;
+      info.eig_sweeps = sv.sweeps + 100 * sv.sweeps2;
       const int32_t *d_idx = sv.d_idx, *d_start = sv.d_start, *d_n = sv.d_n,
                     *d_lab = sv.d_lab;
       tm.end(2);
@@ -723,7 +926,7 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
       sa.d_sec_n = d_n;
       sa.d_mat_off = eb.d_off;
       sa.d_mat_npad = eb.d_npad;
-      sa.A = b.eigA;
+      sa.A = eb.A;
       sa.dcut = Dn;
       sa.ncand = (int32_t)nf;
       sa.tie_rel = kTieRel;
@@ -738,7 +941,7 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
       sa.d_pick_label = b.pick + 2 * Dn;
       sa.d_diag = b.diag;
       launch_select(sa, s);
-      launch_build_projector(b.eigV, eb.d_off, eb.d_npad, d_idx, d_start, d_n, b.pick,
+      launch_build_projector(eb.V, eb.d_off, eb.d_npad, d_idx, d_start, d_n, b.pick,
                              b.pick + Dn, b.diag, nsec, (int)nf, Dn, b.P, s);
       GXY_HIP(hipMemcpyAsync(hp, b.pick + 2 * Dn, Dn * sizeof(int32_t),
                              hipMemcpyDeviceToHost, s));
@@ -774,17 +977,67 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
       proj_y(Xp, Bp, Dh, Dv, ac, b.Y, s);
       hot_end(ctx, s);
     };
-    for (int a0 = 0; a0 < Dn; a0 += ac_max) {
-      const int ac = std::min(ac_max, Dn - a0);
-      proj_x(b.P, Dh, Dv, Dn, a0, ac, b.T, b.X, s);
-      hot_y(b.X, b.T2, ac);
-      proj_t(b.Y, b.P, Dh, Dv, Dn, a0, ac, 1.0, 0.0, b.Tn, s);
-      for (int k = 0; k < nimp; ++k) {
-        hot_y(b.X, b.TX2[k], ac);
-        proj_t(b.Y, b.P, Dh, Dv, Dn, a0, ac, 0.5, 0.0, b.TXn[k], s);
-        proj_x(b.P, Dh, Dv, Dn, a0, ac, b.TX[k], b.XI, s);
-        hot_y(b.XI, b.T2, ac);
-        proj_t(b.Y, b.P, Dh, Dv, Dn, a0, ac, 0.5, 1.0, b.TXn[k], s);
+    if (sym == SYM_NONE) {
+      for (int a0 = 0; a0 < Dn; a0 += ac_max) {
+        const int ac = std::min(ac_max, Dn - a0);
+        proj_x(b.P, Dh, Dv, Dn, a0, ac, b.T, b.X, s);
+        hot_y(b.X, b.T2, ac);
+        proj_t(b.Y, b.P, Dh, Dv, Dn, a0, ac, 1.0, 0.0, b.Tn, s);
+        for (int k = 0; k < nimp; ++k) {
+          hot_y(b.X, b.TX2[k], ac);
+          proj_t(b.Y, b.P, Dh, Dv, Dn, a0, ac, 0.5, 0.0, b.TXn[k], s);
+          proj_x(b.P, Dh, Dv, Dn, a0, ac, b.TX[k], b.XI, s);
+          hot_y(b.XI, b.T2, ac);
+          proj_t(b.Y, b.P, Dh, Dv, Dn, a0, ac, 0.5, 1.0, b.TXn[k], s);
+        }
+      }
+    } else {
+      // charge-block launches for every chunk; tables built and uploaded once
+      StepLegs SL{Dh, Dv, Dn, mod, lh, lv, new_lh};
+      TablePlan tp;
+      const QSet s0{0};
+      struct ChunkPlan {
+        int a0, ac;
+        Launch x0, y00, t0;
+        Launch y0k[2], tk[2], xk[2], yk0[2];
+      };
+      std::vector<ChunkPlan> cps;
+      for (int a0 = 0; a0 < Dn; a0 += ac_max) {
+        ChunkPlan cp;
+        cp.a0 = a0;
+        cp.ac = std::min(ac_max, Dn - a0);
+        const int a1 = a0 + cp.ac;
+        cp.x0 = plan_proj_x(SL, a0, a1, s0, tp);
+        cp.y00 = plan_proj_y(SL, a0, a1, s0, s0, tp);
+        cp.t0 = plan_proj_t(SL, a0, a1, s0, tp);
+        for (int k = 0; k < nimp; ++k) {
+          cp.y0k[k] = plan_proj_y(SL, a0, a1, s0, imp_set[k], tp);
+          cp.tk[k] = plan_proj_t(SL, a0, a1, imp_set[k], tp);
+          cp.xk[k] = plan_proj_x(SL, a0, a1, imp_set[k], tp);
+          cp.yk0[k] = plan_proj_y(SL, a0, a1, imp_set[k], s0, tp);
+        }
+        cps.push_back(cp);
+      }
+      upload_plan(ctx, 1, tp, b.tab_proj, pl.tab_proj, b.grp_proj, pl.grp_proj, s);
+      const int64_t nTn = (int64_t)Dn * Dn * Dv * Dv;
+      launch_fill(b.Tn, nTn, 0.0, s);
+      for (int k = 0; k < nimp; ++k) launch_fill(b.TXn[k], nTn, 0.0, s);
+      auto hot_gy = [&](const Launch &L, const double *Xp, const double *Bp) {
+        hot_begin(ctx, s, L.flops, 0.0);
+        run_launch(L, b.grp_proj, b.tab_proj, Xp, Bp, b.Y, 1.0, 0.0, s);
+        hot_end(ctx, s);
+      };
+      for (const ChunkPlan &cp : cps) {
+        run_launch(cp.x0, b.grp_proj, b.tab_proj, b.P, b.T, b.X, 1.0, 0.0, s);
+        hot_gy(cp.y00, b.X, b.T2);
+        run_launch(cp.t0, b.grp_proj, b.tab_proj, b.Y, b.P, b.Tn, 1.0, 0.0, s);
+        for (int k = 0; k < nimp; ++k) {
+          hot_gy(cp.y0k[k], b.X, b.TX2[k]);
+          run_launch(cp.tk[k], b.grp_proj, b.tab_proj, b.Y, b.P, b.TXn[k], 0.5, 0.0, s);
+          run_launch(cp.xk[k], b.grp_proj, b.tab_proj, b.P, b.TX[k], b.XI, 1.0, 0.0, s);
+          hot_gy(cp.yk0[k], b.XI, b.T2);
+          run_launch(cp.tk[k], b.grp_proj, b.tab_proj, b.Y, b.P, b.TXn[k], 0.5, 1.0, s);
+        }
       }
     }
     tm.end(4);
@@ -808,6 +1061,7 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
       }
       std::swap(Dh, Dv);
       std::swap(lh, lv);
+      for (int k = 0; k < nimp; ++k) imp_set[k] = qset_negate(imp_set[k], mod);
     }
     tm.end(5);
     info.dh = Dh;
@@ -919,6 +1173,10 @@ gxy_status gxy_destroy(gxy_ctx *ctx) {
   if (ctx->ws && ctx->ws_owned) (void)hipFree(ctx->ws);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  for (int j = 0; j < 3; ++j) {
+    if (ctx->stage_ev[j]) (void)hipEventDestroy(ctx->stage_ev[j]);
+    if (ctx->stage[j]) (void)hipHostFree(ctx->stage[j]);
+  }
   delete ctx;
   return GXY_OK;
 }
@@ -1148,14 +1406,20 @@ gxy_status gxy_test_eigh(gxy_ctx *ctx, int32_t n, const double *A, double *w, do
   m.eig_q = 2 * (np / 32) * 1024 + 1024;
   const int64_t tiles = 2 * (3 * (np / 32) * (np / 32) / 2 + 4);
   m.ints_cap = n + 8 + 12 + 4 + 2 * (np / 32) + 4 * tiles + 64;
+  m.gtab_cap = 8 * np + 64;
+  m.ggrp_cap = 8;
   Carver c;
   for (int pass = 0; pass < 2; ++pass) {
     double *E = c.take<double>(2 * nn);
     m.A = c.take<double>(m.eig_elems);
     m.V = c.take<double>(m.eig_elems);
+    m.B1 = c.take<double>(m.eig_elems);
+    m.B2 = c.take<double>(m.eig_elems);
+    m.gtab = c.take<int64_t>(m.gtab_cap);
+    m.ggrp = c.take<GGroup>(m.ggrp_cap);
     m.Q = c.take<double>(m.eig_q);
     m.scale = c.take<double>(8);
-    m.flags = c.take<int32_t>(16);
+    m.flags = c.take<int32_t>(16 + 2 * (np / 32) + 16);
     m.ints = c.take<int32_t>(m.ints_cap);
     if (pass == 0) {
       ensure_workspace(ctx, c.off + 256);
@@ -1167,12 +1431,12 @@ gxy_status gxy_test_eigh(gxy_ctx *ctx, int32_t n, const double *A, double *w, do
     hipStream_t s = ctx->stream;
     GXY_HIP(hipMemcpyAsync(E, A, nn * sizeof(double), hipMemcpyHostToDevice, s));
     GXY_HIP(hipMemcpyAsync(E + nn, A, nn * sizeof(double), hipMemcpyHostToDevice, s));
-    const SectorSolve sv = solve_sectors(s, E, n, sec, m, (int32_t *)ctx->pinned);
-    if (sweeps) *sweeps = sv.sweeps;
+    const SectorSolve sv = solve_sectors(ctx, s, E, n, sec, m, (int32_t *)ctx->pinned);
+    if (sweeps) *sweeps = sv.sweeps + sv.sweeps2;
     // eigenvalues: diagonal of the converged matrix; vectors: first n rows/cols
-    GXY_HIP(hipMemcpy2DAsync(V, n * sizeof(double), m.V, np * sizeof(double),
+    GXY_HIP(hipMemcpy2DAsync(V, n * sizeof(double), sv.eb.V, np * sizeof(double),
                              n * sizeof(double), n, hipMemcpyDeviceToHost, s));
-    GXY_HIP(hipMemcpy2DAsync(w, sizeof(double), m.A, (np + 1) * sizeof(double),
+    GXY_HIP(hipMemcpy2DAsync(w, sizeof(double), sv.eb.A, (np + 1) * sizeof(double),
                              sizeof(double), n, hipMemcpyDeviceToHost, s));
     GXY_HIP(hipStreamSynchronize(s));
   }

@@ -81,6 +81,27 @@ struct GemmDesc {
 };
 
 void gemm_f64(const GemmDesc &g, hipStream_t s);
+
+// One dense sub-product of a grouped launch: M x N x K, tiles numbered from
+// tile_start; ar/ac/br/bc/cr/cc index the shared int64 offset table.
+struct GGroup {
+  int32_t M, N, K, tile_start;
+  int64_t ar, ac, br, bc, cr, cc;
+};
+
+// Many independent sub-products in one launch (charge blocks). Tile size is
+// tile x tile (64 or 128) for every group of the launch.
+struct GroupedGemm {
+  int32_t ngroups, total_tiles, tile;
+  const GGroup *groups;
+  const int64_t *tab;
+  const double *A, *B;
+  double *C;
+  double alpha, beta;
+  bool kfast_a, nfast_b;
+};
+
+void grouped_gemm_f64(const GroupedGemm &g, hipStream_t s);
 // raw register layout of one v_mfma_f64_16x16x4_f64 (a[64], b[64] -> out[256])
 void launch_mfma_probe(const double *a, const double *b, double *out, hipStream_t s);
 
@@ -140,6 +161,7 @@ struct EigBatch {
   double *d_scale;     // per matrix: absolute threshold scale
   int32_t *d_rtl;      // per-update-tile descriptors
   int32_t n_update_tiles;
+  int32_t *d_pair_rot; // per pair: 1 if its subproblem was rotated this round
 };
 
 // Gathers E[idx[i]][idx[j]] of every sector into the padded matrices;
@@ -147,9 +169,17 @@ struct EigBatch {
 void launch_eig_gather(const double *E, int nfused, const int32_t *d_sec_idx,
                        const int32_t *d_sec_start, const int32_t *d_sec_n,
                        int nsec, const EigBatch &b, hipStream_t s);
-// One outer round of block Jacobi for every matrix.
-void launch_eig_round(const EigBatch &b, int round, hipStream_t s);
+// One outer round of block Jacobi for every matrix. A coupling a_pq is
+// rotated if |a_pq| > rel_tol sqrt(|a_pp a_qq|) and (|a_pq| > abs_tol scale or
+// |a_pq| > gap_tol |a_pp - a_qq|); each pair subproblem gets inner_sweeps
+// cyclic sweeps.
+void launch_eig_round(const EigBatch &b, int round, double abs_tol, double rel_tol,
+                      double gap_tol, int inner_sweeps, hipStream_t s);
+// per-matrix max |diagonal|, reduced to the batch maximum; flags <- 1
 void launch_eig_scale(const EigBatch &b, hipStream_t s);
+void launch_eig_identity(const EigBatch &b, double *V, hipStream_t s);
+// y = a x over n elements
+void launch_eig_scaled_copy(int64_t n, double a, const double *x, double *y, hipStream_t s);
 
 // --------------------------------------------------------------------------
 // selection and projector

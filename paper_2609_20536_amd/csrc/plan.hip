@@ -1,0 +1,353 @@
+// Charge-block plans: host-side enumeration of the groups and offset tables
+// of the grouped GEMM launches of one HOTRG step (see plan.h).
+#include "plan.h"
+
+#include <algorithm>
+#include <utility>
+
+namespace gxy {
+
+QSet qset_negate(const QSet &s, int mod) {
+  QSet o;
+  for (int x : s) o.push_back(qnorm(-x, mod));
+  std::sort(o.begin(), o.end());
+  o.erase(std::unique(o.begin(), o.end()), o.end());
+  return o;
+}
+
+QSet qset_sum(const QSet &a, const QSet &b, int mod) {
+  QSet o;
+  for (int x : a)
+    for (int y : b) o.push_back(qnorm(x + y, mod));
+  std::sort(o.begin(), o.end());
+  o.erase(std::unique(o.begin(), o.end()), o.end());
+  return o;
+}
+
+namespace {
+
+typedef std::pair<int, int> PI;
+typedef std::map<int, std::vector<PI>> PairBuckets;
+
+// (x, y) pairs grouped by qnorm(sx q[x] + sy q[y]); x outer, y inner.
+PairBuckets pair_buckets(const std::vector<int> &qx, const std::vector<int> &qy, int sx, int sy,
+                         int mod) {
+  PairBuckets out;
+  for (int x = 0; x < (int)qx.size(); ++x)
+    for (int y = 0; y < (int)qy.size(); ++y)
+      out[qnorm(sx * qx[x] + sy * qy[y], mod)].push_back(PI(x, y));
+  return out;
+}
+
+std::map<int, std::vector<int>> leg_buckets(const std::vector<int> &q, int mod) {
+  std::map<int, std::vector<int>> out;
+  for (int i = 0; i < (int)q.size(); ++i) out[qnorm(q[i], mod)].push_back(i);
+  return out;
+}
+
+bool in_set(int x, const QSet &s) { return std::find(s.begin(), s.end(), x) != s.end(); }
+
+struct GSpec {
+  int32_t M, N, K;
+  int64_t ar, ac, br, bc, cr, cc;
+};
+
+int64_t put(TablePlan &tp, const std::vector<int64_t> &v) {
+  const int64_t at = (int64_t)tp.tab.size();
+  tp.tab.insert(tp.tab.end(), v.begin(), v.end());
+  return at;
+}
+
+int choose_tile(const std::vector<GSpec> &gs) {
+  int64_t t128 = 0;
+  double work = 0.0;
+  for (const auto &g : gs) {
+    t128 += (int64_t)((g.M + 127) / 128) * ((g.N + 127) / 128);
+    work += (double)g.M * g.N;
+  }
+  if (t128 < 256) return 64;
+  return work / ((double)t128 * 128.0 * 128.0) >= 0.6 ? 128 : 64;
+}
+
+Launch finish_launch(TablePlan &tp, const std::vector<GSpec> &gs, bool kfa, bool nfb) {
+  Launch L;
+  L.first_group = (int32_t)tp.groups.size();
+  L.kfast_a = kfa;
+  L.nfast_b = nfb;
+  L.tile = choose_tile(gs);
+  for (const auto &g : gs) {
+    if (g.M <= 0 || g.N <= 0) continue;
+    GGroup G;
+    G.M = g.M;
+    G.N = g.N;
+    G.K = g.K;
+    G.tile_start = L.total_tiles;
+    G.ar = g.ar;
+    G.ac = g.ac;
+    G.br = g.br;
+    G.bc = g.bc;
+    G.cr = g.cr;
+    G.cc = g.cc;
+    L.total_tiles += ((g.M + L.tile - 1) / L.tile) * ((g.N + L.tile - 1) / L.tile);
+    L.flops += 2.0 * g.M * g.N * (double)g.K;
+    tp.groups.push_back(G);
+    ++L.ngroups;
+  }
+  return L;
+}
+
+}  // namespace
+
+void plan_env(const StepLegs &S, bool right, TablePlan &tp, Launch out[3]) {
+  const int Dh = S.Dh, Dv = S.Dv, mod = S.mod;
+  const int64_t sl = (int64_t)Dh * Dv * Dv, sr = (int64_t)Dv * Dv, MN = (int64_t)Dh * Dv;
+  const int64_t nf = (int64_t)Dh * Dh;
+  // --- top Gram: rows (x, i), reduction (y, u) with x the open horizontal
+  // leg and y the contracted one.  left: x = l1, y = r1, key q_l1 + q_i =
+  // q_r1 + q_u.  right: x = r1, y = l1, key q_r1 - q_i = q_l1 - q_u.
+  {
+    const PairBuckets rows = right ? pair_buckets(S.lh, S.lv, 1, -1, mod)
+                                   : pair_buckets(S.lh, S.lv, 1, 1, mod);
+    const PairBuckets ks = right ? pair_buckets(S.lh, S.lv, 1, -1, mod)
+                                 : pair_buckets(S.lh, S.lv, 1, 1, mod);
+    const int64_t sx = right ? sr : sl, sy = right ? sl : sr;
+    std::vector<GSpec> gs;
+    for (const auto &kv : rows) {
+      std::vector<int64_t> ar, ac, cr, cc;
+      for (const PI &p : kv.second) {
+        ar.push_back(p.first * sx + p.second);
+        cr.push_back((p.first * (int64_t)Dv + p.second) * MN);
+        cc.push_back(p.first * (int64_t)Dv + p.second);
+      }
+      auto it = ks.find(kv.first);
+      if (it != ks.end())
+        for (const PI &p : it->second) ac.push_back(p.first * sy + p.second * (int64_t)Dv);
+      GSpec g;
+      g.M = g.N = (int32_t)ar.size();
+      g.K = (int32_t)ac.size();
+      g.ar = put(tp, ar);
+      g.bc = g.ar;
+      g.ac = put(tp, ac);
+      g.br = g.ac;
+      g.cr = put(tp, cr);
+      g.cc = put(tp, cc);
+      gs.push_back(g);
+    }
+    out[0] = finish_launch(tp, gs, false, true);
+  }
+  // --- bottom Gram: rows (x, i), reduction (y, d).  left: x = l2, y = r2,
+  // key q_l2 - q_i = q_r2 - q_d.  right: x = r2, y = l2, key q_r2 + q_i =
+  // q_l2 + q_d.
+  {
+    const PairBuckets rows = right ? pair_buckets(S.lh, S.lv, 1, 1, mod)
+                                   : pair_buckets(S.lh, S.lv, 1, -1, mod);
+    const PairBuckets ks = right ? pair_buckets(S.lh, S.lv, 1, 1, mod)
+                                 : pair_buckets(S.lh, S.lv, 1, -1, mod);
+    const int64_t sx = right ? sr : sl, sy = right ? sl : sr;
+    std::vector<GSpec> gs;
+    for (const auto &kv : rows) {
+      std::vector<int64_t> ar, ac, cr, cc;
+      for (const PI &p : kv.second) {
+        ar.push_back(p.first * sx + p.second * (int64_t)Dv);
+        cr.push_back((p.first * (int64_t)Dv + p.second) * MN);
+        cc.push_back(p.first * (int64_t)Dv + p.second);
+      }
+      auto it = ks.find(kv.first);
+      if (it != ks.end())
+        for (const PI &p : it->second) ac.push_back(p.first * sy + p.second);
+      GSpec g;
+      g.M = g.N = (int32_t)ar.size();
+      g.K = (int32_t)ac.size();
+      g.ar = put(tp, ar);
+      g.bc = g.ar;
+      g.ac = put(tp, ac);
+      g.br = g.ac;
+      g.cr = put(tp, cr);
+      g.cc = put(tp, cc);
+      gs.push_back(g);
+    }
+    out[1] = finish_launch(tp, gs, true, false);
+  }
+  // --- E[(x1,x2),(x1',x2')] = sum_{i,i'} envA[x1,i,x1',i'] envB[x2,i,x2',i']
+  // kappa = q_i - q_i'.  left: rows (l1,l1') with q_l1' - q_l1 = kappa, cols
+  // (l2,l2') with q_l2 - q_l2' = kappa.  right: rows (r1,r1') with
+  // q_r1 - q_r1' = kappa, cols (r2,r2') with q_r2' - q_r2 = kappa.
+  {
+    const PairBuckets rows = right ? pair_buckets(S.lh, S.lh, 1, -1, mod)
+                                   : pair_buckets(S.lh, S.lh, -1, 1, mod);
+    const PairBuckets cols = right ? pair_buckets(S.lh, S.lh, -1, 1, mod)
+                                   : pair_buckets(S.lh, S.lh, 1, -1, mod);
+    const PairBuckets ks = pair_buckets(S.lv, S.lv, 1, -1, mod);
+    const int64_t row = (int64_t)Dv * MN;
+    std::vector<GSpec> gs;
+    for (const auto &kv : rows) {
+      auto ic = cols.find(kv.first);
+      if (ic == cols.end()) continue;
+      std::vector<int64_t> ar, ac, bc, cr, cc;
+      for (const PI &p : kv.second) {
+        ar.push_back(p.first * row + p.second * (int64_t)Dv);
+        cr.push_back(p.first * (int64_t)Dh * nf + p.second * (int64_t)Dh);
+      }
+      for (const PI &p : ic->second) {
+        bc.push_back(p.first * row + p.second * (int64_t)Dv);
+        cc.push_back(p.first * nf + p.second);
+      }
+      auto ik = ks.find(kv.first);
+      if (ik != ks.end())
+        for (const PI &p : ik->second) ac.push_back(p.first * MN + p.second);
+      GSpec g;
+      g.M = (int32_t)ar.size();
+      g.N = (int32_t)bc.size();
+      g.K = (int32_t)ac.size();
+      g.ar = put(tp, ar);
+      g.ac = put(tp, ac);
+      g.br = g.ac;
+      g.bc = put(tp, bc);
+      g.cr = put(tp, cr);
+      g.cc = put(tp, cc);
+      gs.push_back(g);
+    }
+    out[2] = finish_launch(tp, gs, true, false);
+  }
+}
+
+Launch plan_proj_x(const StepLegs &S, int a0, int a1, const QSet &sA, TablePlan &tp) {
+  const int Dh = S.Dh, Dv = S.Dv, Dn = S.Dn, mod = S.mod;
+  const int64_t per_a = (int64_t)Dh * Dv * Dh * Dv;
+  const auto l1s = leg_buckets(S.lh, mod);
+  // rows (a, l2) keyed by c = q_a - q_l2 (= q_l1); a varies fastest
+  std::map<int, std::vector<PI>> rows;
+  for (int l2 = 0; l2 < Dh; ++l2)
+    for (int a = a0; a < a1; ++a) rows[qnorm(S.ln[a] - S.lh[l2], mod)].push_back(PI(a, l2));
+  std::vector<GSpec> gs;
+  for (const auto &kv : rows) {
+    const int c = kv.first;
+    std::vector<int64_t> ar, ac, br, bc, cr, cc;
+    for (const PI &p : kv.second) {
+      ar.push_back((int64_t)p.second * Dn + p.first);
+      cr.push_back((int64_t)(p.first - a0) * per_a + (int64_t)p.second * Dv);
+    }
+    auto il = l1s.find(c);
+    if (il != l1s.end())
+      for (int l1 : il->second) {
+        ac.push_back((int64_t)l1 * Dh * Dn);
+        br.push_back((int64_t)l1 * Dh * Dv * Dv);
+      }
+    // columns (r1, u, i) with c + q_i - q_r1 - q_u in sA
+    for (int r1 = 0; r1 < Dh; ++r1)
+      for (int u = 0; u < Dv; ++u)
+        for (int i = 0; i < Dv; ++i)
+          if (in_set(qnorm(c + S.lv[i] - S.lh[r1] - S.lv[u], mod), sA)) {
+            bc.push_back((int64_t)r1 * Dv * Dv + (int64_t)u * Dv + i);
+            cc.push_back((int64_t)r1 * Dv * Dh * Dv + (int64_t)u * Dh * Dv + i);
+          }
+    GSpec g;
+    g.M = (int32_t)ar.size();
+    g.N = (int32_t)bc.size();
+    g.K = (int32_t)ac.size();
+    g.ar = put(tp, ar);
+    g.ac = put(tp, ac);
+    g.br = put(tp, br);
+    g.bc = put(tp, bc);
+    g.cr = put(tp, cr);
+    g.cc = put(tp, cc);
+    gs.push_back(g);
+  }
+  return finish_launch(tp, gs, false, true);
+}
+
+Launch plan_proj_y(const StepLegs &S, int a0, int a1, const QSet &sA, const QSet &sB,
+                   TablePlan &tp) {
+  const int Dh = S.Dh, Dv = S.Dv, mod = S.mod;
+  const int64_t W = (int64_t)Dh * Dv;
+  // rho = q_a - q_r1 - q_u per row (a, r1, u); kappa = q_l2 - q_i per reduction
+  // index (l2, i); nu = q_r2 - q_d per column (r2, d).
+  std::map<int, std::vector<int64_t>> rows_by_rho, ks_by_kappa, cols_by_nu;
+  for (int a = a0; a < a1; ++a)
+    for (int r1 = 0; r1 < Dh; ++r1)
+      for (int u = 0; u < Dv; ++u)
+        rows_by_rho[qnorm(S.ln[a] - S.lh[r1] - S.lv[u], mod)].push_back(
+            (((int64_t)(a - a0) * Dh + r1) * Dv + u) * W);
+  for (int l2 = 0; l2 < Dh; ++l2)
+    for (int i = 0; i < Dv; ++i)
+      ks_by_kappa[qnorm(S.lh[l2] - S.lv[i], mod)].push_back((int64_t)l2 * Dv + i);
+  for (int r2 = 0; r2 < Dh; ++r2)
+    for (int d = 0; d < Dv; ++d)
+      cols_by_nu[qnorm(S.lh[r2] - S.lv[d], mod)].push_back((int64_t)r2 * Dv + d);
+  std::vector<int> kappas;
+  for (const auto &kv : rows_by_rho)
+    for (int s : sA) kappas.push_back(qnorm(kv.first - s, mod));
+  std::sort(kappas.begin(), kappas.end());
+  kappas.erase(std::unique(kappas.begin(), kappas.end()), kappas.end());
+  std::vector<GSpec> gs;
+  for (int kappa : kappas) {
+    std::vector<int64_t> rows, cols, ac, br;
+    for (const auto &kv : rows_by_rho)
+      if (in_set(qnorm(kv.first - kappa, mod), sA))
+        rows.insert(rows.end(), kv.second.begin(), kv.second.end());
+    for (const auto &kv : cols_by_nu)
+      if (in_set(qnorm(kappa - kv.first, mod), sB))
+        cols.insert(cols.end(), kv.second.begin(), kv.second.end());
+    if (rows.empty() || cols.empty()) continue;
+    auto ik = ks_by_kappa.find(kappa);
+    if (ik != ks_by_kappa.end()) {
+      ac = ik->second;
+      for (int64_t k : ik->second) br.push_back(k * W);
+    }
+    GSpec g;
+    g.M = (int32_t)rows.size();
+    g.N = (int32_t)cols.size();
+    g.K = (int32_t)ac.size();
+    g.ar = put(tp, rows);
+    g.cr = g.ar;
+    g.ac = put(tp, ac);
+    g.br = put(tp, br);
+    g.bc = put(tp, cols);
+    g.cc = g.bc;
+    gs.push_back(g);
+  }
+  return finish_launch(tp, gs, true, true);
+}
+
+Launch plan_proj_t(const StepLegs &S, int a0, int a1, const QSet &sY, TablePlan &tp) {
+  const int Dh = S.Dh, Dv = S.Dv, Dn = S.Dn, mod = S.mod;
+  const int64_t W = (int64_t)Dh * Dv, per_a = W * W;
+  const auto bs = leg_buckets(S.ln, mod);
+  const PairBuckets ks = pair_buckets(S.lh, S.lh, 1, 1, mod);  // q_r1 + q_r2
+  std::vector<GSpec> gs;
+  for (const auto &kv : bs) {
+    const int sigma = kv.first;
+    std::vector<int64_t> ar, ac, br, bc, cr, cc;
+    for (int a = a0; a < a1; ++a)
+      for (int u = 0; u < Dv; ++u)
+        for (int d = 0; d < Dv; ++d)
+          if (in_set(qnorm(S.ln[a] - S.lv[u] + S.lv[d] - sigma, mod), sY)) {
+            ar.push_back((int64_t)(a - a0) * per_a + (int64_t)u * W + d);
+            cr.push_back((int64_t)a * Dn * Dv * Dv + (int64_t)u * Dv + d);
+          }
+    auto ik = ks.find(sigma);
+    if (ik != ks.end())
+      for (const PI &p : ik->second) {
+        ac.push_back((int64_t)p.first * Dv * W + (int64_t)p.second * Dv);
+        br.push_back(((int64_t)p.first * Dh + p.second) * Dn);
+      }
+    for (int b : kv.second) {
+      bc.push_back(b);
+      cc.push_back((int64_t)b * Dv * Dv);
+    }
+    GSpec g;
+    g.M = (int32_t)ar.size();
+    g.N = (int32_t)bc.size();
+    g.K = (int32_t)ac.size();
+    g.ar = put(tp, ar);
+    g.ac = put(tp, ac);
+    g.br = put(tp, br);
+    g.bc = put(tp, bc);
+    g.cr = put(tp, cr);
+    g.cc = put(tp, cc);
+    gs.push_back(g);
+  }
+  return finish_launch(tp, gs, false, true);
+}
+
+}  // namespace gxy

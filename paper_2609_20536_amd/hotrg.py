@@ -47,7 +47,7 @@ class StepInfo(C.Structure):
     _fields_ = [("lnc", C.c_double), ("eps_l", C.c_double), ("eps_r", C.c_double),
                 ("lam_max", C.c_double), ("cut_gap", C.c_double), ("side", C.c_int32),
                 ("dh", C.c_int32), ("dv", C.c_int32), ("truncated", C.c_int32),
-                ("ties", C.c_int32), ("pad_", C.c_int32)]
+                ("ties", C.c_int32), ("eig_sweeps", C.c_int32)]
 
 
 _lib = None
@@ -227,7 +227,7 @@ class Context:
         arr = (StepInfo * max(cnt.value, 1))()
         self._check(self.lib.gxy_step_log(self.handle, run, arr, cnt.value, C.byref(cnt)),
                     self.handle)
-        return [dict((f, getattr(arr[i], f)) for f, _ in StepInfo._fields_ if f != "pad_")
+        return [dict((f, getattr(arr[i], f)) for f, _ in StepInfo._fields_)
                 for i in range(cnt.value)]
 
     def _result(self, r: Result, run: int) -> RunResult:
@@ -273,8 +273,8 @@ class Context:
         V = np.empty((n, n))
         npad = (n + 31) // 32 * 32
         q = npad // 32
-        self._reserve_bytes(8 * (2 * n * n + 4 * npad * npad + 2 * q * 1024 + 1024)
-                            + 4 * (n + 16 * q * q + 256) + 65536)
+        self._reserve_bytes(8 * (2 * n * n + 8 * npad * npad + 2 * q * 1024 + 2048 + 8 * npad)
+                            + 4 * (n + 16 * q * q + 256) + (1 << 20))
         dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))  # noqa: E731
         sw = C.c_int32(0)
         self._check(self.lib.gxy_test_eigh(self.handle, n, dp(A), dp(w), dp(V), C.byref(sw)),

@@ -1,7 +1,10 @@
 """Write oracle reference values for the GPU parity tests.
 
 Calls only the CPU oracle (oracle/). Each job writes tests/golden/<name>.json
-with the point, ln Z per site, the impurity values and the per-step logs.
+with the point, ln Z per site, the impurity values and the per-step logs;
+--spread adds the oracle's own spread under equally valid FP64 eigensolves
+(runs whose cut falls inside a near-degenerate multiplet are only
+determined to that level).
 Jobs whose oracle run takes minutes to hours (Dcut >= 48 at 40 steps) are
 computed once with this script and stored.
 
@@ -65,6 +68,34 @@ def jobs():
     return j
 
 
+def spread_of(pt, runs=2):
+    """Largest |d ln Z/V| and |d m| of the oracle between its default run and
+    runs whose sector eigensolves use a random orthogonal basis (an equally
+    valid FP64 backward-stable eigensolve with a different rounding pattern).
+    Where near-degenerate eigenvalues straddle the cut, the kept vectors -- and
+    so the run -- are fixed by the FP64 eigensolve only to this level."""
+    base = o.run_point(**pt)
+    sp, spm = 0.0, 0.0
+    for seed in range(1, runs + 1):
+        r = o.run_point(**pt, basis_seed=seed)
+        sp = max(sp, abs(r.lnz_per_site - base.lnz_per_site))
+        for a, b in ((r.m_cos1, base.m_cos1), (r.m_cos2, base.m_cos2)):
+            if a == a and b == b:
+                spm = max(spm, abs(a - b))
+    return sp, spm
+
+
+def add_spread(name):
+    path = os.path.join(HERE, name + ".json")
+    gd = json.load(open(path))
+    sp, spm = spread_of(gd["point"])
+    gd["spread"] = sp
+    gd["spread_m"] = spm
+    with open(path, "w") as f:
+        json.dump(gd, f, indent=1)
+    return sp
+
+
 def run_job(name, pt):
     t0 = time.time()
     r = o.run_point(**pt)
@@ -80,6 +111,7 @@ def run_job(name, pt):
         "eps_r": [s.eps_r for s in r.steps],
         "side": [s.side for s in r.steps],
         "cut_gap": [s.cut_gap for s in r.steps],
+        "lam_max": [s.lam_max for s in r.steps],
         "ties": [s.ties for s in r.steps],
         "oracle_seconds": time.time() - t0,
         "writer": "tests/golden/make_golden.py (CPU oracle only)",
@@ -94,6 +126,10 @@ if __name__ == "__main__":
     if "--list" in sys.argv:
         for k, v in J.items():
             print(k, v)
+        sys.exit(0)
+    if sys.argv[1] == "--spread":
+        for name in sys.argv[2:]:
+            print(name, "spread", add_spread(name), flush=True)
         sys.exit(0)
     for name in sys.argv[1:]:
         r = run_job(name, J[name])

@@ -84,8 +84,8 @@ def _select_smallest(secL, secR, dcut, nfused):
     return sel
 
 
-def _run_wrong_lognorm(T, imps, lab_h, lab_v, sym, dcut, nsteps, first="y", norm="fro"):
-    r = _orig_run(T, imps, lab_h, lab_v, sym, dcut, nsteps, first, norm)
+def _run_wrong_lognorm(T, imps, lab_h, lab_v, sym, dcut, nsteps, first="y", norm="fro", **kw):
+    r = _orig_run(T, imps, lab_h, lab_v, sym, dcut, nsteps, first, norm, **kw)
     # mistake: weight ln c_n by 2^-(n-1)
     extra = sum(s.lnc / 2.0 ** (i + 1) for i, s in enumerate(r.steps))
     r.lnz_per_site += extra
