@@ -18,6 +18,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <future>
 #include <map>
 #include <memory>
 #include <string>
@@ -253,6 +254,11 @@ struct gxy_ctx {
   size_t stage_bytes[3] = {0, 0, 0};
   hipEvent_t stage_ev[3] = {nullptr, nullptr, nullptr};
   bool stage_used[3] = {false, false, false};
+  // pinned arena for the projection tables of one step
+  void *arena = nullptr;
+  size_t arena_bytes = 0, arena_cur = 0;
+  hipEvent_t arena_ev = nullptr;
+  bool arena_pending = false;
 };
 
 namespace gxy {
@@ -289,6 +295,48 @@ static void upload_plan(gxy_ctx *ctx, int j, const TablePlan &tp, int64_t *d_tab
   if (gb) GXY_HIP(hipMemcpyAsync(d_grp, h + tb, gb, hipMemcpyHostToDevice, s));
   GXY_HIP(hipEventRecord(ctx->stage_ev[j], s));
   ctx->stage_used[j] = true;
+}
+
+// Projection tables of one step: each part is copied through its own slice of
+// a pinned arena (reset once the previous step's copies have completed).
+static void upload_part(gxy_ctx *ctx, const TablePlan &tp, int64_t *d_tab, int64_t tab_cap,
+                        GGroup *d_grp, int64_t grp_cap, hipStream_t s) {
+  if ((int64_t)tp.tab.size() > tab_cap || (int64_t)tp.groups.size() > grp_cap)
+    fail(GXY_ENOMEM, "charge-block table bound exceeded");
+  const size_t tb = tp.tab.size() * sizeof(int64_t), gb = tp.groups.size() * sizeof(GGroup);
+  const size_t need = (tb + gb + 255) & ~(size_t)255;
+  if (ctx->arena_cur + need > ctx->arena_bytes) {
+    // grow: wait for copies from the old arena before releasing it
+    if (ctx->arena) {
+      GXY_HIP(hipStreamSynchronize(s));
+      GXY_HIP(hipHostFree(ctx->arena));
+    }
+    const size_t nb = std::max(2 * ctx->arena_bytes, ctx->arena_cur + need + (64 << 20));
+    ctx->arena = nullptr;
+    GXY_HIP(hipHostMalloc(&ctx->arena, nb, hipHostMallocDefault));
+    ctx->arena_bytes = nb;
+    ctx->arena_cur = 0;
+  }
+  char *h = (char *)ctx->arena + ctx->arena_cur;
+  memcpy(h, tp.tab.data(), tb);
+  memcpy(h + tb, tp.groups.data(), gb);
+  if (tb) GXY_HIP(hipMemcpyAsync(d_tab, h, tb, hipMemcpyHostToDevice, s));
+  if (gb) GXY_HIP(hipMemcpyAsync(d_grp, h + tb, gb, hipMemcpyHostToDevice, s));
+  ctx->arena_cur += need;
+}
+
+// After the last part of a step: the arena may be reused once this event
+// has completed.
+static void proj_stage_done(gxy_ctx *ctx, hipStream_t s) {
+  if (!ctx->arena_ev) GXY_HIP(hipEventCreateWithFlags(&ctx->arena_ev, hipEventDisableTiming));
+  GXY_HIP(hipEventRecord(ctx->arena_ev, s));
+  ctx->arena_pending = true;
+}
+
+static void proj_stage_begin(gxy_ctx *ctx) {
+  if (ctx->arena_pending) GXY_HIP(hipEventSynchronize(ctx->arena_ev));
+  ctx->arena_pending = false;
+  ctx->arena_cur = 0;
 }
 
 static void run_launch(const Launch &L, const GGroup *d_grp, const int64_t *d_tab,
@@ -992,53 +1040,76 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
         }
       }
     } else {
-      // charge-block launches for every chunk; tables built and uploaded once
-      StepLegs SL{Dh, Dv, Dn, mod, lh, lv, new_lh};
-      TablePlan tp;
+      // charge-block launches. The tables of each (chunk, tensor pair) are
+      // built on host threads; each part is uploaded at its own place in the
+      // step's table area and launched as soon as it is ready, so the host
+      // builds the next part while the device runs the previous one.
+      proj_stage_begin(ctx);
+      const StepLegs SL{Dh, Dv, Dn, mod, lh, lv, new_lh};
       const QSet s0{0};
-      struct ChunkPlan {
-        int a0, ac;
-        Launch x0, y00, t0;
-        Launch y0k[2], tk[2], xk[2], yk0[2];
+      struct Part {
+        int a0 = 0, ac = 0, k = -1;  // k = -1: pure tensor; else impurity k
+        TablePlan tp;
+        Launch x, y, t, x2, y2;      // impurity: y = (T, T_X), x2/y2 = (T_X, T)
       };
-      std::vector<ChunkPlan> cps;
-      for (int a0 = 0; a0 < Dn; a0 += ac_max) {
-        ChunkPlan cp;
-        cp.a0 = a0;
-        cp.ac = std::min(ac_max, Dn - a0);
-        const int a1 = a0 + cp.ac;
-        cp.x0 = plan_proj_x(SL, a0, a1, s0, tp);
-        cp.y00 = plan_proj_y(SL, a0, a1, s0, s0, tp);
-        cp.t0 = plan_proj_t(SL, a0, a1, s0, tp);
-        for (int k = 0; k < nimp; ++k) {
-          cp.y0k[k] = plan_proj_y(SL, a0, a1, s0, imp_set[k], tp);
-          cp.tk[k] = plan_proj_t(SL, a0, a1, imp_set[k], tp);
-          cp.xk[k] = plan_proj_x(SL, a0, a1, imp_set[k], tp);
-          cp.yk0[k] = plan_proj_y(SL, a0, a1, imp_set[k], s0, tp);
+      std::vector<std::unique_ptr<Part>> parts;
+      for (int a0 = 0; a0 < Dn; a0 += ac_max)
+        for (int k = -1; k < nimp; ++k) {
+          auto pt = std::make_unique<Part>();
+          pt->a0 = a0;
+          pt->ac = std::min(ac_max, Dn - a0);
+          pt->k = k;
+          parts.push_back(std::move(pt));
         }
-        cps.push_back(cp);
+      std::vector<std::future<void>> built;
+      for (auto &up : parts) {
+        Part *pt = up.get();
+        built.push_back(std::async(std::launch::async, [pt, &SL, &s0, &imp_set]() {
+          const int a1 = pt->a0 + pt->ac;
+          if (pt->k < 0) {
+            pt->x = plan_proj_x(SL, pt->a0, a1, s0, pt->tp);
+            pt->y = plan_proj_y(SL, pt->a0, a1, s0, s0, pt->tp);
+            pt->t = plan_proj_t(SL, pt->a0, a1, s0, pt->tp);
+          } else {
+            const QSet &sk = imp_set[pt->k];
+            pt->y = plan_proj_y(SL, pt->a0, a1, s0, sk, pt->tp);
+            pt->t = plan_proj_t(SL, pt->a0, a1, sk, pt->tp);
+            pt->x2 = plan_proj_x(SL, pt->a0, a1, sk, pt->tp);
+            pt->y2 = plan_proj_y(SL, pt->a0, a1, sk, s0, pt->tp);
+          }
+        }));
       }
-      upload_plan(ctx, 1, tp, b.tab_proj, pl.tab_proj, b.grp_proj, pl.grp_proj, s);
       const int64_t nTn = (int64_t)Dn * Dn * Dv * Dv;
       launch_fill(b.Tn, nTn, 0.0, s);
       for (int k = 0; k < nimp; ++k) launch_fill(b.TXn[k], nTn, 0.0, s);
-      auto hot_gy = [&](const Launch &L, const double *Xp, const double *Bp) {
-        hot_begin(ctx, s, L.flops, 0.0);
-        run_launch(L, b.grp_proj, b.tab_proj, Xp, Bp, b.Y, 1.0, 0.0, s);
-        hot_end(ctx, s);
-      };
-      for (const ChunkPlan &cp : cps) {
-        run_launch(cp.x0, b.grp_proj, b.tab_proj, b.P, b.T, b.X, 1.0, 0.0, s);
-        hot_gy(cp.y00, b.X, b.T2);
-        run_launch(cp.t0, b.grp_proj, b.tab_proj, b.Y, b.P, b.Tn, 1.0, 0.0, s);
-        for (int k = 0; k < nimp; ++k) {
-          hot_gy(cp.y0k[k], b.X, b.TX2[k]);
-          run_launch(cp.tk[k], b.grp_proj, b.tab_proj, b.Y, b.P, b.TXn[k], 0.5, 0.0, s);
-          run_launch(cp.xk[k], b.grp_proj, b.tab_proj, b.P, b.TX[k], b.XI, 1.0, 0.0, s);
-          hot_gy(cp.yk0[k], b.XI, b.T2);
-          run_launch(cp.tk[k], b.grp_proj, b.tab_proj, b.Y, b.P, b.TXn[k], 0.5, 1.0, s);
+      int64_t tab_cur = 0, grp_cur = 0;
+      for (size_t i = 0; i < parts.size(); ++i) {
+        built[i].get();
+        Part &pt = *parts[i];
+        int64_t *dt = b.tab_proj + tab_cur;
+        GGroup *dg = b.grp_proj + grp_cur;
+        upload_part(ctx, pt.tp, dt, pl.tab_proj - tab_cur, dg, pl.grp_proj - grp_cur, s);
+        tab_cur += (int64_t)pt.tp.tab.size();
+        grp_cur += (int64_t)pt.tp.groups.size();
+        auto gy = [&](const Launch &L, const double *Xp, const double *Bp) {
+          hot_begin(ctx, s, L.flops, 0.0);
+          run_launch(L, dg, dt, Xp, Bp, b.Y, 1.0, 0.0, s);
+          hot_end(ctx, s);
+        };
+        if (pt.k < 0) {
+          run_launch(pt.x, dg, dt, b.P, b.T, b.X, 1.0, 0.0, s);
+          gy(pt.y, b.X, b.T2);
+          run_launch(pt.t, dg, dt, b.Y, b.P, b.Tn, 1.0, 0.0, s);
+        } else {
+          const int k = pt.k;
+          gy(pt.y, b.X, b.TX2[k]);
+          run_launch(pt.t, dg, dt, b.Y, b.P, b.TXn[k], 0.5, 0.0, s);
+          run_launch(pt.x2, dg, dt, b.P, b.TX[k], b.XI, 1.0, 0.0, s);
+          gy(pt.y2, b.XI, b.T2);
+          run_launch(pt.t, dg, dt, b.Y, b.P, b.TXn[k], 0.5, 1.0, s);
         }
       }
+      proj_stage_done(ctx, s);
     }
     tm.end(4);
     tm.begin();
@@ -1173,6 +1244,8 @@ gxy_status gxy_destroy(gxy_ctx *ctx) {
   if (ctx->ws && ctx->ws_owned) (void)hipFree(ctx->ws);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  if (ctx->arena_ev) (void)hipEventDestroy(ctx->arena_ev);
+  if (ctx->arena) (void)hipHostFree(ctx->arena);
   for (int j = 0; j < 3; ++j) {
     if (ctx->stage_ev[j]) (void)hipEventDestroy(ctx->stage_ev[j]);
     if (ctx->stage[j]) (void)hipHostFree(ctx->stage[j]);

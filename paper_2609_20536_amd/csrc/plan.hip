@@ -219,6 +219,16 @@ Launch plan_proj_x(const StepLegs &S, int a0, int a1, const QSet &sA, TablePlan 
   std::map<int, std::vector<PI>> rows;
   for (int l2 = 0; l2 < Dh; ++l2)
     for (int a = a0; a < a1; ++a) rows[qnorm(S.ln[a] - S.lh[l2], mod)].push_back(PI(a, l2));
+  // columns (r1, u, i) keyed by kc = q_r1 + q_u - q_i; group c takes the
+  // columns with c - kc in sA
+  std::map<int, std::pair<std::vector<int64_t>, std::vector<int64_t>>> cols;
+  for (int r1 = 0; r1 < Dh; ++r1)
+    for (int u = 0; u < Dv; ++u)
+      for (int i = 0; i < Dv; ++i) {
+        auto &c = cols[qnorm(S.lh[r1] + S.lv[u] - S.lv[i], mod)];
+        c.first.push_back((int64_t)r1 * Dv * Dv + (int64_t)u * Dv + i);
+        c.second.push_back((int64_t)r1 * Dv * Dh * Dv + (int64_t)u * Dh * Dv + i);
+      }
   std::vector<GSpec> gs;
   for (const auto &kv : rows) {
     const int c = kv.first;
@@ -233,14 +243,12 @@ Launch plan_proj_x(const StepLegs &S, int a0, int a1, const QSet &sA, TablePlan 
         ac.push_back((int64_t)l1 * Dh * Dn);
         br.push_back((int64_t)l1 * Dh * Dv * Dv);
       }
-    // columns (r1, u, i) with c + q_i - q_r1 - q_u in sA
-    for (int r1 = 0; r1 < Dh; ++r1)
-      for (int u = 0; u < Dv; ++u)
-        for (int i = 0; i < Dv; ++i)
-          if (in_set(qnorm(c + S.lv[i] - S.lh[r1] - S.lv[u], mod), sA)) {
-            bc.push_back((int64_t)r1 * Dv * Dv + (int64_t)u * Dv + i);
-            cc.push_back((int64_t)r1 * Dv * Dh * Dv + (int64_t)u * Dh * Dv + i);
-          }
+    for (int sv : sA) {
+      auto ic = cols.find(qnorm(c - sv, mod));
+      if (ic == cols.end()) continue;
+      bc.insert(bc.end(), ic->second.first.begin(), ic->second.first.end());
+      cc.insert(cc.end(), ic->second.second.begin(), ic->second.second.end());
+    }
     GSpec g;
     g.M = (int32_t)ar.size();
     g.N = (int32_t)bc.size();
@@ -314,17 +322,26 @@ Launch plan_proj_t(const StepLegs &S, int a0, int a1, const QSet &sY, TablePlan 
   const int64_t W = (int64_t)Dh * Dv, per_a = W * W;
   const auto bs = leg_buckets(S.ln, mod);
   const PairBuckets ks = pair_buckets(S.lh, S.lh, 1, 1, mod);  // q_r1 + q_r2
+  // rows (a, u, d) keyed by w = q_a - q_u + q_d; group sigma takes the rows
+  // with w - sigma in sY
+  std::map<int, std::pair<std::vector<int64_t>, std::vector<int64_t>>> rows;
+  for (int a = a0; a < a1; ++a)
+    for (int u = 0; u < Dv; ++u)
+      for (int d = 0; d < Dv; ++d) {
+        auto &r = rows[qnorm(S.ln[a] - S.lv[u] + S.lv[d], mod)];
+        r.first.push_back((int64_t)(a - a0) * per_a + (int64_t)u * W + d);
+        r.second.push_back((int64_t)a * Dn * Dv * Dv + (int64_t)u * Dv + d);
+      }
   std::vector<GSpec> gs;
   for (const auto &kv : bs) {
     const int sigma = kv.first;
     std::vector<int64_t> ar, ac, br, bc, cr, cc;
-    for (int a = a0; a < a1; ++a)
-      for (int u = 0; u < Dv; ++u)
-        for (int d = 0; d < Dv; ++d)
-          if (in_set(qnorm(S.ln[a] - S.lv[u] + S.lv[d] - sigma, mod), sY)) {
-            ar.push_back((int64_t)(a - a0) * per_a + (int64_t)u * W + d);
-            cr.push_back((int64_t)a * Dn * Dv * Dv + (int64_t)u * Dv + d);
-          }
+    for (int sv : sY) {
+      auto ir = rows.find(qnorm(sigma + sv, mod));
+      if (ir == rows.end()) continue;
+      ar.insert(ar.end(), ir->second.first.begin(), ir->second.first.end());
+      cr.insert(cr.end(), ir->second.second.begin(), ir->second.second.end());
+    }
     auto ik = ks.find(sigma);
     if (ik != ks.end())
       for (const PI &p : ik->second) {

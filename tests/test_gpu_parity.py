@@ -5,10 +5,15 @@ oracle runs (Dcut >= 48, 40 steps) against stored values written by
 tests/golden/make_golden.py, which calls only the oracle.
 
 Tolerance: |d ln Z/V| <= 1e-12 and per-step |d ln c_n| <= 1e-11 for FP64.
-Where the truncated flow itself amplifies rounding (the oracle's own result
-moves by more than 1e-12 under a 1-ulp change of its input; see
-test_conditioning_spread_of_single_point), ln Z/V is compared at ten times
-that measured spread and the steps before the amplification at 1e-11.
+Two kinds of points are only determined to a looser level by FP64 at all:
+* the truncated flow amplifies rounding (the oracle's own result moves by
+  more than 1e-12 under a 1-ulp change of its input; see
+  test_conditioning_spread_of_single_point): ln Z/V is compared at ten times
+  that measured spread (stored per golden run as "spread");
+* a cut falls inside a (nearly) degenerate multiplet (|cut gap| < 1e-10 at
+  some step): which member or which direction of a near-degenerate pair is
+  kept is fixed only to eps ||E|| / gap by any FP64 eigensolver, so ln Z/V is
+  compared at TIE_CUT_LNZ_TOL and per-step values only before that step.
 """
 
 import glob
@@ -35,6 +40,13 @@ def ctx():
     c.close()
 
 
+TIE_CUT_LNZ_TOL = 1e-10
+
+
+def _tie_level(cut_gaps):
+    return any(abs(g) < 1e-10 for g in cut_gaps)
+
+
 def _defined_steps(cut_gaps, cap):
     """Steps whose per-step values are unique: those before the first cut
     that falls inside an (exactly) degenerate multiplet (|gap| < 1e-10), where
@@ -49,6 +61,8 @@ def _defined_steps(cut_gaps, cap):
 
 def _compare(g, r, lnz_tol=1e-12, step_tol=1e-11, nsteps_exact=None, m_tol=1e-11):
     assert g.status == 0
+    if _tie_level([s.cut_gap for s in r.steps if s.truncated]):
+        lnz_tol = max(lnz_tol, TIE_CUT_LNZ_TOL)
     assert abs(g.lnz_per_site - r.lnz_per_site) <= lnz_tol, (g.lnz_per_site, r.lnz_per_site)
     cap = len(r.steps) if nsteps_exact is None else nsteps_exact
     n = _defined_steps([s.cut_gap if s.truncated else 1.0 for s in r.steps], cap)
@@ -167,6 +181,8 @@ def test_golden_runs(ctx, path):
     g = ctx.run(pt)
     assert g.status == 0
     tol = max(1e-12, 10 * gd.get("spread", 0.0))
+    if _tie_level(gd["cut_gap"]):
+        tol = max(tol, TIE_CUT_LNZ_TOL)
     assert abs(g.lnz_per_site - gd["lnz_per_site"]) <= tol
     for k in range(_defined_steps(gd["cut_gap"], 10)):
         assert abs(g.steps[k]["lnc"] - gd["lnc"][k]) <= 1e-11, k
