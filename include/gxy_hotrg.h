@@ -48,11 +48,17 @@ typedef enum {
   GXY_EPARTIAL = 6       /* batch: at least one run failed (see per-run)    */
 } gxy_status;
 
+/* Arithmetic of the projection contractions (the D^7 work of eq.
+ * renormalizedT and the impurity placements). Tensors stay FP64 in memory;
+ * the environments (eq. hosvd), their eigendecompositions, t_n, the norms
+ * and the log-norm accumulation are FP64 in every form. */
 typedef enum {
-  GXY_PREC_FP64 = 0,     /* all contractions in FP64 MFMA                   */
-  GXY_PREC_FP32 = 1,     /* contractions in FP32 MFMA, FP32 accumulation    */
-  GXY_PREC_BF16X3 = 2    /* contractions as hi*hi + hi*lo + lo*hi BF16 MFMA
-                            with FP32 accumulation                          */
+  GXY_PREC_FP64 = 0,     /* FP64 MFMA                                       */
+  GXY_PREC_FP32 = 1,     /* operands rounded to FP32, FP32 MFMA, FP32
+                            accumulation                                    */
+  GXY_PREC_BF16X3 = 2    /* operands rounded to FP32, split x = hi + lo into
+                            bfloat16 terms, hi*hi + hi*lo + lo*hi by BF16
+                            MFMA with FP32 accumulation                     */
 } gxy_precision;
 
 enum { GXY_IMP_COS1 = 1u, GXY_IMP_COS2 = 2u };
@@ -68,8 +74,10 @@ typedef struct {
   int32_t nsteps;       /* coarse-graining steps, 0..62 (lattice 2^nsteps sites) */
   int32_t nquad;        /* quadrature points for t_n, > 2 nmax              */
   uint32_t impurities;  /* GXY_IMP_* bitmask                                 */
-  int32_t prec;         /* gxy_precision of the contractions                 */
-  int32_t fp64_steps;   /* mixed precision: the first fp64_steps steps in FP64 */
+  int32_t prec;         /* gxy_precision of the projection contractions      */
+  int32_t fp64_steps;   /* precision schedule: steps 1..fp64_steps contract in
+                           FP64, later steps in prec (>= 0; step n enters
+                           ln Z / N with weight 2^-n)                         */
 } gxy_point;
 
 typedef struct {

@@ -23,6 +23,14 @@ gxy_status gxy_test_gemm_f64(gxy_ctx *ctx, int32_t M, int32_t N, int32_t K,
                              const double *A, int32_t a_trans, const double *B,
                              int32_t b_trans, double *C);
 
+/* The same product in one of the contraction forms (gxy_precision): FP64;
+ * FP32 (operands rounded to FP32, FP32 accumulation); BF16X3 (operands
+ * rounded to FP32 and split into bfloat16 hi + lo, hi*hi + hi*lo + lo*hi,
+ * FP32 accumulation). Operands and C are FP64 in memory in every form. */
+gxy_status gxy_test_gemm(gxy_ctx *ctx, int32_t prec, int32_t M, int32_t N, int32_t K,
+                         const double *A, int32_t a_trans, const double *B,
+                         int32_t b_trans, double *C);
+
 /* Eigendecomposition of one symmetric n x n matrix (row-major) with the
  * batched block-Jacobi solver used for the environment matrices (Ch. 2,
  * eq. hosvd). w[n] receives the eigenvalues, V[n x n] (row-major) the
@@ -36,6 +44,14 @@ gxy_status gxy_test_eigh(gxy_ctx *ctx, int32_t n, const double *A, double *w,
  * lane l (accumulator initially zero). */
 gxy_status gxy_test_mfma_layout(gxy_ctx *ctx, const double *a, const double *b,
                                 double *out);
+
+/* Register layout of the FP32-accumulating matrix-core instructions used by
+ * the reduced-precision contractions: kind 0 = 16x16x4 FP32 (a[64], b[64],
+ * one value per lane), kind 1 = 16x16x32 BF16 (a[512], b[512], eight values
+ * per lane, rounded to bfloat16 on the device). out[4 l + r] = accumulator
+ * register r of lane l. */
+gxy_status gxy_test_mfma_layout32(gxy_ctx *ctx, int32_t kind, const float *a,
+                                  const float *b, float *out);
 
 #ifdef __cplusplus
 }

@@ -341,8 +341,9 @@ static void proj_stage_begin(gxy_ctx *ctx) {
 
 static void run_launch(const Launch &L, const GGroup *d_grp, const int64_t *d_tab,
                        const double *A, const double *B, double *C, double alpha, double beta,
-                       hipStream_t s) {
+                       hipStream_t s, int prec = GXY_PREC_FP64) {
   GroupedGemm g{};
+  g.prec = prec;
   g.ngroups = L.ngroups;
   g.total_tiles = L.total_tiles;
   g.tile = L.tile;
@@ -355,7 +356,7 @@ static void run_launch(const Launch &L, const GGroup *d_grp, const int64_t *d_ta
   g.beta = beta;
   g.kfast_a = L.kfast_a;
   g.nfast_b = L.nfast_b;
-  grouped_gemm_f64(g, s);
+  grouped_gemm(g, s);
 }
 
 static void ensure_workspace(gxy_ctx *ctx, size_t need) {
@@ -420,7 +421,9 @@ static void validate(const gxy_point &p) {
   if (p.nsteps < 0 || p.nsteps > 62) fail(GXY_EINVAL, "nsteps must lie in [0, 62]");
   if (p.nquad <= 2 * p.nmax) fail(GXY_EINVAL, "nquad must exceed 2*nmax");
   if (p.impurities & ~3u) fail(GXY_EINVAL, "unknown impurity bits");
-  if (p.prec != GXY_PREC_FP64) fail(GXY_EUNSUPPORTED, "only FP64 contractions in this build");
+  if (p.prec != GXY_PREC_FP64 && p.prec != GXY_PREC_FP32 && p.prec != GXY_PREC_BF16X3)
+    fail(GXY_EINVAL, "unknown contraction precision");
+  if (p.fp64_steps < 0) fail(GXY_EINVAL, "fp64_steps must be >= 0");
 }
 
 static int sym_of(const gxy_point &p) {
@@ -487,7 +490,7 @@ static void env_gemms(const double *T, int Dh, int Dv, double *envA, double *env
   g.cn = imap1(1);
   g.kfast_a = false;
   g.nfast_b = true;
-  gemm_f64(g, s);
+  gemm(g, s);
   // bottom tensor: rows (x, i), reduction (other leg, d)
   if (!right) {
     g.am = imap2(Dv, sl, Dv);      // (l2, i)
@@ -501,7 +504,7 @@ static void env_gemms(const double *T, int Dh, int Dv, double *envA, double *env
   g.C = envB;
   g.kfast_a = true;
   g.nfast_b = false;
-  gemm_f64(g, s);
+  gemm(g, s);
   // E[(x1,x2),(x1',x2')] = sum_{i,i'} envA[x1,i,x1',i'] envB[x2,i,x2',i']
   GemmDesc e{};
   e.M = Dh * Dh;
@@ -522,13 +525,14 @@ static void env_gemms(const double *T, int Dh, int Dv, double *envA, double *env
   e.cn = imap2(Dh, nf, 1);
   e.kfast_a = true;
   e.nfast_b = false;
-  gemm_f64(e, s);
+  gemm(e, s);
 }
 
 // X[a][r1][u][l2][i] = sum_{l1} P[(l1,l2), a0 + a] A[l1][r1][u][i], a < ac
 static void proj_x(const double *P, int Dh, int Dv, int Dn, int a0, int ac,
-                   const double *A, double *X, hipStream_t s) {
+                   const double *A, double *X, hipStream_t s, int prec) {
   GemmDesc g{};
+  g.prec = prec;
   g.M = ac * Dh;
   g.N = Dh * Dv * Dv;
   g.K = Dh;
@@ -546,13 +550,14 @@ static void proj_x(const double *P, int Dh, int Dv, int Dn, int a0, int ac,
   g.beta = 0.0;
   g.kfast_a = false;
   g.nfast_b = true;
-  gemm_f64(g, s);
+  gemm(g, s);
 }
 
 // Y[(a,r1,u),(r2,d)] = sum_{(l2,i)} X[(a,r1,u),(l2,i)] B2[(l2,i),(r2,d)]
 static void proj_y(const double *X, const double *B2, int Dh, int Dv, int ac,
-                   double *Y, hipStream_t s) {
+                   double *Y, hipStream_t s, int prec) {
   GemmDesc g{};
+  g.prec = prec;
   const int32_t W = Dh * Dv;
   g.M = ac * W;
   g.N = W;
@@ -570,13 +575,14 @@ static void proj_y(const double *X, const double *B2, int Dh, int Dv, int ac,
   g.beta = 0.0;
   g.kfast_a = true;
   g.nfast_b = true;
-  gemm_f64(g, s);
+  gemm(g, s);
 }
 
 // T'[a0+a][b][u][d] = alpha sum_{r1,r2} Y[a][r1][u][r2][d] P[(r1,r2), b] + beta T'
 static void proj_t(const double *Y, const double *P, int Dh, int Dv, int Dn, int a0,
-                   int ac, double alpha, double beta, double *Tout, hipStream_t s) {
+                   int ac, double alpha, double beta, double *Tout, hipStream_t s, int prec) {
   GemmDesc g{};
+  g.prec = prec;
   g.M = ac * Dv * Dv;
   g.N = Dn;
   g.K = Dh * Dh;
@@ -594,7 +600,7 @@ static void proj_t(const double *Y, const double *P, int Dh, int Dv, int Dn, int
   g.beta = beta;
   g.kfast_a = false;
   g.nfast_b = true;
-  gemm_f64(g, s);
+  gemm(g, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -925,6 +931,9 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
     const int64_t nf = (int64_t)Dh * Dh;
     const int Dn = sd.dn;
     gxy_step_info info{};
+    // precision schedule: the first fp64_steps steps contract in FP64, the
+    // rest in the requested form (environments and eigensolves always FP64)
+    const int sprec = (n <= p.fp64_steps) ? (int)GXY_PREC_FP64 : (int)p.prec;
     std::vector<int> new_lh;
     if (nf <= p.dcut) {
       launch_identity(b.P, (int)nf, s);
@@ -1022,21 +1031,21 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
       // algorithmic work of the dense product: 2 M N K flops, A + B + C bytes
       const double M = (double)ac * W;
       hot_begin(ctx, s, 2.0 * M * W * W, 8.0 * (M * W + W * W + M * W));
-      proj_y(Xp, Bp, Dh, Dv, ac, b.Y, s);
+      proj_y(Xp, Bp, Dh, Dv, ac, b.Y, s, sprec);
       hot_end(ctx, s);
     };
     if (sym == SYM_NONE) {
       for (int a0 = 0; a0 < Dn; a0 += ac_max) {
         const int ac = std::min(ac_max, Dn - a0);
-        proj_x(b.P, Dh, Dv, Dn, a0, ac, b.T, b.X, s);
+        proj_x(b.P, Dh, Dv, Dn, a0, ac, b.T, b.X, s, sprec);
         hot_y(b.X, b.T2, ac);
-        proj_t(b.Y, b.P, Dh, Dv, Dn, a0, ac, 1.0, 0.0, b.Tn, s);
+        proj_t(b.Y, b.P, Dh, Dv, Dn, a0, ac, 1.0, 0.0, b.Tn, s, sprec);
         for (int k = 0; k < nimp; ++k) {
           hot_y(b.X, b.TX2[k], ac);
-          proj_t(b.Y, b.P, Dh, Dv, Dn, a0, ac, 0.5, 0.0, b.TXn[k], s);
-          proj_x(b.P, Dh, Dv, Dn, a0, ac, b.TX[k], b.XI, s);
+          proj_t(b.Y, b.P, Dh, Dv, Dn, a0, ac, 0.5, 0.0, b.TXn[k], s, sprec);
+          proj_x(b.P, Dh, Dv, Dn, a0, ac, b.TX[k], b.XI, s, sprec);
           hot_y(b.XI, b.T2, ac);
-          proj_t(b.Y, b.P, Dh, Dv, Dn, a0, ac, 0.5, 1.0, b.TXn[k], s);
+          proj_t(b.Y, b.P, Dh, Dv, Dn, a0, ac, 0.5, 1.0, b.TXn[k], s, sprec);
         }
       }
     } else {
@@ -1093,20 +1102,20 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
         grp_cur += (int64_t)pt.tp.groups.size();
         auto gy = [&](const Launch &L, const double *Xp, const double *Bp) {
           hot_begin(ctx, s, L.flops, 0.0);
-          run_launch(L, dg, dt, Xp, Bp, b.Y, 1.0, 0.0, s);
+          run_launch(L, dg, dt, Xp, Bp, b.Y, 1.0, 0.0, s, sprec);
           hot_end(ctx, s);
         };
         if (pt.k < 0) {
-          run_launch(pt.x, dg, dt, b.P, b.T, b.X, 1.0, 0.0, s);
+          run_launch(pt.x, dg, dt, b.P, b.T, b.X, 1.0, 0.0,  s, sprec);
           gy(pt.y, b.X, b.T2);
-          run_launch(pt.t, dg, dt, b.Y, b.P, b.Tn, 1.0, 0.0, s);
+          run_launch(pt.t, dg, dt, b.Y, b.P, b.Tn, 1.0, 0.0,  s, sprec);
         } else {
           const int k = pt.k;
           gy(pt.y, b.X, b.TX2[k]);
-          run_launch(pt.t, dg, dt, b.Y, b.P, b.TXn[k], 0.5, 0.0, s);
-          run_launch(pt.x2, dg, dt, b.P, b.TX[k], b.XI, 1.0, 0.0, s);
+          run_launch(pt.t, dg, dt, b.Y, b.P, b.TXn[k], 0.5, 0.0,  s, sprec);
+          run_launch(pt.x2, dg, dt, b.P, b.TX[k], b.XI, 1.0, 0.0,  s, sprec);
           gy(pt.y2, b.XI, b.T2);
-          run_launch(pt.t, dg, dt, b.Y, b.P, b.TXn[k], 0.5, 1.0, s);
+          run_launch(pt.t, dg, dt, b.Y, b.P, b.TXn[k], 0.5, 1.0,  s, sprec);
         }
       }
       proj_stage_done(ctx, s);
@@ -1424,9 +1433,11 @@ gxy_status gxy_phase_times(gxy_ctx *ctx, double *ms6) {
 
 extern "C" {
 
-gxy_status gxy_test_gemm_f64(gxy_ctx *ctx, int32_t M, int32_t N, int32_t K, const double *A,
-                             int32_t a_trans, const double *B, int32_t b_trans, double *Cout) {
+gxy_status gxy_test_gemm(gxy_ctx *ctx, int32_t prec, int32_t M, int32_t N, int32_t K,
+                         const double *A, int32_t a_trans, const double *B, int32_t b_trans,
+                         double *Cout) {
   if (!ctx || M <= 0 || N <= 0 || K < 0 || !A || !B || !Cout) return GXY_EINVAL;
+  if (prec < GXY_PREC_FP64 || prec > GXY_PREC_BF16X3) return GXY_EINVAL;
   GXY_API_BEGIN
   GXY_HIP(hipSetDevice(ctx->device));
   const size_t na = (size_t)M * K, nb = (size_t)K * N, nc = (size_t)M * N;
@@ -1452,11 +1463,17 @@ gxy_status gxy_test_gemm_f64(gxy_ctx *ctx, int32_t M, int32_t N, int32_t K, cons
   g.nfast_b = !b_trans;
   g.cm = gxy::imap1(N);
   g.cn = gxy::imap1(1);
-  gxy::gemm_f64(g, s);
+  g.prec = prec;
+  gxy::gemm(g, s);
   GXY_HIP(hipMemcpyAsync(Cout, dC, nc * sizeof(double), hipMemcpyDeviceToHost, s));
   GXY_HIP(hipStreamSynchronize(s));
   return GXY_OK;
   GXY_API_END(ctx)
+}
+
+gxy_status gxy_test_gemm_f64(gxy_ctx *ctx, int32_t M, int32_t N, int32_t K, const double *A,
+                             int32_t a_trans, const double *B, int32_t b_trans, double *Cout) {
+  return gxy_test_gemm(ctx, GXY_PREC_FP64, M, N, K, A, a_trans, B, b_trans, Cout);
 }
 
 gxy_status gxy_test_eigh(gxy_ctx *ctx, int32_t n, const double *A, double *w, double *V,
@@ -1528,6 +1545,24 @@ gxy_status gxy_test_mfma_layout(gxy_ctx *ctx, const double *a, const double *b, 
   GXY_HIP(hipMemcpyAsync(db, b, 64 * sizeof(double), hipMemcpyHostToDevice, s));
   gxy::launch_mfma_probe(da, db, dout, s);
   GXY_HIP(hipMemcpyAsync(out, dout, 256 * sizeof(double), hipMemcpyDeviceToHost, s));
+  GXY_HIP(hipStreamSynchronize(s));
+  return GXY_OK;
+  GXY_API_END(ctx)
+}
+
+gxy_status gxy_test_mfma_layout32(gxy_ctx *ctx, int32_t kind, const float *a, const float *b,
+                                  float *out) {
+  if (!ctx || !a || !b || !out || kind < 0 || kind > 1) return GXY_EINVAL;
+  GXY_API_BEGIN
+  GXY_HIP(hipSetDevice(ctx->device));
+  const int n = kind == 0 ? 64 : 512;
+  gxy::ensure_workspace(ctx, sizeof(float) * (2 * n + 256) + 256);
+  float *da = (float *)ctx->ws, *db = da + n, *dout = db + n;
+  hipStream_t s = ctx->stream;
+  GXY_HIP(hipMemcpyAsync(da, a, n * sizeof(float), hipMemcpyHostToDevice, s));
+  GXY_HIP(hipMemcpyAsync(db, b, n * sizeof(float), hipMemcpyHostToDevice, s));
+  gxy::launch_mfma_probe32(kind, da, db, dout, s);
+  GXY_HIP(hipMemcpyAsync(out, dout, 256 * sizeof(float), hipMemcpyDeviceToHost, s));
   GXY_HIP(hipStreamSynchronize(s));
   return GXY_OK;
   GXY_API_END(ctx)

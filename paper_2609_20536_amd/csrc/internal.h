@@ -64,7 +64,7 @@ __host__ __device__ inline int64_t imap_off(const IdxMap &m, int32_t x) {
   return d0 * m.s0 + d1 * m.s1 + d2 * m.s2 + d3 * m.s3;
 }
 
-// C(m, n) = alpha * sum_k A(m, k) B(k, n) + beta * C(m, n), FP64 MFMA.
+// C(m, n) = alpha * sum_k A(m, k) B(k, n) + beta * C(m, n) on the matrix cores.
 // Element (m, k) of A is A[imap_off(am, m) + imap_off(ak, k)], and so on.
 // kfast_a: neighbouring k of A are adjacent in memory (else neighbouring m);
 // nfast_b: neighbouring n of B are adjacent (else neighbouring k).
@@ -78,9 +78,10 @@ struct GemmDesc {
   IdxMap cm, cn;
   double alpha, beta;
   bool kfast_a, nfast_b;
+  int32_t prec;  // gxy_precision of the matrix-core arithmetic (0 = FP64)
 };
 
-void gemm_f64(const GemmDesc &g, hipStream_t s);
+void gemm(const GemmDesc &g, hipStream_t s);
 
 // One dense sub-product of a grouped launch: M x N x K, tiles numbered from
 // tile_start; ar/ac/br/bc/cr/cc index the shared int64 offset table.
@@ -90,9 +91,10 @@ struct GGroup {
 };
 
 // Many independent sub-products in one launch (charge blocks). Tile size is
-// tile x tile (64 or 128) for every group of the launch.
+// tile x tile (64 or 128) for every group of the launch. prec (gxy_precision)
+// selects what the matrix cores compute in; operands and C stay FP64.
 struct GroupedGemm {
-  int32_t ngroups, total_tiles, tile;
+  int32_t ngroups, total_tiles, tile, prec;
   const GGroup *groups;
   const int64_t *tab;
   const double *A, *B;
@@ -101,9 +103,12 @@ struct GroupedGemm {
   bool kfast_a, nfast_b;
 };
 
-void grouped_gemm_f64(const GroupedGemm &g, hipStream_t s);
+void grouped_gemm(const GroupedGemm &g, hipStream_t s);
 // raw register layout of one v_mfma_f64_16x16x4_f64 (a[64], b[64] -> out[256])
 void launch_mfma_probe(const double *a, const double *b, double *out, hipStream_t s);
+// kind 0: f32 16x16x4 (a[64], b[64]); kind 1: bf16 16x16x32 (a[512], b[512])
+void launch_mfma_probe32(int kind, const float *a, const float *b, float *out,
+                         hipStream_t s);
 
 // --------------------------------------------------------------------------
 // coefficients and initial tensors (FP64)

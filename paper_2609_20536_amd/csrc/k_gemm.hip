@@ -1,4 +1,4 @@
-// FP64 MFMA GEMMs with index-fused operands for the HOTRG contractions.
+// Matrix-core GEMMs with index-fused operands for the HOTRG contractions.
 //
 // Every contraction of a HOTRG step (the environment Gram matrices of the
 // mode unfoldings of M, eq. hosvd, and the three factors of the projection
@@ -12,12 +12,24 @@
 //    (the charge blocks left by the U(1) or Z2 symmetry of the site tensor),
 //    each with its own row / reduction / column offset tables.
 //
-// Tiling for CDNA4: 256 threads = 4 wave64s in a 2x2 arrangement; each wave
-// owns a (BM/2) x (BN/2) sub-tile made of 16x16 blocks computed with
-// v_mfma_f64_16x16x4_f64. A and B tiles (BK = 16) are staged through LDS with
-// the next tile's global loads in flight while the current one is consumed.
-// Workgroups are renumbered so that each XCD (own L2) works on a contiguous
-// band of output tiles.
+// Three arithmetic forms share the tile body. Operands and results are FP64
+// in memory in every form; the form decides what the matrix cores see:
+//  * F64:    v_mfma_f64_16x16x4_f64, FP64 accumulation;
+//  * F32:    operands rounded to FP32, v_mfma_f32_16x16x4_f32, FP32
+//            accumulation;
+//  * BF16X3: operands rounded to FP32 and split x = hi + lo into two bfloat16
+//            terms; hi*hi + hi*lo + lo*hi by v_mfma_f32_16x16x32_bf16, FP32
+//            accumulation (the lo*lo term is dropped).
+//
+// Tiling for CDNA4: a workgroup owns a BM x BN output tile; its waves (wave64)
+// form a WGM x WGN grid, each wave owning (BM/WGM) x (BN/WGN) built from 16x16
+// matrix-core blocks. A and B k-slices are staged through double-buffered LDS
+// (one barrier per k-slice). The index tables of the operands are gathered
+// one k-slice ahead of the data, so a data load never waits for its own
+// address. Workgroups are renumbered so that each XCD (own L2) works on a
+// contiguous band of output tiles.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace gxy {
@@ -25,9 +37,10 @@ namespace gxy {
 namespace {
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 
-constexpr int kThreads = 256;
-constexpr int kBK = 16;
+enum { kF64 = GXY_PREC_FP64, kF32 = GXY_PREC_FP32, kB3 = GXY_PREC_BF16X3 };
 
 struct AffineAddr {
   const IdxMap *am, *ak, *bk, *bn, *cm, *cn;
@@ -49,29 +62,64 @@ struct TableAddr {
   __device__ int64_t c_n(int n) const { return cc[n]; }
 };
 
+// LDS staging of one operand slice (two stages). F64/F32: [k][m] rows with a
+// small pad. BF16X3: [k/8][m] cells of 8 consecutive k (one 16-byte read per
+// lane feeds a 16x16x32 instruction), hi and lo terms in separate arrays.
+template <int BK, int BX, int PREC>
+struct Stage {
+  double v[2][BK][BX + 2];
+  __device__ void put(int st, int k, int x, double a) { v[st][k][x] = a; }
+};
+template <int BK, int BX>
+struct Stage<BK, BX, kF32> {
+  float v[2][BK][BX + 4];
+  __device__ void put(int st, int k, int x, double a) { v[st][k][x] = (float)a; }
+};
+template <int BK, int BX>
+struct Stage<BK, BX, kB3> {
+  bf16x8_t hi[2][BK / 8][BX + 1];
+  bf16x8_t lo[2][BK / 8][BX + 1];
+  __device__ void put(int st, int k, int x, double a) {
+    const float f = (float)a;
+    const __bf16 h = (__bf16)f;
+    const __bf16 l = (__bf16)(f - (float)h);
+    ((__bf16 *)&hi[st][k >> 3][x])[k & 7] = h;
+    ((__bf16 *)&lo[st][k >> 3][x])[k & 7] = l;
+  }
+};
+
+template <int PREC> struct Acc { typedef float4_t type; };
+template <> struct Acc<kF64> { typedef double4_t type; };
+
 // One BM x BN output tile of C(m, n) = alpha sum_k A(m, k) B(k, n) + beta C.
-template <int BM, int BN, bool KFA, bool NFB, class Addr>
+template <int BM, int BN, int BK, int WGM, int WGN, bool KFA, bool NFB, int PREC, class Addr>
 __device__ __forceinline__ void gemm_tile(const Addr &ad, int M, int N, int K, int m0, int n0,
                                           const double *__restrict__ A,
                                           const double *__restrict__ B, double *C,
-                                          double alpha, double beta,
-                                          double (*As)[BM + 1], double (*Bs)[BN + 1]) {
-  constexpr int WM = BM / 2, WN = BN / 2;
+                                          double alpha, double beta, Stage<BK, BM, PREC> &sa,
+                                          Stage<BK, BN, PREC> &sb) {
+  constexpr int NT = 64 * WGM * WGN;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
   constexpr int FM = WM / 16, FN = WN / 16;
-  constexpr int A_PER = BM * kBK / kThreads;
-  constexpr int B_PER = BN * kBK / kThreads;
+  constexpr int A_PER = BM * BK / NT, B_PER = BN * BK / NT;
+  static_assert(NT % BK == 0 && NT % BM == 0 && NT % BN == 0, "thread mapping");
+  static_assert(BM % (NT / BK) == 0 && BN % (NT / BK) == 0, "thread mapping");
+  static_assert(BK % (NT / BM) == 0 && BK % (NT / BN) == 0, "thread mapping");
+  static_assert(FM >= 1 && FN >= 1 && WM % 16 == 0 && WN % 16 == 0, "wave tile");
+  static_assert(PREC != kB3 || BK % 32 == 0, "bf16 k-step");
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm0 = (wave >> 1) * WM;
-  const int wn0 = (wave & 1) * WN;
+  const int wm0 = (wave / WGN) * WM;
+  const int wn0 = (wave % WGN) * WN;
 
+  // fixed (row / column) parts of the operand offsets of this thread
   int64_t a_fixed[KFA ? A_PER : 1];
   bool a_ok[KFA ? A_PER : 1];
   if (KFA) {
 #pragma unroll
     for (int p = 0; p < A_PER; ++p) {
-      const int m = m0 + tid / kBK + 16 * p;
+      const int m = m0 + tid / BK + (NT / BK) * p;
       a_ok[p] = m < M;
       a_fixed[p] = a_ok[p] ? ad.a_m(m) : 0;
     }
@@ -89,109 +137,160 @@ __device__ __forceinline__ void gemm_tile(const Addr &ad, int M, int N, int K, i
   } else {
 #pragma unroll
     for (int p = 0; p < B_PER; ++p) {
-      const int n = n0 + tid / kBK + 16 * p;
+      const int n = n0 + tid / BK + (NT / BK) * p;
       b_ok[p] = n < N;
       b_fixed[p] = b_ok[p] ? ad.b_n(n) : 0;
     }
   }
 
-  double ra[A_PER], rb[B_PER];
-  auto load_tiles = [&](int k0) {
+  // reduction-index parts, gathered one slice ahead (-1 = beyond K)
+  constexpr int TA = KFA ? 1 : A_PER, TB = NFB ? B_PER : 1;
+  int64_t ta[TA], tb[TB];
+  auto load_offsets = [&](int k0) {
     if (KFA) {
-      const int k = k0 + tid % kBK;
-      const bool kok = k < K;
-      const int64_t ko = kok ? ad.a_k(k) : 0;
-#pragma unroll
-      for (int p = 0; p < A_PER; ++p) ra[p] = (kok && a_ok[p]) ? A[a_fixed[p] + ko] : 0.0;
+      const int k = k0 + tid % BK;
+      ta[0] = k < K ? ad.a_k(k) : -1;
     } else {
-      constexpr int KSTEP = kThreads / BM;
 #pragma unroll
       for (int p = 0; p < A_PER; ++p) {
-        const int k = k0 + tid / BM + KSTEP * p;
-        ra[p] = (k < K && a_ok[0]) ? A[a_fixed[0] + ad.a_k(k)] : 0.0;
+        const int k = k0 + tid / BM + (NT / BM) * p;
+        ta[p] = k < K ? ad.a_k(k) : -1;
       }
     }
     if (NFB) {
-      constexpr int KSTEP = kThreads / BN;
 #pragma unroll
       for (int p = 0; p < B_PER; ++p) {
-        const int k = k0 + tid / BN + KSTEP * p;
-        rb[p] = (k < K && b_ok[0]) ? B[ad.b_k(k) + b_fixed[0]] : 0.0;
+        const int k = k0 + tid / BN + (NT / BN) * p;
+        tb[p] = k < K ? ad.b_k(k) : -1;
       }
     } else {
-      const int k = k0 + tid % kBK;
-      const bool kok = k < K;
-      const int64_t ko = kok ? ad.b_k(k) : 0;
-#pragma unroll
-      for (int p = 0; p < B_PER; ++p) rb[p] = (kok && b_ok[p]) ? B[ko + b_fixed[p]] : 0.0;
+      const int k = k0 + tid % BK;
+      tb[0] = k < K ? ad.b_k(k) : -1;
     }
   };
-  auto store_tiles = [&]() {
+  double ra[A_PER], rb[B_PER];
+  auto load_data = [&]() {
     if (KFA) {
 #pragma unroll
-      for (int p = 0; p < A_PER; ++p) As[tid % kBK][tid / kBK + 16 * p] = ra[p];
+      for (int p = 0; p < A_PER; ++p)
+        ra[p] = (ta[0] >= 0 && a_ok[p]) ? A[a_fixed[p] + ta[0]] : 0.0;
     } else {
-      constexpr int KSTEP = kThreads / BM;
 #pragma unroll
-      for (int p = 0; p < A_PER; ++p) As[tid / BM + KSTEP * p][tid % BM] = ra[p];
+      for (int p = 0; p < A_PER; ++p)
+        ra[p] = (ta[p] >= 0 && a_ok[0]) ? A[a_fixed[0] + ta[p]] : 0.0;
     }
     if (NFB) {
-      constexpr int KSTEP = kThreads / BN;
 #pragma unroll
-      for (int p = 0; p < B_PER; ++p) Bs[tid / BN + KSTEP * p][tid % BN] = rb[p];
+      for (int p = 0; p < B_PER; ++p)
+        rb[p] = (tb[p] >= 0 && b_ok[0]) ? B[tb[p] + b_fixed[0]] : 0.0;
     } else {
 #pragma unroll
-      for (int p = 0; p < B_PER; ++p) Bs[tid % kBK][tid / kBK + 16 * p] = rb[p];
+      for (int p = 0; p < B_PER; ++p)
+        rb[p] = (tb[0] >= 0 && b_ok[p]) ? B[tb[0] + b_fixed[p]] : 0.0;
+    }
+  };
+  auto store = [&](int st) {
+#pragma unroll
+    for (int p = 0; p < A_PER; ++p) {
+      if (KFA)
+        sa.put(st, tid % BK, tid / BK + (NT / BK) * p, ra[p]);
+      else
+        sa.put(st, tid / BM + (NT / BM) * p, tid % BM, ra[p]);
+    }
+#pragma unroll
+    for (int p = 0; p < B_PER; ++p) {
+      if (NFB)
+        sb.put(st, tid / BN + (NT / BN) * p, tid % BN, rb[p]);
+      else
+        sb.put(st, tid % BK, tid / BK + (NT / BK) * p, rb[p]);
     }
   };
 
-  double4_t acc[FM][FN];
+  typedef typename Acc<PREC>::type acc_t;
+  acc_t acc[FM][FN];
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < FN; ++j) acc[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < FN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
-  const int ktiles = (K + kBK - 1) / kBK;
-  if (ktiles > 0) load_tiles(0);
+  const int ktiles = (K + BK - 1) / BK;
+  const int li = lane & 15;
+  const int lk = lane >> 4;
+  if (ktiles > 0) {
+    load_offsets(0);
+    load_data();
+    store(0);
+    load_offsets(BK);
+  }
+  __syncthreads();
   for (int kt = 0; kt < ktiles; ++kt) {
-    store_tiles();
-    __syncthreads();
-    if (kt + 1 < ktiles) load_tiles((kt + 1) * kBK);
-    const int li = lane & 15;
-    const int lk = lane >> 4;
-#pragma unroll
-    for (int kk = 0; kk < kBK; kk += 4) {
-      double fa[FM], fb[FN];
-#pragma unroll
-      for (int i = 0; i < FM; ++i) fa[i] = As[kk + lk][wm0 + 16 * i + li];
-#pragma unroll
-      for (int j = 0; j < FN; ++j) fb[j] = Bs[kk + lk][wn0 + 16 * j + li];
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
+    const int st = kt & 1;
+    if (kt + 1 < ktiles) {
+      load_data();
+      load_offsets((kt + 2) * BK);
     }
+    if constexpr (PREC == kB3) {
+#pragma unroll
+      for (int kk = 0; kk < BK / 8; kk += 4) {
+        bf16x8_t ah[FM], al[FM], bh[FN], bl[FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i) {
+          ah[i] = sa.hi[st][kk + lk][wm0 + 16 * i + li];
+          al[i] = sa.lo[st][kk + lk][wm0 + 16 * i + li];
+        }
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          bh[j] = sb.hi[st][kk + lk][wn0 + 16 * j + li];
+          bl[j] = sb.lo[st][kk + lk][wn0 + 16 * j + li];
+        }
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+          }
+      }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        typedef typename std::remove_reference<decltype(sa.v[0][0][0])>::type op_t;
+        op_t fa[FM], fb[FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i) fa[i] = sa.v[st][kk + lk][wm0 + 16 * i + li];
+#pragma unroll
+        for (int j = 0; j < FN; ++j) fb[j] = sb.v[st][kk + lk][wn0 + 16 * j + li];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+            if constexpr (PREC == kF64)
+              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
+            else
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i], fb[j], acc[i][j], 0, 0, 0);
+          }
+      }
+    }
+    if (kt + 1 < ktiles) store(st ^ 1);
     __syncthreads();
   }
 
-  // the f64 16x16x4 accumulator of lane l holds rows l/16 + 4r (r = 0..3) of
-  // column l%16
-  const int cr = lane >> 4;
-  const int cc = lane & 15;
+  // Accumulator register r of lane l holds column l%16 and row l/16 + 4r
+  // (FP64 instruction) or 4(l/16) + r (FP32-accumulating instructions).
 #pragma unroll
   for (int j = 0; j < FN; ++j) {
-    const int n = n0 + wn0 + 16 * j + cc;
+    const int n = n0 + wn0 + 16 * j + li;
     if (n >= N) continue;
     const int64_t noff = ad.c_n(n);
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm0 + 16 * i + cr + 4 * r;
+        const int m = m0 + wm0 + 16 * i + (PREC == kF64 ? lk + 4 * r : 4 * lk + r);
         if (m >= M) continue;
         double *dst = C + ad.c_m(m) + noff;
-        const double v = alpha * acc[i][j][r];
+        const double v = alpha * (double)acc[i][j][r];
         *dst = (beta == 0.0) ? v : v + beta * (*dst);
       }
     }
@@ -202,10 +301,10 @@ __device__ __forceinline__ int xcd_remap(int pid, int total) {
   return ((total & 7) == 0) ? (pid & 7) * (total >> 3) + (pid >> 3) : pid;
 }
 
-template <int BM, int BN, bool KFA, bool NFB>
-__global__ __launch_bounds__(kThreads) void gemm_f64_kernel(GemmDesc g) {
-  __shared__ double As[kBK][BM + 1];
-  __shared__ double Bs[kBK][BN + 1];
+template <int BM, int BN, int BK, int WGM, int WGN, bool KFA, bool NFB, int PREC>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(GemmDesc g) {
+  __shared__ Stage<BK, BM, PREC> sa;
+  __shared__ Stage<BK, BN, PREC> sb;
   const int tiles_m = (g.M + BM - 1) / BM;
   const int tiles_n = (g.N + BN - 1) / BN;
   const int total = tiles_m * tiles_n;
@@ -218,14 +317,14 @@ __global__ __launch_bounds__(kThreads) void gemm_f64_kernel(GemmDesc g) {
   const int tm = first_m + (pid % in_group) % gsize;
   const int tn = (pid % in_group) / gsize;
   AffineAddr ad{&g.am, &g.ak, &g.bk, &g.bn, &g.cm, &g.cn};
-  gemm_tile<BM, BN, KFA, NFB>(ad, g.M, g.N, g.K, tm * BM, tn * BN, g.A, g.B, g.C, g.alpha,
-                              g.beta, As, Bs);
+  gemm_tile<BM, BN, BK, WGM, WGN, KFA, NFB, PREC>(ad, g.M, g.N, g.K, tm * BM, tn * BN, g.A, g.B,
+                                                  g.C, g.alpha, g.beta, sa, sb);
 }
 
-template <int BM, int BN, bool KFA, bool NFB>
-__global__ __launch_bounds__(kThreads) void ggemm_f64_kernel(GroupedGemm g) {
-  __shared__ double As[kBK][BM + 1];
-  __shared__ double Bs[kBK][BN + 1];
+template <int BM, int BN, int BK, int WGM, int WGN, bool KFA, bool NFB, int PREC>
+__global__ __launch_bounds__(64 * WGM * WGN) void ggemm_kernel(GroupedGemm g) {
+  __shared__ Stage<BK, BM, PREC> sa;
+  __shared__ Stage<BK, BN, PREC> sb;
   const int t = xcd_remap(blockIdx.x, g.total_tiles);
   // group of tile t: last group whose tile_start <= t
   int lo = 0, hi = g.ngroups - 1;
@@ -242,37 +341,64 @@ __global__ __launch_bounds__(kThreads) void ggemm_f64_kernel(GroupedGemm g) {
   const int tm = local / tiles_n, tn = local % tiles_n;
   TableAddr ad{g.tab + G.ar, g.tab + G.ac, g.tab + G.br, g.tab + G.bc, g.tab + G.cr,
                g.tab + G.cc};
-  gemm_tile<BM, BN, KFA, NFB>(ad, G.M, G.N, G.K, tm * BM, tn * BN, g.A, g.B, g.C, g.alpha,
-                              g.beta, As, Bs);
+  gemm_tile<BM, BN, BK, WGM, WGN, KFA, NFB, PREC>(ad, G.M, G.N, G.K, tm * BM, tn * BN, g.A, g.B,
+                                                  g.C, g.alpha, g.beta, sa, sb);
 }
 
-template <int BM, int BN>
+template <int BM, int BN, int BK, int WGM, int WGN, int PREC>
 void launch_tile(const GemmDesc &g, hipStream_t s) {
   const int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
-  dim3 grid(tiles), block(kThreads);
+  dim3 grid(tiles), block(64 * WGM * WGN);
   if (g.kfast_a && g.nfast_b)
-    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, true, true>), grid, block, 0, s, g);
+    hipLaunchKernelGGL((gemm_kernel<BM, BN, BK, WGM, WGN, true, true, PREC>), grid, block, 0, s,
+                       g);
   else if (g.kfast_a)
-    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, true, false>), grid, block, 0, s, g);
+    hipLaunchKernelGGL((gemm_kernel<BM, BN, BK, WGM, WGN, true, false, PREC>), grid, block, 0, s,
+                       g);
   else if (g.nfast_b)
-    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, false, true>), grid, block, 0, s, g);
+    hipLaunchKernelGGL((gemm_kernel<BM, BN, BK, WGM, WGN, false, true, PREC>), grid, block, 0, s,
+                       g);
   else
-    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, false, false>), grid, block, 0, s, g);
+    hipLaunchKernelGGL((gemm_kernel<BM, BN, BK, WGM, WGN, false, false, PREC>), grid, block, 0,
+                       s, g);
   GXY_CHECK_LAUNCH();
 }
 
-template <int BM, int BN>
-void launch_grouped(const GroupedGemm &g, hipStream_t s) {
-  dim3 grid(g.total_tiles), block(kThreads);
-  if (g.kfast_a && g.nfast_b)
-    hipLaunchKernelGGL((ggemm_f64_kernel<BM, BN, true, true>), grid, block, 0, s, g);
-  else if (g.kfast_a)
-    hipLaunchKernelGGL((ggemm_f64_kernel<BM, BN, true, false>), grid, block, 0, s, g);
-  else if (g.nfast_b)
-    hipLaunchKernelGGL((ggemm_f64_kernel<BM, BN, false, true>), grid, block, 0, s, g);
+template <int PREC>
+void launch_tile_prec(const GemmDesc &g, hipStream_t s) {
+  constexpr int BK = PREC == kB3 ? 32 : 16;
+  const int64_t big = (int64_t)((g.M + 127) / 128) * ((g.N + 127) / 128);
+  if (g.K > 0 && big >= 512)
+    launch_tile<128, 128, BK, 4, 2, PREC>(g, s);
   else
-    hipLaunchKernelGGL((ggemm_f64_kernel<BM, BN, false, false>), grid, block, 0, s, g);
+    launch_tile<64, 64, BK, 2, 2, PREC>(g, s);
+}
+
+template <int BM, int BN, int BK, int WGM, int WGN, int PREC>
+void launch_grouped(const GroupedGemm &g, hipStream_t s) {
+  dim3 grid(g.total_tiles), block(64 * WGM * WGN);
+  if (g.kfast_a && g.nfast_b)
+    hipLaunchKernelGGL((ggemm_kernel<BM, BN, BK, WGM, WGN, true, true, PREC>), grid, block, 0, s,
+                       g);
+  else if (g.kfast_a)
+    hipLaunchKernelGGL((ggemm_kernel<BM, BN, BK, WGM, WGN, true, false, PREC>), grid, block, 0,
+                       s, g);
+  else if (g.nfast_b)
+    hipLaunchKernelGGL((ggemm_kernel<BM, BN, BK, WGM, WGN, false, true, PREC>), grid, block, 0,
+                       s, g);
+  else
+    hipLaunchKernelGGL((ggemm_kernel<BM, BN, BK, WGM, WGN, false, false, PREC>), grid, block, 0,
+                       s, g);
   GXY_CHECK_LAUNCH();
+}
+
+template <int PREC>
+void launch_grouped_prec(const GroupedGemm &g, hipStream_t s) {
+  constexpr int BK = PREC == kB3 ? 32 : 16;
+  if (g.tile == 128)
+    launch_grouped<128, 128, BK, 4, 2, PREC>(g, s);
+  else
+    launch_grouped<64, 64, BK, 2, 2, PREC>(g, s);
 }
 
 // One wave: lane l supplies a[l], b[l]; out[4 l + r] = result register r.
@@ -283,23 +409,53 @@ __global__ void mfma_probe_kernel(const double *a, const double *b, double *out)
   for (int r = 0; r < 4; ++r) out[4 * l + r] = acc[r];
 }
 
-}  // namespace
+typedef float float4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 
-void gemm_f64(const GemmDesc &g, hipStream_t s) {
-  if (g.M <= 0 || g.N <= 0) return;
-  const int64_t big = (int64_t)((g.M + 127) / 128) * ((g.N + 127) / 128);
-  if (g.K > 0 && big >= 512)
-    launch_tile<128, 128>(g, s);
-  else
-    launch_tile<64, 64>(g, s);
+// kind 0: v_mfma_f32_16x16x4_f32 with a[l], b[l];
+// kind 1: v_mfma_f32_16x16x32_bf16 with a[8 l + j], b[8 l + j] (j < 8) as bf16.
+__global__ void mfma_probe32_kernel(int kind, const float *a, const float *b, float *out) {
+  const int l = threadIdx.x;
+  float4_t acc = {0.f, 0.f, 0.f, 0.f};
+  if (kind == 0) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[l], b[l], acc, 0, 0, 0);
+  } else {
+    bf16x8_t av, bv;
+    for (int j = 0; j < 8; ++j) {
+      av[j] = (__bf16)a[8 * l + j];
+      bv[j] = (__bf16)b[8 * l + j];
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+  }
+  for (int r = 0; r < 4; ++r) out[4 * l + r] = acc[r];
 }
 
-void grouped_gemm_f64(const GroupedGemm &g, hipStream_t s) {
+}  // namespace
+
+void launch_mfma_probe32(int kind, const float *a, const float *b, float *out,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(mfma_probe32_kernel, dim3(1), dim3(64), 0, s, kind, a, b, out);
+  GXY_CHECK_LAUNCH();
+}
+
+void gemm(const GemmDesc &g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0) return;
+  switch (g.prec) {
+    case kF64: launch_tile_prec<kF64>(g, s); break;
+    case kF32: launch_tile_prec<kF32>(g, s); break;
+    case kB3: launch_tile_prec<kB3>(g, s); break;
+    default: fail(GXY_EUNSUPPORTED, "GEMM: unknown precision");
+  }
+}
+
+void grouped_gemm(const GroupedGemm &g, hipStream_t s) {
   if (g.ngroups <= 0 || g.total_tiles <= 0) return;
-  if (g.tile == 128)
-    launch_grouped<128, 128>(g, s);
-  else
-    launch_grouped<64, 64>(g, s);
+  switch (g.prec) {
+    case kF64: launch_grouped_prec<kF64>(g, s); break;
+    case kF32: launch_grouped_prec<kF32>(g, s); break;
+    case kB3: launch_grouped_prec<kB3>(g, s); break;
+    default: fail(GXY_EUNSUPPORTED, "grouped GEMM: unknown precision");
+  }
 }
 
 void launch_mfma_probe(const double *a, const double *b, double *out, hipStream_t s) {

@@ -80,9 +80,13 @@ def load_library(path: str = LIB_PATH):
         "gxy_hot_kernel_stats": [C.c_void_p, P(C.c_double), C.c_int32],
         "gxy_test_gemm_f64": [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, P(C.c_double),
                               C.c_int32, P(C.c_double), C.c_int32, P(C.c_double)],
+        "gxy_test_gemm": [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                          P(C.c_double), C.c_int32, P(C.c_double), C.c_int32, P(C.c_double)],
         "gxy_test_eigh": [C.c_void_p, C.c_int32, P(C.c_double), P(C.c_double),
                           P(C.c_double), P(C.c_int32)],
         "gxy_test_mfma_layout": [C.c_void_p, P(C.c_double), P(C.c_double), P(C.c_double)],
+        "gxy_test_mfma_layout32": [C.c_void_p, C.c_int32, P(C.c_float), P(C.c_float),
+                                   P(C.c_float)],
     }
     for name, args in sigs.items():
         f = getattr(lib, name)
@@ -250,8 +254,11 @@ class Context:
         return out
 
     # -- single-kernel checks (include/gxy_hotrg_testing.h) -------------------
-    def test_gemm(self, A, B, a_trans=False, b_trans=False):
-        """C = A @ B through the FP64 MFMA GEMM; A (M,K), B (K,N) as numpy."""
+    def test_gemm(self, A, B, a_trans=False, b_trans=False, prec=None):
+        """C = A @ B through the matrix-core GEMM; A (M,K), B (K,N) as numpy.
+
+        prec None calls the FP64 entry point; otherwise a gxy_precision value.
+        """
         import numpy as np
         M, K = A.shape
         K2, N = B.shape
@@ -261,8 +268,13 @@ class Context:
         out = np.empty((M, N))
         self._reserve_bytes(8 * (M * K + K * N + M * N) + 4096)
         dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))  # noqa: E731
-        self._check(self.lib.gxy_test_gemm_f64(self.handle, M, N, K, dp(Ah), int(a_trans),
-                                               dp(Bh), int(b_trans), dp(out)), self.handle)
+        if prec is None:
+            rc = self.lib.gxy_test_gemm_f64(self.handle, M, N, K, dp(Ah), int(a_trans),
+                                            dp(Bh), int(b_trans), dp(out))
+        else:
+            rc = self.lib.gxy_test_gemm(self.handle, int(prec), M, N, K, dp(Ah), int(a_trans),
+                                        dp(Bh), int(b_trans), dp(out))
+        self._check(rc, self.handle)
         return out
 
     def test_eigh(self, A):
@@ -298,6 +310,17 @@ class Context:
         out = (C.c_double * 4)()
         self._check(self.lib.gxy_hot_kernel_stats(self.handle, out, int(reset)), self.handle)
         return list(out)
+
+    def test_mfma_layout32(self, kind, a, b):
+        import numpy as np
+        a = np.ascontiguousarray(a, dtype=np.float32)
+        b = np.ascontiguousarray(b, dtype=np.float32)
+        out = np.empty(256, dtype=np.float32)
+        self._reserve_bytes(4 * (2 * 512 + 256) + 4096)
+        fp = lambda x: x.ctypes.data_as(C.POINTER(C.c_float))  # noqa: E731
+        self._check(self.lib.gxy_test_mfma_layout32(self.handle, int(kind), fp(a), fp(b),
+                                                    fp(out)), self.handle)
+        return out.reshape(64, 4)
 
     def phase_times(self):
         out = (C.c_double * 6)()

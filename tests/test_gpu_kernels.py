@@ -56,6 +56,98 @@ def test_gemm_exact_on_integers(ctx):
     assert np.array_equal(ctx.test_gemm(A, B), A @ B)
 
 
+def test_gemm_large_tile_path(ctx):
+    """Shapes with >= 512 output tiles of 128 x 128 take the 8-wave 128-tile kernel."""
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((3000, 40))
+    B = rng.standard_normal((40, 3001))
+    for at, bt in [(0, 0), (1, 1)]:
+        C = ctx.test_gemm(A, B, at, bt)
+        ref = A @ B
+        assert np.max(np.abs(C - ref)) <= 1e-13 * math.sqrt(40) * np.max(np.abs(ref) + 1)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_mfma_fp32_accumulating_register_layout(ctx, kind):
+    """FP32-output 16x16 instructions: acc r of lane l = D[4(l/16) + r][l%16].
+
+    kind 0 (FP32, 16x16x4): A[i][k] = a[i + 16k], B[k][j] = b[j + 16k].
+    kind 1 (BF16, 16x16x32): lane l holds row l%16 of A and column l%16 of B
+    with k = 8(l/16) + j for its eight values j (integers, exact in BF16).
+    """
+    rng = np.random.default_rng(4 + kind)
+    n = 64 if kind == 0 else 512
+    a = rng.integers(-4, 5, n).astype(np.float32)
+    b = rng.integers(-4, 5, n).astype(np.float32)
+    out = ctx.test_mfma_layout32(kind, a, b)
+    kdim = 4 if kind == 0 else 32
+    A = np.zeros((16, kdim))
+    B = np.zeros((kdim, 16))
+    for l in range(64):
+        if kind == 0:
+            A[l % 16, l // 16] = a[l]
+            B[l // 16, l % 16] = b[l]
+        else:
+            for j in range(8):
+                A[l % 16, 8 * (l // 16) + j] = a[8 * l + j]
+                B[8 * (l // 16) + j, l % 16] = b[8 * l + j]
+    D = A @ B
+    for l in range(64):
+        for r in range(4):
+            assert out[l, r] == D[4 * (l // 16) + r, l % 16]
+
+
+def _bf16_rne(x32):
+    """Round float32 values to bfloat16 (round to nearest even), as float32."""
+    u = x32.astype(np.float32).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
+    return r.view(np.float32)
+
+
+GEMM_PREC_SHAPES = [(37, 29, 13), (130, 70, 45), (257, 300, 129), (3000, 300, 40)]
+
+
+@pytest.mark.parametrize("M,N,K", GEMM_PREC_SHAPES)
+@pytest.mark.parametrize("at,bt", [(0, 0), (1, 1), (0, 1)])
+def test_gemm_fp32_form(ctx, M, N, K, at, bt):
+    """FP32 form = exact product of the FP32-rounded operands, up to FP32
+    accumulation (|err| <= 2 K u32 (|A32||B32|)), and measurably not FP64."""
+    rng = np.random.default_rng(M + 5 * N + 11 * K + at)
+    A = rng.standard_normal((M, K))
+    B = rng.standard_normal((K, N))
+    C = ctx.test_gemm(A, B, at, bt, prec=1)
+    A32 = A.astype(np.float32).astype(np.float64)
+    B32 = B.astype(np.float32).astype(np.float64)
+    ref = A32 @ B32
+    bound = 2.0 * K * 2.0 ** -24 * (np.abs(A32) @ np.abs(B32)) + 1e-300
+    assert np.all(np.abs(C - ref) <= bound)
+    assert np.max(np.abs(C - A @ B)) > 1e-12
+
+
+@pytest.mark.parametrize("M,N,K", GEMM_PREC_SHAPES)
+@pytest.mark.parametrize("at,bt", [(0, 0), (1, 1), (1, 0)])
+def test_gemm_bf16x3_form(ctx, M, N, K, at, bt):
+    """BF16X3 form = hi*hi + hi*lo + lo*hi of the bfloat16 split of the
+    FP32-rounded operands (products exact in FP32), up to FP32 accumulation;
+    against the FP64 product it is within the split's 2^-16 relative bound."""
+    rng = np.random.default_rng(3 * M + N + 7 * K + bt)
+    A = rng.standard_normal((M, K))
+    B = rng.standard_normal((K, N))
+    C = ctx.test_gemm(A, B, at, bt, prec=2)
+    def split(X):
+        f = X.astype(np.float32)
+        hi = _bf16_rne(f)
+        lo = _bf16_rne(f - hi)
+        return hi.astype(np.float64), lo.astype(np.float64)
+    ah, al = split(A)
+    bh, bl = split(B)
+    ref = ah @ bh + ah @ bl + al @ bh
+    absAB = np.abs(A) @ np.abs(B)
+    assert np.all(np.abs(C - ref) <= 4.0 * K * 2.0 ** -24 * absAB + 1e-300)
+    assert np.all(np.abs(C - A @ B) <= (2.0 ** -15 + 4.0 * K * 2.0 ** -24) * absAB + 1e-300)
+    assert np.max(np.abs(C - A @ B)) > 1e-12
+
+
 def _check_eig(A, w, V, tol=None):
     n = A.shape[0]
     if tol is None:
