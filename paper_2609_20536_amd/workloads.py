@@ -147,3 +147,47 @@ def observable_runs(beta: float, delta: float, dcut: int, nmax: int = 10,
         base.with_(h1=hc - dh, impurities=IMP_COS2),
         base.with_(h1=hc + dh, impurities=IMP_COS2),
     ]
+
+
+# ---------------------------------------------------------------------------
+# Learned surrogate: seeded initial weights and train/validation split.
+# ---------------------------------------------------------------------------
+
+MLP_SEED = 20536
+MLP_LAYERS = ((128, 2), (128, 128), (4, 128))   # (fan_out, fan_in) per layer
+MLP_NPARAM = sum(o * i + o for o, i in MLP_LAYERS)  # 17412
+
+
+def mlp_init_params(seed: int = MLP_SEED) -> List[float]:
+    """Xavier-uniform weights, zero biases, as one flat vector.
+
+    Layout: W1[128][2], b1[128], W2[128][128], b2[128], W3[4][128], b3[4]
+    (row-major). Weight w of a layer with limit a = sqrt(6 / (fan_in +
+    fan_out)) is (2u - 1) a with u = (z >> 11) 2^-53 from consecutive
+    SplitMix64 outputs z of one stream seeded with ``seed`` (weights of W1,
+    then W2, then W3; biases draw nothing).
+    """
+    import math
+    out: List[float] = []
+    s = seed
+    for fo, fi in MLP_LAYERS:
+        a = math.sqrt(6.0 / (fi + fo))
+        for _ in range(fo * fi):
+            s, z = splitmix64(s)
+            u = (z >> 11) * 2.0 ** -53
+            out.append((2.0 * u - 1.0) * a)
+        out.extend([0.0] * fo)
+    return out
+
+
+def mlp_split(n: int, seed: int = MLP_SEED, train_frac: float = 0.9):
+    """Seeded 90/10 split of n samples: Fisher-Yates with SplitMix64, the
+    first round(train_frac n) indices of the permutation train."""
+    perm = list(range(n))
+    s = seed
+    for i in range(n - 1, 0, -1):
+        s, z = splitmix64(s)
+        j = z % (i + 1)
+        perm[i], perm[j] = perm[j], perm[i]
+    ntr = int(round(train_frac * n))
+    return perm[:ntr], perm[ntr:]
