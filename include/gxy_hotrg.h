@@ -170,6 +170,72 @@ gxy_status gxy_phase_times(gxy_ctx *ctx, double *ms6);
  * reset != 0 clears the totals after reading. */
 gxy_status gxy_hot_kernel_stats(gxy_ctx *ctx, double *out4, int32_t reset);
 
+/* ------------------------------------------------------------------------
+ * Learned surrogate of the phase diagram (not in the thesis, which motivates
+ * cheaper scans of the (beta, Delta) plane in Ch. 3): a 2 -> 128 -> 128 -> 4
+ * multilayer perceptron, SiLU after both hidden layers, linear output,
+ * 17 412 FP32 parameters laid out W1[128][2], b1[128], W2[128][128], b2[128],
+ * W3[4][128], b3[4] (row-major, layer maps a -> W a + b). Inputs
+ * (beta, Delta); targets (f, C_v, chi, chi_n), the observables of Ch. 3
+ * (eqs. spech, susc). Training is full-batch Adam on the mean squared error
+ * of standardised targets, in FP32 on the device, reproducible bit for bit.
+ * A surrogate belongs to the context it was created on and uses its device;
+ * calls are ordered after the context stream's work and return when done.
+ * ---------------------------------------------------------------------- */
+typedef struct gxy_mlp gxy_mlp;
+
+typedef struct {
+  int32_t epochs;          /* Adam updates (full batch), >= 0                */
+  float lr, beta1, beta2, eps; /* Adam step size and moment constants       */
+  uint32_t log_targets;    /* bit c set: target column c enters as ln(y_c)   */
+  int32_t standardize;     /* 1: inputs and (transformed) targets are
+                              standardised with the training set's mean and
+                              population standard deviation; 0: used as is  */
+} gxy_train_cfg;
+
+typedef struct {
+  int32_t nbeta, ndelta;   /* candidate lattice, nbeta >= 3, ndelta >= 2     */
+  double beta_lo, beta_hi; /* beta_i = lo + i (hi - lo) / (nbeta - 1)       */
+  double delta_lo, delta_hi; /* likewise Delta_j                             */
+  uint64_t seed;           /* SplitMix64 stream of the jitter               */
+  double jitter;           /* 0..1: proposals move by jitter (2u - 1) / 2
+                              lattice spacings along beta                   */
+  int32_t cv_col, chi_col; /* target columns whose maxima are proposed      */
+} gxy_propose_cfg;
+
+/* New surrogate with Xavier-uniform weights drawn from the SplitMix64 stream
+ * seeded with seed (weights of W1, W2, W3 in order; u = (z >> 11) 2^-53,
+ * w = (2u - 1) sqrt(6 / (fan_in + fan_out))) and zero biases. */
+gxy_status gxy_mlp_create(gxy_ctx *ctx, uint64_t seed, gxy_mlp **out);
+gxy_status gxy_mlp_destroy(gxy_mlp *mlp);
+/* Copy the 17 412 parameters out (get) and/or in (set); either may be NULL. */
+gxy_status gxy_mlp_params(gxy_mlp *mlp, float *get, const float *set);
+/* Train from the current parameters with a fresh Adam state. x: n x 2
+ * (beta, Delta), y: n x 4 targets in physical units (row-major FP64);
+ * columns selected by log_targets must be > 0. loss_hist (optional,
+ * epochs floats): loss at the parameters before each update. The scaling
+ * found here is kept for gxy_mlp_predict / gxy_mlp_propose. */
+gxy_status gxy_mlp_train(gxy_mlp *mlp, const double *x, const double *y, int32_t n,
+                         const gxy_train_cfg *cfg, float *loss_hist);
+/* Loss and its gradient (17 412 floats, parameter layout) at the current
+ * parameters for data already in network units (x: n x 2, y: n x 4, FP32). */
+gxy_status gxy_mlp_grad(gxy_mlp *mlp, const float *x, const float *y, int32_t n,
+                        float *grad, float *loss);
+/* Predictions in physical units (n x 4, FP64) for raw (beta, Delta) rows;
+ * bf16 = 1 runs the 128 x 128 layer on BF16 matrix cores, 0 all-FP32. */
+gxy_status gxy_mlp_predict(gxy_mlp *mlp, const double *x, int32_t n, int32_t bf16,
+                           double *y);
+/* Scaling in use: out12 = x mean[2], y mean[4], x std[2], y std[4] (targets
+ * after the log transform); *log_mask = the transformed columns. */
+gxy_status gxy_mlp_scaling(gxy_mlp *mlp, double *out12, uint32_t *log_mask);
+/* Two refinement points per Delta_j of the lattice: at the predicted maxima
+ * along beta of columns cv_col and chi_col (BF16 inference). beta_delta
+ * receives 2 ndelta rows (beta, Delta): row 2j the cv_col maximum, row 2j+1
+ * the chi_col maximum. The first maximum wins ties; the vertex of the
+ * parabola through it and its two neighbours moves it by at most half a
+ * spacing; then the jitter is added and beta is clamped to the lattice. */
+gxy_status gxy_mlp_propose(gxy_mlp *mlp, const gxy_propose_cfg *cfg, double *beta_delta);
+
 #ifdef __cplusplus
 }
 #endif

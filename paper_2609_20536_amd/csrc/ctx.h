@@ -1,0 +1,67 @@
+// Library context shared by the run engine and the surrogate: device,
+// stream, workspace, per-run step logs, timing events and pinned staging.
+#pragma once
+
+#include <stdio.h>
+#include <stdlib.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "internal.h"
+
+namespace gxy {
+
+struct RunLog {
+  std::vector<gxy_step_info> steps;
+};
+
+}  // namespace gxy
+
+struct gxy_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  bool ws_owned = false;
+  std::string last_error;
+  std::vector<gxy::RunLog> logs;
+  double phase_ms[6] = {0, 0, 0, 0, 0, 0};
+  // per-launch events around the dominant contraction (the D^7 product)
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, double>> hot_launches;  // (event pair index, flops)
+  double hot_stats[4] = {0, 0, 0, 0};  // launches, ms, flops, bytes
+  bool hot_on = false;
+  void *pinned = nullptr;  // small host staging buffer
+  size_t pinned_bytes = 0;
+  // two pinned staging buffers for table uploads, each guarded by an event
+  void *stage[3] = {nullptr, nullptr, nullptr};
+  size_t stage_bytes[3] = {0, 0, 0};
+  hipEvent_t stage_ev[3] = {nullptr, nullptr, nullptr};
+  bool stage_used[3] = {false, false, false};
+  // pinned arena for the projection tables of one step
+  void *arena = nullptr;
+  size_t arena_bytes = 0, arena_cur = 0;
+  hipEvent_t arena_ev = nullptr;
+  bool arena_pending = false;
+};
+
+// Every C entry point runs its body inside these: library errors become
+// status codes and the message is kept for gxy_last_error.
+#define GXY_API_BEGIN try {
+#define GXY_API_END(ctx)                                         \
+  }                                                              \
+  catch (const Error &e) {                                       \
+    if (ctx) (ctx)->last_error = e.msg;                          \
+    if (getenv("GXY_LOG")) fprintf(stderr, "gxy: %s\n", e.msg.c_str()); \
+    return e.status;                                             \
+  }                                                              \
+  catch (const std::bad_alloc &) {                               \
+    if (ctx) (ctx)->last_error = "host allocation failed";       \
+    return GXY_ENOMEM;                                           \
+  }                                                              \
+  catch (...) {                                                  \
+    if (ctx) (ctx)->last_error = "unexpected host exception";    \
+    return GXY_EDEVICE;                                          \
+  }

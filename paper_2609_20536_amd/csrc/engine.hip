@@ -24,6 +24,7 @@
 #include <string>
 #include <vector>
 
+#include "ctx.h"
 #include "internal.h"
 #include "plan.h"
 
@@ -223,43 +224,7 @@ static size_t carve(const gxy_point &p, const Plan &pl, Carver &c, Buffers &b) {
   return c.off + 256;
 }
 
-// ---------------------------------------------------------------------------
-// context
-// ---------------------------------------------------------------------------
-
-struct RunLog {
-  std::vector<gxy_step_info> steps;
-};
-
 }  // namespace gxy
-
-struct gxy_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  void *ws = nullptr;
-  size_t ws_bytes = 0;
-  bool ws_owned = false;
-  std::string last_error;
-  std::vector<gxy::RunLog> logs;
-  double phase_ms[6] = {0, 0, 0, 0, 0, 0};
-  // per-launch events around the dominant contraction (the D^7 product)
-  std::vector<hipEvent_t> ev_pool;
-  std::vector<std::pair<int, double>> hot_launches;  // (event pair index, flops)
-  double hot_stats[4] = {0, 0, 0, 0};  // launches, ms, flops, bytes
-  bool hot_on = false;
-  void *pinned = nullptr;  // small host staging buffer
-  size_t pinned_bytes = 0;
-  // two pinned staging buffers for table uploads, each guarded by an event
-  void *stage[3] = {nullptr, nullptr, nullptr};
-  size_t stage_bytes[3] = {0, 0, 0};
-  hipEvent_t stage_ev[3] = {nullptr, nullptr, nullptr};
-  bool stage_used[3] = {false, false, false};
-  // pinned arena for the projection tables of one step
-  void *arena = nullptr;
-  size_t arena_bytes = 0, arena_cur = 0;
-  hipEvent_t arena_ev = nullptr;
-  bool arena_pending = false;
-};
 
 namespace gxy {
 
@@ -1210,22 +1175,6 @@ static size_t workspace_for(const gxy_point &p) {
 
 using gxy::Error;
 
-#define GXY_API_BEGIN try {
-#define GXY_API_END(ctx)                                         \
-  }                                                              \
-  catch (const Error &e) {                                       \
-    if (ctx) (ctx)->last_error = e.msg;                          \
-    if (getenv("GXY_LOG")) fprintf(stderr, "gxy: %s\n", e.msg.c_str()); \
-    return e.status;                                             \
-  }                                                              \
-  catch (const std::bad_alloc &) {                               \
-    if (ctx) (ctx)->last_error = "host allocation failed";       \
-    return GXY_ENOMEM;                                           \
-  }                                                              \
-  catch (...) {                                                  \
-    if (ctx) (ctx)->last_error = "unexpected host exception";    \
-    return GXY_EDEVICE;                                          \
-  }
 
 extern "C" {
 

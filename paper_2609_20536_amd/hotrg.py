@@ -53,6 +53,19 @@ class StepInfo(C.Structure):
 _lib = None
 
 
+class TrainCfg(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("lr", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float), ("log_targets", C.c_uint32),
+                ("standardize", C.c_int32)]
+
+
+class ProposeCfg(C.Structure):
+    _fields_ = [("nbeta", C.c_int32), ("ndelta", C.c_int32), ("beta_lo", C.c_double),
+                ("beta_hi", C.c_double), ("delta_lo", C.c_double), ("delta_hi", C.c_double),
+                ("seed", C.c_uint64), ("jitter", C.c_double), ("cv_col", C.c_int32),
+                ("chi_col", C.c_int32)]
+
+
 def load_library(path: str = LIB_PATH):
     """Load the HIP library; raises if it has not been built."""
     global _lib
@@ -77,6 +90,16 @@ def load_library(path: str = LIB_PATH):
                             P(C.c_double), P(C.c_double), C.c_double, C.c_double,
                             C.c_double, P(C.c_double)],
         "gxy_phase_times": [C.c_void_p, P(C.c_double)],
+        "gxy_mlp_create": [C.c_void_p, C.c_uint64, P(C.c_void_p)],
+        "gxy_mlp_destroy": [C.c_void_p],
+        "gxy_mlp_params": [C.c_void_p, P(C.c_float), P(C.c_float)],
+        "gxy_mlp_train": [C.c_void_p, P(C.c_double), P(C.c_double), C.c_int32, P(TrainCfg),
+                          P(C.c_float)],
+        "gxy_mlp_grad": [C.c_void_p, P(C.c_float), P(C.c_float), C.c_int32, P(C.c_float),
+                         P(C.c_float)],
+        "gxy_mlp_predict": [C.c_void_p, P(C.c_double), C.c_int32, C.c_int32, P(C.c_double)],
+        "gxy_mlp_scaling": [C.c_void_p, P(C.c_double), P(C.c_uint32)],
+        "gxy_mlp_propose": [C.c_void_p, P(ProposeCfg), P(C.c_double)],
         "gxy_hot_kernel_stats": [C.c_void_p, P(C.c_double), C.c_int32],
         "gxy_test_gemm_f64": [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, P(C.c_double),
                               C.c_int32, P(C.c_double), C.c_int32, P(C.c_double)],
@@ -326,3 +349,105 @@ class Context:
         out = (C.c_double * 6)()
         self._check(self.lib.gxy_phase_times(self.handle, out), self.handle)
         return list(out)
+
+
+NPARAM = 17412
+
+
+class Surrogate:
+    """The 2 -> 128 -> 128 -> 4 surrogate MLP on a context's device.
+
+    Thin marshalling over gxy_mlp_*: every computation (initialisation,
+    scaling, training, inference, proposals) runs in the library's kernels.
+    """
+
+    def __init__(self, ctx: "Context", seed: int = 20536):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        h = C.c_void_p()
+        ctx._check(self.lib.gxy_mlp_create(ctx.handle, C.c_uint64(seed), C.byref(h)),
+                   ctx.handle)
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.gxy_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, st):
+        self.ctx._check(st, self.ctx.handle)
+
+    @staticmethod
+    def _f(a):
+        return a.ctypes.data_as(C.POINTER(C.c_float))
+
+    @staticmethod
+    def _d(a):
+        return a.ctypes.data_as(C.POINTER(C.c_double))
+
+    def get_params(self):
+        import numpy as np
+        out = np.empty(NPARAM, dtype=np.float32)
+        self._chk(self.lib.gxy_mlp_params(self.handle, self._f(out), None))
+        return out
+
+    def set_params(self, theta):
+        import numpy as np
+        a = np.ascontiguousarray(theta, dtype=np.float32)
+        assert a.shape == (NPARAM,)
+        self._chk(self.lib.gxy_mlp_params(self.handle, None, self._f(a)))
+
+    def train(self, X, Y, epochs=5000, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+              log_targets=0b1100, standardize=True):
+        import numpy as np
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        Y = np.ascontiguousarray(Y, dtype=np.float64)
+        n = X.shape[0]
+        assert X.shape == (n, 2) and Y.shape == (n, 4)
+        cfg = TrainCfg(int(epochs), lr, beta1, beta2, eps, int(log_targets), int(standardize))
+        hist = np.empty(max(int(epochs), 1), dtype=np.float32)
+        self._chk(self.lib.gxy_mlp_train(self.handle, self._d(X), self._d(Y), n,
+                                         C.byref(cfg), self._f(hist)))
+        return hist[:int(epochs)]
+
+    def grad(self, Xs, Ys):
+        import numpy as np
+        Xs = np.ascontiguousarray(Xs, dtype=np.float32)
+        Ys = np.ascontiguousarray(Ys, dtype=np.float32)
+        n = Xs.shape[0]
+        g = np.empty(NPARAM, dtype=np.float32)
+        loss = np.empty(1, dtype=np.float32)
+        self._chk(self.lib.gxy_mlp_grad(self.handle, self._f(Xs), self._f(Ys), n,
+                                        self._f(g), self._f(loss)))
+        return float(loss[0]), g
+
+    def predict(self, X, bf16=False):
+        import numpy as np
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        n = X.shape[0]
+        y = np.empty((n, 4))
+        self._chk(self.lib.gxy_mlp_predict(self.handle, self._d(X), n, int(bool(bf16)),
+                                           self._d(y)))
+        return y
+
+    def scaling(self):
+        import numpy as np
+        out = np.empty(12)
+        mask = C.c_uint32()
+        self._chk(self.lib.gxy_mlp_scaling(self.handle, self._d(out), C.byref(mask)))
+        return out[0:2], out[6:8], out[2:6], out[8:12], int(mask.value)
+
+    def propose(self, nbeta=256, ndelta=256, beta_lo=0.5, beta_hi=1.5, delta_lo=0.0,
+                delta_hi=1.0, seed=20536, jitter=0.5, cv_col=1, chi_col=2):
+        import numpy as np
+        cfg = ProposeCfg(int(nbeta), int(ndelta), beta_lo, beta_hi, delta_lo, delta_hi,
+                         C.c_uint64(seed), jitter, int(cv_col), int(chi_col))
+        out = np.empty((2 * int(ndelta), 2))
+        self._chk(self.lib.gxy_mlp_propose(self.handle, C.byref(cfg), self._d(out)))
+        return out
