@@ -136,9 +136,33 @@ gxy_status gxy_initial_tensor(gxy_ctx *ctx, const gxy_point *pt, int32_t which,
 /* One synchronous HOTRG run. */
 gxy_status gxy_run(gxy_ctx *ctx, const gxy_point *pt, gxy_result *out);
 
-/* n runs; per-run status in out[i].status; GXY_EPARTIAL if any failed. */
+/* n independent runs (points of a (beta, Delta, h, h1) scan, any mix of
+ * Dcut, fields and precisions). With W > 1 workers (gxy_set_batch_workers,
+ * else the GXY_BATCH_WORKERS environment variable, else 4) the runs are
+ * taken longest first (cost ~ Dcut^7 x steps x placements) from a shared
+ * queue by W host threads, each driving its own worker context: own
+ * non-blocking stream, own device workspace (library-allocated, projection
+ * chunks of at most 4 GiB), the caller's autotuned tiles. Small-Dcut runs
+ * overlap the launch and host latency of the large ones. Results are in
+ * input order and identical, bit for bit, to gxy_run of each point. Per-run
+ * status in out[i].status (failed runs: NaN outputs); GXY_EPARTIAL if any
+ * run failed, GXY_EDEVICE (remaining runs not started) on a device error. */
 gxy_status gxy_run_batch(gxy_ctx *ctx, const gxy_point *pts, int32_t n,
                          gxy_result *out);
+
+/* Number of worker contexts gxy_run_batch uses (0 = default, at most 64). */
+gxy_status gxy_set_batch_workers(gxy_ctx *ctx, int32_t workers);
+
+/* Measure, for each Dcut in dcuts[0..n), the projection contractions with
+ * 64 x 64 and with 128 x 128 output tiles on the run templ (with that
+ * Dcut; its second run is timed, the first warms up) and keep the faster
+ * tile for later runs at that Dcut on this context (and its batch
+ * workers). tiles[i] (optional) receives the choice, ms[2 i], ms[2 i + 1]
+ * (optional) the summed time of the D^7 products for 64 and 128. The tile
+ * does not change any result: every output element is accumulated over
+ * the same k-slices in the same order. */
+gxy_status gxy_autotune(gxy_ctx *ctx, const gxy_point *templ, const int32_t *dcuts,
+                        int32_t n, int32_t *tiles, double *ms);
 
 /* Per-step diagnostics of run `run` of the last gxy_run (run = 0) or
  * gxy_run_batch; writes min(cap, steps) entries and the count to *count. */

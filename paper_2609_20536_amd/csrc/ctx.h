@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <stdlib.h>
 
+#include <map>
 #include <string>
 #include <utility>
 #include <vector>
@@ -45,6 +46,15 @@ struct gxy_ctx {
   size_t arena_bytes = 0, arena_cur = 0;
   hipEvent_t arena_ev = nullptr;
   bool arena_pending = false;
+  // projection tile per Dcut chosen by gxy_autotune (absent: by tile fill);
+  // force_tile (64 / 128) overrides both while the autotuner measures
+  std::map<int, int> tile_for_dcut;
+  int force_tile = 0;
+  bool hot_force = false;  // keep the contraction events on (autotuner)
+  // batched runs: worker contexts, each with its own stream and workspace
+  int batch_workers = 0;  // 0 = default
+  size_t chunk_bytes = 0;  // projection chunk bound (0: GXY_CHUNK_BYTES or 16 GiB)
+  std::vector<gxy_ctx *> children;
 };
 
 // Every C entry point runs its body inside these: library errors become

@@ -18,7 +18,11 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
+#include <cmath>
 #include <future>
+#include <mutex>
+#include <thread>
 #include <map>
 #include <memory>
 #include <string>
@@ -788,7 +792,8 @@ static SectorSolve solve_sectors(gxy_ctx *ctx, hipStream_t s, const double *E, i
 static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &log) {
   validate(p);
   const hipStream_t s = ctx->stream;
-  const size_t chunk_bytes = env_size("GXY_CHUNK_BYTES", (size_t)16 << 30);
+  const size_t chunk_bytes =
+      ctx->chunk_bytes ? ctx->chunk_bytes : env_size("GXY_CHUNK_BYTES", (size_t)16 << 30);
   const Plan pl = make_plan(p, chunk_bytes);
   Buffers b{};
   {
@@ -802,7 +807,7 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
   ensure_pinned(ctx, 1 << 20);
   Timer tm;
   tm.on = env_flag("GXY_TIMING");
-  ctx->hot_on = tm.on || env_flag("GXY_HOT_EVENTS");
+  ctx->hot_on = tm.on || ctx->hot_force || env_flag("GXY_HOT_EVENTS");
   ctx->hot_launches.clear();
   tm.s = s;
   tm.acc = ctx->phase_ms;
@@ -1019,7 +1024,12 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
       // step's table area and launched as soon as it is ready, so the host
       // builds the next part while the device runs the previous one.
       proj_stage_begin(ctx);
-      const StepLegs SL{Dh, Dv, Dn, mod, lh, lv, new_lh};
+      int proj_tile = ctx->force_tile;
+      if (!proj_tile) {
+        const auto it = ctx->tile_for_dcut.find(p.dcut);
+        if (it != ctx->tile_for_dcut.end()) proj_tile = it->second;
+      }
+      const StepLegs SL{Dh, Dv, Dn, mod, lh, lv, new_lh, proj_tile};
       const QSet s0{0};
       struct Part {
         int a0 = 0, ac = 0, k = -1;  // k = -1: pure tensor; else impurity k
@@ -1198,6 +1208,12 @@ gxy_status gxy_create(gxy_ctx **out, int device, void *hip_stream) {
 gxy_status gxy_destroy(gxy_ctx *ctx) {
   if (!ctx) return GXY_EINVAL;
   (void)hipSetDevice(ctx->device);
+  for (gxy_ctx *c : ctx->children) {
+    hipStream_t cs = c->stream;
+    gxy_destroy(c);
+    if (cs) (void)hipStreamDestroy(cs);
+  }
+  ctx->children.clear();
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   if (ctx->ws && ctx->ws_owned) (void)hipFree(ctx->ws);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
@@ -1277,35 +1293,164 @@ gxy_status gxy_run(gxy_ctx *ctx, const gxy_point *pt, gxy_result *out) {
 
 gxy_status gxy_run_batch(gxy_ctx *ctx, const gxy_point *pts, int32_t n, gxy_result *out) {
   if (!ctx || !pts || !out || n <= 0) return GXY_EINVAL;
-  bool any_fail = false;
   try {
     GXY_HIP(hipSetDevice(ctx->device));
   } catch (const Error &e) {
     ctx->last_error = e.msg;
     return e.status;
   }
-  ctx->logs.assign(n, gxy::RunLog{});
+  int W = ctx->batch_workers;
+  if (W <= 0) W = (int)gxy::env_size("GXY_BATCH_WORKERS", 4);
+  W = std::max(1, std::min(W, n));
+  std::vector<gxy::RunLog> logs(n);
   for (int i = 0; i < n; ++i) {
+    out[i] = gxy_result{};
+    out[i].fail_step = -1;
+  }
+  std::atomic<bool> dead{false};
+  std::mutex err_mu;
+  std::string last;
+  // one run on context c; a device error stops the whole batch
+  auto one = [&](gxy_ctx *c, int i) {
     gxy_result r{};
     r.fail_step = -1;
     try {
-      gxy::run_one(ctx, pts[i], r, ctx->logs[i]);
+      GXY_HIP(hipSetDevice(c->device));
+      gxy::run_one(c, pts[i], r, logs[i]);
     } catch (const Error &e) {
-      ctx->last_error = e.msg;
       r.status = e.status;
       r.lnz_per_site = r.m_cos1 = r.m_cos2 = NAN;
-      if (e.status == GXY_EDEVICE) {
-        out[i] = r;
-        for (int j = i + 1; j < n; ++j) {
-          out[j] = r;
-        }
-        return GXY_EDEVICE;
-      }
+      std::lock_guard<std::mutex> g(err_mu);
+      last = e.msg;
+      if (e.status == GXY_EDEVICE) dead = true;
+    } catch (...) {
+      r.status = GXY_EDEVICE;
+      r.lnz_per_site = r.m_cos1 = r.m_cos2 = NAN;
+      std::lock_guard<std::mutex> g(err_mu);
+      last = "unexpected host exception";
+      dead = true;
     }
     out[i] = r;
-    any_fail |= r.status != GXY_OK;
+  };
+  if (W == 1) {
+    for (int i = 0; i < n && !dead; ++i) one(ctx, i);
+  } else {
+    try {
+      // worker contexts: own non-blocking stream (default priority), the
+      // parent's tile table, ordered after the work already on its stream
+      while ((int)ctx->children.size() < W) {
+        hipStream_t cs = nullptr;
+        GXY_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        gxy_ctx *c = new gxy_ctx();
+        c->device = ctx->device;
+        c->stream = cs;
+        c->chunk_bytes = (size_t)4 << 30;   // smaller projection chunks per worker
+        ctx->children.push_back(c);
+      }
+      hipEvent_t ev = nullptr;
+      GXY_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      GXY_HIP(hipEventRecord(ev, ctx->stream));
+      for (int w = 0; w < W; ++w) {
+        ctx->children[w]->tile_for_dcut = ctx->tile_for_dcut;
+        ctx->children[w]->force_tile = ctx->force_tile;
+        GXY_HIP(hipStreamWaitEvent(ctx->children[w]->stream, ev, 0));
+      }
+      GXY_HIP(hipEventDestroy(ev));
+    } catch (const Error &e) {
+      ctx->last_error = e.msg;
+      return e.status;
+    }
+    // longest runs first (cost ~ Dcut^7 per placement, dense steps dearer)
+    std::vector<int> order(n);
+    std::vector<double> cost(n);
+    for (int i = 0; i < n; ++i) {
+      const gxy_point &p = pts[i];
+      const int nimp = ((p.impurities & 1) ? 1 : 0) + ((p.impurities & 2) ? 1 : 0);
+      const double D = std::max(1, std::min(p.dcut, 128));
+      cost[i] = std::pow(D, 7.0) * std::max(p.nsteps, 1) * (1 + 2 * nimp) *
+                ((p.h != 0.0) ? 16.0 : (p.h1 != 0.0 ? 2.0 : 1.0));
+      order[i] = i;
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return cost[a] > cost[b]; });
+    std::atomic<int> next{0};
+    std::vector<std::thread> th;
+    for (int w = 0; w < W; ++w)
+      th.emplace_back([&, w]() {
+        gxy_ctx *c = ctx->children[w];
+        for (;;) {
+          if (dead) return;
+          const int k = next++;
+          if (k >= n) return;
+          one(c, order[k]);
+        }
+      });
+    for (auto &t : th) t.join();
+    for (int w = 0; w < W; ++w) (void)hipStreamSynchronize(ctx->children[w]->stream);
   }
+  ctx->logs = std::move(logs);
+  bool any_fail = false;
+  for (int i = 0; i < n; ++i) {
+    if (dead && out[i].status == GXY_OK && out[i].nsteps_done == 0 && pts[i].nsteps > 0) {
+      out[i].status = GXY_EDEVICE;
+      out[i].lnz_per_site = out[i].m_cos1 = out[i].m_cos2 = NAN;
+    }
+    any_fail |= out[i].status != GXY_OK;
+  }
+  if (!last.empty()) ctx->last_error = last;
+  if (dead) return GXY_EDEVICE;
   return any_fail ? GXY_EPARTIAL : GXY_OK;
+}
+
+gxy_status gxy_set_batch_workers(gxy_ctx *ctx, int32_t workers) {
+  if (!ctx || workers < 0 || workers > 64) return GXY_EINVAL;
+  ctx->batch_workers = workers;
+  return GXY_OK;
+}
+
+gxy_status gxy_autotune(gxy_ctx *ctx, const gxy_point *templ, const int32_t *dcuts, int32_t n,
+                        int32_t *tiles, double *ms) {
+  if (!ctx || !templ || !dcuts || n <= 0) return GXY_EINVAL;
+  GXY_API_BEGIN
+  GXY_HIP(hipSetDevice(ctx->device));
+  for (int i = 0; i < n; ++i) {
+    gxy_point p = *templ;
+    p.dcut = dcuts[i];
+    gxy::validate(p);
+    double best_ms = 0.0;
+    int best = 0;
+    for (int tile : {64, 128}) {
+      ctx->force_tile = tile;
+      ctx->hot_force = true;
+      double st[4] = {0, 0, 0, 0};
+      ctx->logs.assign(1, gxy::RunLog{});
+      gxy_result r{};
+      r.fail_step = -1;
+      try {
+        // first run warms the code objects and the workspace, second is timed
+        gxy::run_one(ctx, p, r, ctx->logs[0]);
+        for (int j = 0; j < 4; ++j) ctx->hot_stats[j] = 0.0;
+        gxy::run_one(ctx, p, r, ctx->logs[0]);
+      } catch (...) {
+        ctx->force_tile = 0;
+        ctx->hot_force = false;
+        throw;
+      }
+      for (int j = 0; j < 4; ++j) st[j] = ctx->hot_stats[j];
+      if (ms) ms[2 * i + (tile == 128)] = st[1];
+      if (best == 0 || st[1] < best_ms) {
+        best = tile;
+        best_ms = st[1];
+      }
+    }
+    ctx->force_tile = 0;
+    ctx->hot_force = false;
+    for (int j = 0; j < 4; ++j) ctx->hot_stats[j] = 0.0;
+    ctx->tile_for_dcut[p.dcut] = best;
+    if (tiles) tiles[i] = best;
+  }
+  return GXY_OK;
+  GXY_API_END(ctx)
 }
 
 gxy_status gxy_step_log(gxy_ctx *ctx, int32_t run, gxy_step_info *out, int32_t cap,

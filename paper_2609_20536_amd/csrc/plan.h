@@ -50,6 +50,7 @@ struct TablePlan {
 struct StepLegs {
   int Dh, Dv, Dn, mod;
   std::vector<int> lh, lv, ln;  // labels of l/r legs, u/d legs, new a/b legs
+  int tile = 0;  // projection tiles: 0 = chosen by tile fill, else 64 or 128
 };
 
 // Environment Gram matrices of one side (right = false: E_L, else E_R):

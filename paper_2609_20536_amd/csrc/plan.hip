@@ -69,12 +69,13 @@ int choose_tile(const std::vector<GSpec> &gs) {
   return work / ((double)t128 * 128.0 * 128.0) >= 0.6 ? 128 : 64;
 }
 
-Launch finish_launch(TablePlan &tp, const std::vector<GSpec> &gs, bool kfa, bool nfb) {
+Launch finish_launch(TablePlan &tp, const std::vector<GSpec> &gs, bool kfa, bool nfb,
+                     int force_tile = 0) {
   Launch L;
   L.first_group = (int32_t)tp.groups.size();
   L.kfast_a = kfa;
   L.nfast_b = nfb;
-  L.tile = choose_tile(gs);
+  L.tile = force_tile ? force_tile : choose_tile(gs);
   for (const auto &g : gs) {
     if (g.M <= 0 || g.N <= 0) continue;
     GGroup G;
@@ -261,7 +262,7 @@ Launch plan_proj_x(const StepLegs &S, int a0, int a1, const QSet &sA, TablePlan 
     g.cc = put(tp, cc);
     gs.push_back(g);
   }
-  return finish_launch(tp, gs, false, true);
+  return finish_launch(tp, gs, false, true, S.tile);
 }
 
 Launch plan_proj_y(const StepLegs &S, int a0, int a1, const QSet &sA, const QSet &sB,
@@ -314,7 +315,7 @@ Launch plan_proj_y(const StepLegs &S, int a0, int a1, const QSet &sA, const QSet
     g.cc = g.bc;
     gs.push_back(g);
   }
-  return finish_launch(tp, gs, true, true);
+  return finish_launch(tp, gs, true, true, S.tile);
 }
 
 Launch plan_proj_t(const StepLegs &S, int a0, int a1, const QSet &sY, TablePlan &tp) {
@@ -364,7 +365,7 @@ Launch plan_proj_t(const StepLegs &S, int a0, int a1, const QSet &sY, TablePlan 
     g.cc = put(tp, cc);
     gs.push_back(g);
   }
-  return finish_launch(tp, gs, false, true);
+  return finish_launch(tp, gs, false, true, S.tile);
 }
 
 }  // namespace gxy

@@ -85,6 +85,9 @@ def load_library(path: str = LIB_PATH):
         "gxy_initial_tensor": [C.c_void_p, P(Point), C.c_int32, P(C.c_double)],
         "gxy_run": [C.c_void_p, P(Point), P(Result)],
         "gxy_run_batch": [C.c_void_p, P(Point), C.c_int32, P(Result)],
+        "gxy_set_batch_workers": [C.c_void_p, C.c_int32],
+        "gxy_autotune": [C.c_void_p, P(Point), P(C.c_int32), C.c_int32, P(C.c_int32),
+                         P(C.c_double)],
         "gxy_step_log": [C.c_void_p, C.c_int32, P(StepInfo), C.c_int32, P(C.c_int32)],
         "gxy_observables": [C.c_void_p, C.c_int32, P(C.c_double), P(C.c_double),
                             P(C.c_double), P(C.c_double), C.c_double, C.c_double,
@@ -238,15 +241,42 @@ class Context:
             self._check(st, self.handle)
         return self._result(r, 0)
 
-    def run_batch(self, points) -> List[RunResult]:
+    def run_batch(self, points, workers: int = 1) -> List[RunResult]:
+        """Runs of all points; workers > 1 runs them concurrently on worker
+        contexts (own streams and library-allocated workspaces)."""
         pts = [point_from(p) for p in points]
-        self.reserve(pts)
+        self._check(self.lib.gxy_set_batch_workers(self.handle, int(workers)), self.handle)
+        if workers <= 1:
+            self.reserve(pts)
         arr = (Point * len(pts))(*pts)
         res = (Result * len(pts))()
         st = self.lib.gxy_run_batch(self.handle, arr, len(pts), res)
         if st not in (GXY_OK, 6):
             self._check(st, self.handle)
         return [self._result(res[i], i) for i in range(len(pts))]
+
+    def autotune(self, point, dcuts):
+        """Pick the faster projection tile per Dcut (see gxy_autotune);
+        returns {dcut: (tile, ms64, ms128)}."""
+        import numpy as np
+        pt = point_from(point)
+        d = np.ascontiguousarray(dcuts, dtype=np.int32)
+        copies = []
+        for x in d:
+            q = Point()
+            C.memmove(C.byref(q), C.byref(pt), C.sizeof(Point))
+            q.dcut = int(x)
+            copies.append(q)
+        self.reserve(copies)
+        tiles = np.empty(d.size, dtype=np.int32)
+        ms = np.empty(2 * d.size)
+        self._check(self.lib.gxy_autotune(self.handle, C.byref(pt),
+                                          d.ctypes.data_as(C.POINTER(C.c_int32)), d.size,
+                                          tiles.ctypes.data_as(C.POINTER(C.c_int32)),
+                                          ms.ctypes.data_as(C.POINTER(C.c_double))),
+                    self.handle)
+        return {int(x): (int(t), float(ms[2 * i]), float(ms[2 * i + 1]))
+                for i, (x, t) in enumerate(zip(d, tiles))}
 
     def step_log(self, run=0):
         cnt = C.c_int32()
