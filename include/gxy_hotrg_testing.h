@@ -39,6 +39,13 @@ gxy_status gxy_test_gemm(gxy_ctx *ctx, int32_t prec, int32_t M, int32_t N, int32
 gxy_status gxy_test_eigh(gxy_ctx *ctx, int32_t n, const double *A, double *w,
                          double *V, int32_t *sweeps);
 
+/* The same with the solver chosen: method 0 = as a run would, 1 = block
+ * Jacobi, 2 = Householder tridiagonalisation + bisection + inverse
+ * iteration (n <= 128 here, since all n eigenvectors are asked for; larger
+ * n use block Jacobi). Eigenvalues w in the solver's column order. */
+gxy_status gxy_test_eigh_method(gxy_ctx *ctx, int32_t method, int32_t n, const double *A,
+                                double *w, double *V, int32_t *sweeps);
+
 /* Register layout of one FP64 16x16x4 matrix-core instruction: lane l
  * supplies a[l] and b[l]; out[4 l + r] receives accumulator register r of
  * lane l (accumulator initially zero). */

@@ -28,6 +28,7 @@
 #include <string>
 #include <vector>
 
+#include "../../include/gxy_hotrg_testing.h"
 #include "ctx.h"
 #include "internal.h"
 #include "plan.h"
@@ -36,7 +37,7 @@ namespace gxy {
 
 constexpr double kTieRel = 1e-12;
 constexpr double kSideTol = 1e-10;
-constexpr int kMaxSweeps = 40;
+constexpr int kMaxSweeps = 120;
 constexpr int kLmax = 50;
 
 enum Sym { SYM_U1 = 0, SYM_NONE = 1, SYM_Z2 = 2 };
@@ -624,7 +625,8 @@ static int jacobi_sweeps(const EigBatch &eb, double abs_tol, double rel_tol, dou
   const int nmat = eb.nmat;
   launch_eig_scale(eb, s);
   launch_fill_i32(eb.d_flags + nmat, nmat, 0, s);
-  for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
+  const int max_sweeps = (int)env_size("GXY_JACOBI_MAX_SWEEPS", kMaxSweeps);
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     for (int rr = 0; rr < eb.max_nb - 1; ++rr)
       launch_eig_round(eb, rr, abs_tol, rel_tol, gap_tol, 1, s);
     // flags <- next flags, next <- 0, and read them back
@@ -646,10 +648,25 @@ struct SectorSolve {
   int sweeps, sweeps2;  // block-Jacobi sweeps of the two stages
 };
 
-// Eigendecomposition of every label sector of E_L (E) and E_R (E + nf*nf) by
-// batched block Jacobi. hp: pinned host scratch (>= 2 * nsec ints).
+// Which batched eigensolver: where every sector has at most kTriMaxN rows and
+// at most kTriMaxVecs eigenvectors are needed, Householder tridiagonalisation
+// + bisection + inverse iteration (O(n^3) once); otherwise block Jacobi
+// (O(n^3) per sweep, tens of sweeps). GXY_EIG=jacobi forces block Jacobi.
+enum { EIG_AUTO = 0, EIG_JACOBI = 1, EIG_TRI = 2 };
+static int eig_method_env() {
+  const char *v = getenv("GXY_EIG");
+  if (!v) return EIG_AUTO;
+  if (!strcmp(v, "jacobi")) return EIG_JACOBI;
+  if (!strcmp(v, "tri")) return EIG_TRI;
+  return EIG_AUTO;
+}
+
+// Eigendecomposition of every label sector of E_L (E) and E_R (E + nf*nf).
+// kmax: eigenvectors needed per sector (the leading ones; the tridiagonal
+// path forms only those). hp: pinned host scratch (>= 2 * nsec ints).
 static SectorSolve solve_sectors(gxy_ctx *ctx, hipStream_t s, const double *E, int nf,
-                                 const Sectors &sec, const EigMem &m, int32_t *hp) {
+                                 const Sectors &sec, const EigMem &m, int32_t *hp,
+                                 int kmax, int method = EIG_AUTO) {
   const int nsec = (int)sec.label.size();
   const int nmat = 2 * nsec;
   std::vector<int32_t> npad(nmat), pairbase(nmat + 1), pair_mat, tiles;
@@ -716,6 +733,27 @@ static SectorSolve solve_sectors(gxy_ctx *ctx, hipStream_t s, const double *E, i
   eb.d_rtl = m.ints + o_tl;
   eb.n_update_tiles = (int32_t)(tiles.size() / 4);
   eb.d_pair_rot = m.flags + 2 * nmat;
+  int maxn = 0;
+  for (int k = 0; k < nsec; ++k) maxn = std::max(maxn, (int)sec.n[k]);
+  if (method == EIG_AUTO) method = eig_method_env();
+  if (method != EIG_JACOBI && maxn <= kTriMaxN && std::min(kmax, maxn) <= kTriMaxVecs) {
+    // Householder tridiagonalisation + implicit QL + back-transformation
+    EigBatch eg = eb;
+    eg.V = nullptr;
+    launch_eig_gather(E, nf, r.d_idx, r.d_start, r.d_n, nsec, eg, s);
+    launch_fill_i32(m.flags, nmat, 0, s);
+    launch_tri_eig(nmat, nsec, r.d_n, eb.d_npad, eb.d_off, m.A, m.V, m.B1, m.B2, m.flags,
+                   std::max(1, kmax), s);
+    GXY_HIP(hipMemcpyAsync(hp, m.flags, nmat * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    GXY_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k < nmat; ++k)
+      if (hp[k]) fail(GXY_ENUMERIC, "tridiagonal QL did not converge");
+    r.eb.A = m.A;
+    r.eb.V = m.V;
+    r.sweeps = 0;
+    r.sweeps2 = 0;
+    return r;
+  }
   // batched products over the padded matrices: C = A B and C = A^T B
   TablePlan tp;
   Launch L_nn, L_tn;
@@ -939,7 +977,7 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
       EigMem em{b.eigA, b.eigV, b.eigQ, b.eig_scale, b.eig_flags, b.ints, b.ints_cap,
                 b.eig_elems, b.eig_q, b.eigB1, b.eigB2, b.gtab, b.ggrp, b.gtab_cap,
                 b.ggrp_cap};
-      const SectorSolve sv = solve_sectors(ctx, s, b.E, (int)nf, sec, em, hp);
+      const SectorSolve sv = solve_sectors(ctx, s, b.E, (int)nf, sec, em, hp, Dn);
       const EigBatch &eb = sv.eb;
       info.eig_sweeps = sv.sweeps + 100 * sv.sweeps2;
       const int32_t *d_idx = sv.d_idx, *d_start = sv.d_start, *d_n = sv.d_n,
@@ -1572,7 +1610,13 @@ gxy_status gxy_test_gemm_f64(gxy_ctx *ctx, int32_t M, int32_t N, int32_t K, cons
 
 gxy_status gxy_test_eigh(gxy_ctx *ctx, int32_t n, const double *A, double *w, double *V,
                          int32_t *sweeps) {
-  if (!ctx || n <= 0 || n > 8192 || !A || !w || !V) return GXY_EINVAL;
+  return gxy_test_eigh_method(ctx, 0, n, A, w, V, sweeps);
+}
+
+gxy_status gxy_test_eigh_method(gxy_ctx *ctx, int32_t method, int32_t n, const double *A,
+                                double *w, double *V, int32_t *sweeps) {
+  if (!ctx || n <= 0 || n > 8192 || !A || !w || !V || method < 0 || method > 2)
+    return GXY_EINVAL;
   GXY_API_BEGIN
   GXY_HIP(hipSetDevice(ctx->device));
   using namespace gxy;
@@ -1615,7 +1659,8 @@ gxy_status gxy_test_eigh(gxy_ctx *ctx, int32_t n, const double *A, double *w, do
     hipStream_t s = ctx->stream;
     GXY_HIP(hipMemcpyAsync(E, A, nn * sizeof(double), hipMemcpyHostToDevice, s));
     GXY_HIP(hipMemcpyAsync(E + nn, A, nn * sizeof(double), hipMemcpyHostToDevice, s));
-    const SectorSolve sv = solve_sectors(ctx, s, E, n, sec, m, (int32_t *)ctx->pinned);
+    const SectorSolve sv =
+        solve_sectors(ctx, s, E, n, sec, m, (int32_t *)ctx->pinned, n, method);
     if (sweeps) *sweeps = sv.sweeps + sv.sweeps2;
     // eigenvalues: diagonal of the converged matrix; vectors: first n rows/cols
     GXY_HIP(hipMemcpy2DAsync(V, n * sizeof(double), sv.eb.V, np * sizeof(double),

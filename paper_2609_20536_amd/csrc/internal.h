@@ -186,6 +186,18 @@ void launch_eig_identity(const EigBatch &b, double *V, hipStream_t s);
 // y = a x over n elements
 void launch_eig_scaled_copy(int64_t n, double a, const double *x, double *y, hipStream_t s);
 
+// Tridiagonal path for sector matrices of at most kTriMaxN rows (one
+// workgroup per matrix). A: gathered padded matrices (overwritten: reflectors
+// right of the diagonal, sorted eigenvalues on the diagonal); V: leading
+// min(n, kmax) eigenvectors (row-major, column c = c-th largest); Y, work:
+// scratch shaped like A; status[mi] = 1 if QL did not converge (caller
+// zeroes it).
+constexpr int kTriMaxN = 512;
+constexpr int kTriMaxVecs = 128;   // eigenvectors formed per matrix
+void launch_tri_eig(int nmat, int nsec, const int32_t *d_sec_n, const int32_t *d_npad,
+                    const int64_t *d_off, double *A, double *V, double *Y, double *work,
+                    int32_t *d_status, int kmax, hipStream_t s);
+
 // --------------------------------------------------------------------------
 // selection and projector
 // --------------------------------------------------------------------------

@@ -1,0 +1,447 @@
+// Batched FP64 symmetric eigensolver for sector matrices of up to 512 rows:
+// Householder tridiagonalisation, bisection for every eigenvalue, inverse
+// iteration for the leading eigenvectors, back-transformation.
+//
+// The HOSVD factors of M (Ch. 2, eq. hosvd) are eigenvectors of the Gram
+// matrices E of M's unfoldings, block diagonal in the symmetry label of the
+// fused bond; every label sector of both sides is one matrix of the batch
+// (gathered into padded row-major storage, row stride npad).
+//
+//  1. tri_reduce: one workgroup per matrix reduces A to tridiagonal form
+//     T = H^T A H with n - 2 Householder reflectors (the reduction of the
+//     textbook symmetric QR algorithm). The two-sided rank-2 update keeps A
+//     exactly symmetric (both triangles receive the same two rounded
+//     products). Reflector j is kept in row j of A (right of the diagonal).
+//  2. tri_bisect: every eigenvalue of T by bisection on Sturm counts, one
+//     thread each (all of them enter the discarded weights).
+//  3. tri_invit: the leading kq = min(n, Dcut) eigenvectors of T, one thread
+//     per vector, by inverse iteration on the pivoted LU factorisation of
+//     T - lambda I, then Gram-Schmidt across the workgroup (the textbook
+//     bisection + inverse iteration pair for selected eigenpairs).
+//  4. tri_back: eigenvalues (decreasing) go to the diagonal of A, the
+//     vectors are mapped back through the reflectors into V (row-major,
+//     column c = c-th largest eigenvalue).
+#include <float.h>
+
+#include "internal.h"
+
+namespace gxy {
+
+namespace {
+
+constexpr int kRedThreads = 1024;
+constexpr int kRedWaves = kRedThreads / 64;
+
+__device__ __forceinline__ double wave_sum(double x) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+// sum over the workgroup (every thread receives the total); red >= 16 slots
+__device__ double block_sum(double x, double *red) {
+  x = wave_sum(x);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = x;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < kRedWaves; ++w) t += red[w];
+  return t;
+}
+
+__global__ __launch_bounds__(kRedThreads) void tri_reduce_kernel(
+    int nmat, int nsec, const int32_t *sec_n, const int32_t *npad, const int64_t *off,
+    double *A, double *work) {
+  __shared__ double v[kTriMaxN];
+  __shared__ double w[kTriMaxN];
+  __shared__ double red[kRedWaves];
+  __shared__ double s_tau, s_scal;
+  const int mi = blockIdx.x;
+  if (mi >= nmat) return;
+  const int n = sec_n[mi % nsec];
+  const int np = npad[mi];
+  double *Am = A + off[mi];
+  double *d = work + off[mi], *e = d + np, *tau = e + np;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int j = 0; j + 2 < n; ++j) {
+    const int m = n - j - 1;
+    const double *rowj = Am + (int64_t)j * np + j + 1;   // column j below the diagonal
+    double part = 0.0;
+    for (int i = tid; i < m; i += kRedThreads) {
+      const double x = rowj[i];
+      v[i] = x;
+      if (i > 0) part += x * x;
+    }
+    const double sigma = block_sum(part, red);
+    if (tid == 0) {
+      const double alpha = v[0];
+      d[j] = Am[(int64_t)j * np + j];
+      if (sigma == 0.0) {
+        s_tau = 0.0;
+        s_scal = 0.0;
+        e[j] = alpha;
+      } else {
+        const double beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
+        s_tau = (beta - alpha) / beta;
+        s_scal = 1.0 / (alpha - beta);
+        e[j] = beta;
+      }
+      tau[j] = s_tau;
+    }
+    __syncthreads();
+    const double tj = s_tau;
+    if (tj == 0.0) continue;   // uniform: no reflection needed
+    const double sc = s_scal;
+    double *roww = Am + (int64_t)j * np + j + 1;
+    for (int i = tid; i < m; i += kRedThreads) {
+      const double vi = (i == 0) ? 1.0 : v[i] * sc;
+      v[i] = vi;
+      roww[i] = vi;   // keep the reflector for the back-transformation
+    }
+    __syncthreads();
+    // p = tau A22 v (one wave per row, lanes along the row)
+    const double *A22 = Am + (int64_t)(j + 1) * np + (j + 1);
+    for (int i = wave; i < m; i += kRedWaves) {
+      const double *ri = A22 + (int64_t)i * np;
+      double acc = 0.0;
+      for (int k = lane; k < m; k += 64) acc += ri[k] * v[k];
+      acc = wave_sum(acc);
+      if (lane == 0) w[i] = tj * acc;
+    }
+    __syncthreads();
+    double pv = 0.0;
+    for (int i = tid; i < m; i += kRedThreads) pv += w[i] * v[i];
+    const double K = -0.5 * tj * block_sum(pv, red);
+    for (int i = tid; i < m; i += kRedThreads) w[i] += K * v[i];
+    __syncthreads();
+    // A22 -= v w^T + w v^T; the two products are rounded separately and added
+    // in either order, so entries (i, k) and (k, i) stay equal
+    double *B22 = Am + (int64_t)(j + 1) * np + (j + 1);
+    for (int i = wave; i < m; i += kRedWaves) {
+      double *ri = B22 + (int64_t)i * np;
+      const double vi = v[i], wi = w[i];
+      for (int k = lane; k < m; k += 64) {
+        const double upd = __dadd_rn(__dmul_rn(vi, w[k]), __dmul_rn(wi, v[k]));
+        ri[k] = ri[k] - upd;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (n >= 2) {
+      d[n - 2] = Am[(int64_t)(n - 2) * np + (n - 2)];
+      e[n - 2] = Am[(int64_t)(n - 2) * np + (n - 1)];
+      tau[n - 2] = 0.0;
+    }
+    d[n - 1] = Am[(int64_t)(n - 1) * np + (n - 1)];
+    e[n - 1] = 0.0;
+    tau[n - 1] = 0.0;
+  }
+}
+
+// Eigenvalues of T by bisection on Sturm counts, one thread per eigenvalue
+// (index k = k-th largest). The count of eigenvalues below x is the number of
+// negative pivots of the LDL^T factorisation of T - x I; pivots smaller than
+// pivmin are replaced by -pivmin. Bisection stops at relative width 2 eps or
+// after 128 halvings. The results are made non-increasing in k.
+constexpr int kBisThreads = 256;
+
+__device__ int sturm_below(const double *d, const double *e2, int n, double x, double pivmin) {
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  int cnt = q < 0.0;
+  for (int i = 1; i < n; ++i) {
+    q = d[i] - x - e2[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
+  }
+  return cnt;
+}
+
+__global__ __launch_bounds__(kBisThreads) void tri_bisect_kernel(int nmat, int nsec,
+                                                                 const int32_t *sec_n,
+                                                                 const int32_t *npad,
+                                                                 const int64_t *off,
+                                                                 double *work) {
+  __shared__ double ds[kTriMaxN], e2s[kTriMaxN];
+  __shared__ double gl_s, gu_s, piv_s;
+  const int mi = blockIdx.y;
+  if (mi >= nmat) return;
+  const int n = sec_n[mi % nsec];
+  const int np = npad[mi];
+  double *dg = work + off[mi], *eg = dg + np, *lam = dg + 3 * np;
+  for (int i = threadIdx.x; i < n; i += kBisThreads) {
+    ds[i] = dg[i];
+    e2s[i] = i < n - 1 ? eg[i] * eg[i] : 0.0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // Gershgorin interval and the pivot floor
+    double gl = DBL_MAX, gu = -DBL_MAX, emax2 = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double r = (i > 0 ? fabs(eg[i - 1]) : 0.0) + (i < n - 1 ? fabs(eg[i]) : 0.0);
+      gl = fmin(gl, ds[i] - r);
+      gu = fmax(gu, ds[i] + r);
+      emax2 = fmax(emax2, e2s[i]);
+    }
+    const double w = fmax(gu - gl, DBL_MIN);
+    gl_s = gl - 2.0 * DBL_EPSILON * w - DBL_MIN;
+    gu_s = gu + 2.0 * DBL_EPSILON * w + DBL_MIN;
+    piv_s = DBL_MIN * fmax(1.0, emax2);
+  }
+  __syncthreads();
+  const int k = blockIdx.x * kBisThreads + threadIdx.x;
+  if (k < n) {
+    const int j = n - 1 - k;   // ascending index of the k-th largest eigenvalue
+    double lo = gl_s, hi = gu_s;
+    for (int it = 0; it < 128; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (mid <= lo || mid >= hi) break;
+      if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi))) break;
+      if (sturm_below(ds, e2s, n, mid, piv_s) > j)
+        hi = mid;
+      else
+        lo = mid;
+    }
+    lam[k] = 0.5 * (lo + hi);
+  }
+}
+
+__global__ void tri_monotone_kernel(int nmat, int nsec, const int32_t *sec_n,
+                                    const int32_t *npad, const int64_t *off, double *work) {
+  const int mi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (mi >= nmat) return;
+  const int n = sec_n[mi % nsec];
+  const int np = npad[mi];
+  double *lam = work + off[mi] + 3 * np;
+  for (int k = 1; k < n; ++k) lam[k] = fmin(lam[k], lam[k - 1]);
+}
+
+// Leading kq eigenvectors of T by inverse iteration, one thread per vector:
+// three solves of (T - mu I) y = x with the LU factorisation with partial
+// pivoting of the tridiagonal matrix, x <- y / max|y| after each, mu the
+// eigenvalue, moved apart by pertol = 10 eps ||T|| where consecutive ones are
+// closer (so equal eigenvalues give independent solves). Then classical
+// Gram-Schmidt, twice, in decreasing eigenvalue order, and unit 2-norm.
+// Y[c * np + i]: vector c; U: factor scratch laid out [3][n][kq].
+constexpr int kInvThreads = 256;
+constexpr int kMaxKq = kTriMaxVecs;
+
+__device__ __forceinline__ double start_value(int i, int c) {
+  uint64_t z = ((uint64_t)(i + 1) << 32) ^ (uint64_t)(c + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return (double)(z >> 11) * 0x1.0p-53 * 2.0 - 1.0;
+}
+
+__global__ __launch_bounds__(kInvThreads) void tri_invit_kernel(int nmat, int nsec,
+                                                                const int32_t *sec_n,
+                                                                const int32_t *npad,
+                                                                const int64_t *off,
+                                                                const double *work, double *U,
+                                                                double *Y, int kmax) {
+  __shared__ double ds[kTriMaxN], es[kTriMaxN];
+  __shared__ double mu[kMaxKq];
+  __shared__ double dot[kMaxKq];
+  __shared__ double red[kInvThreads / 64];
+  __shared__ double tnorm_s;
+  const int mi = blockIdx.x;
+  if (mi >= nmat) return;
+  const int n = sec_n[mi % nsec];
+  const int np = npad[mi];
+  const int kq = min(min(n, kmax), kMaxKq);
+  const double *dg = work + off[mi], *eg = dg + np, *lam = dg + 3 * np;
+  double *Um = U + off[mi];
+  double *Ym = Y + off[mi];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int i = tid; i < n; i += kInvThreads) {
+    ds[i] = dg[i];
+    es[i] = i < n - 1 ? eg[i] : 0.0;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int i = 0; i < n; ++i)
+      t = fmax(t, fabs(ds[i]) + fabs(es[i]) + (i > 0 ? fabs(es[i - 1]) : 0.0));
+    tnorm_s = fmax(t, DBL_MIN);
+    const double pertol = 10.0 * DBL_EPSILON * tnorm_s;
+    double prev = 0.0;
+    for (int c = 0; c < kq; ++c) {
+      double m = lam[c];
+      if (c > 0 && prev - m < pertol) m = prev - pertol;
+      mu[c] = m;
+      prev = m;
+    }
+  }
+  __syncthreads();
+  const double tiny = DBL_EPSILON * tnorm_s;
+  const bool zero_matrix = tnorm_s <= DBL_MIN;   // any orthonormal basis will do
+  // the factor scratch holds 3 n kb doubles (kb vectors at a time) inside
+  // this matrix's npad x npad block of U
+  const int kb = max(1, min(kq, (int)(((int64_t)np * np) / (3 * (int64_t)n))));
+  for (int c0 = 0; c0 < kq; c0 += kb) {
+    const int t = tid;
+    const int c = c0 + t;
+    if (t < kb && c < kq) {
+      double *x = Ym + (int64_t)c * np;
+      if (n == 1 || zero_matrix) {
+        for (int i = 0; i < n; ++i) x[i] = (i == c) ? 1.0 : 0.0;
+      } else {
+        const double m = mu[c];
+        double *u0 = Um, *u1 = Um + (int64_t)n * kb, *u2 = Um + 2 * (int64_t)n * kb;
+        for (int i = 0; i < n; ++i) x[i] = start_value(i, c);
+        for (int it = 0; it < 3; ++it) {
+          // factor T - m I with row interchanges while eliminating the
+          // right-hand side x; row i of U is (u0, u1, u2) at columns i..i+2
+          double a = ds[0] - m, bsup = es[0], y = x[0];
+          for (int i = 0; i < n - 1; ++i) {
+            const double csub = es[i];            // T[i+1][i]
+            const double anext = ds[i + 1] - m;   // T[i+1][i+1]
+            const double bnext = i + 1 < n - 1 ? es[i + 1] : 0.0;
+            const double ynext = x[i + 1];
+            const int64_t at = (int64_t)i * kb + t;
+            if (fabs(a) >= fabs(csub)) {
+              const double piv = (a != 0.0) ? a : tiny;
+              const double l = csub / piv;
+              u0[at] = piv;
+              u1[at] = bsup;
+              u2[at] = 0.0;
+              x[i] = y;
+              a = anext - l * bsup;
+              bsup = bnext;
+              y = ynext - l * y;
+            } else {
+              const double l = a / csub;
+              u0[at] = csub;
+              u1[at] = anext;
+              u2[at] = bnext;
+              x[i] = ynext;
+              a = bsup - l * anext;
+              bsup = -l * bnext;
+              y = y - l * ynext;
+            }
+          }
+          {
+            const int64_t at = (int64_t)(n - 1) * kb + t;
+            u0[at] = (a != 0.0) ? a : tiny;
+            x[n - 1] = y;
+          }
+          // back substitution, then scale by the largest entry
+          double xmax = 0.0, x1 = 0.0, x2 = 0.0;
+          for (int i = n - 1; i >= 0; --i) {
+            const int64_t at = (int64_t)i * kb + t;
+            const double v = (x[i] - u1[at] * x1 - u2[at] * x2) / u0[at];
+            x[i] = v;
+            x2 = x1;
+            x1 = v;
+            xmax = fmax(xmax, fabs(v));
+          }
+          const double inv = xmax > 0.0 ? 1.0 / xmax : 1.0;
+          for (int i = 0; i < n; ++i) x[i] *= inv;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // classical Gram-Schmidt, twice, in order c = 0, 1, ...
+  for (int c = 0; c < kq; ++c) {
+    double *xc = Ym + (int64_t)c * np;
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int j = wave; j < c; j += kInvThreads / 64) {
+        const double *xj = Ym + (int64_t)j * np;
+        double acc = 0.0;
+        for (int i = lane; i < n; i += 64) acc += xj[i] * xc[i];
+        acc = wave_sum(acc);
+        if (lane == 0) dot[j] = acc;
+      }
+      __syncthreads();
+      for (int i = tid; i < n; i += kInvThreads) {
+        double v = xc[i];
+        for (int j = 0; j < c; ++j) v -= dot[j] * Ym[(int64_t)j * np + i];
+        xc[i] = v;
+      }
+      __syncthreads();
+    }
+    double part = 0.0;
+    for (int i = tid; i < n; i += kInvThreads) part += xc[i] * xc[i];
+    part = wave_sum(part);
+    if (lane == 0) red[wave] = part;
+    __syncthreads();
+    double nrm2 = 0.0;
+    for (int w = 0; w < kInvThreads / 64; ++w) nrm2 += red[w];
+    const double inv = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
+    for (int i = tid; i < n; i += kInvThreads) xc[i] *= inv;
+    __syncthreads();
+  }
+}
+
+// Eigenvalues to diag(A); the leading kq eigenvectors of A = H Y, with
+// H = H_0 H_1 ... H_{n-3} (the last reflector applied first), written to V.
+constexpr int kBackThreads = 1024;
+
+__global__ __launch_bounds__(kBackThreads) void tri_back_kernel(
+    int nmat, int nsec, const int32_t *sec_n, const int32_t *npad, const int64_t *off,
+    double *A, const double *work, double *V, double *Y, int kmax) {
+  const int mi = blockIdx.x;
+  if (mi >= nmat) return;
+  const int n = sec_n[mi % nsec];
+  const int np = npad[mi];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int nwv = kBackThreads / 64;
+  const double *dg = work + off[mi], *tau = dg + 2 * np, *lam = dg + 3 * np;
+  double *Am = A + off[mi];
+  double *Vm = V + off[mi];
+  double *Ym = Y + off[mi];   // Y[c * np + r], c < kq
+  const int kq = min(min(n, kmax), kMaxKq);
+  // each wave owns whole columns of Y: no waiting between waves here
+  for (int c = wave; c < kq; c += nwv) {
+    double *yc = Ym + (int64_t)c * np;
+    for (int j = n - 3; j >= 0; --j) {
+      const double tj = tau[j];
+      if (tj == 0.0) continue;
+      const double *vj = Am + (int64_t)j * np + j + 1;   // v[0] = 1 stored explicitly
+      const int m = n - j - 1;
+      double acc = 0.0;
+      for (int i = lane; i < m; i += 64) acc += vj[i] * yc[j + 1 + i];
+      const double sdot = tj * wave_sum(acc);
+      for (int i = lane; i < m; i += 64) yc[j + 1 + i] -= sdot * vj[i];
+    }
+  }
+  __syncthreads();
+  // outputs: V row-major (columns >= kq zero), eigenvalues on diag(A)
+  for (int64_t el = tid; el < (int64_t)n * np; el += kBackThreads) {
+    const int r = (int)(el / np), c = (int)(el % np);
+    Vm[el] = (c < kq && r < n) ? Ym[(int64_t)c * np + r] : 0.0;
+  }
+  __syncthreads();
+  for (int c = tid; c < np; c += kBackThreads)
+    Am[(int64_t)c * np + c] = c < n ? lam[c] : -1.0;
+}
+
+}  // namespace
+
+void launch_tri_eig(int nmat, int nsec, const int32_t *d_sec_n, const int32_t *d_npad,
+                    const int64_t *d_off, double *A, double *V, double *Y, double *work,
+                    int32_t *d_status, int kmax, hipStream_t s) {
+  (void)d_status;
+  if (kmax > kMaxKq) fail(GXY_EUNSUPPORTED, "tridiagonal path: more than 128 vectors");
+  hipLaunchKernelGGL(tri_reduce_kernel, dim3(nmat), dim3(kRedThreads), 0, s, nmat, nsec,
+                     d_sec_n, d_npad, d_off, A, work);
+  GXY_CHECK_LAUNCH();
+  hipLaunchKernelGGL(tri_bisect_kernel, dim3(kTriMaxN / kBisThreads, nmat), dim3(kBisThreads),
+                     0, s, nmat, nsec, d_sec_n, d_npad, d_off, work);
+  GXY_CHECK_LAUNCH();
+  hipLaunchKernelGGL(tri_monotone_kernel, dim3((nmat + 63) / 64), dim3(64), 0, s, nmat, nsec,
+                     d_sec_n, d_npad, d_off, work);
+  GXY_CHECK_LAUNCH();
+  // V serves as the factor scratch of the inverse iteration until tri_back
+  hipLaunchKernelGGL(tri_invit_kernel, dim3(nmat), dim3(kInvThreads), 0, s, nmat, nsec,
+                     d_sec_n, d_npad, d_off, work, V, Y, kmax);
+  GXY_CHECK_LAUNCH();
+  hipLaunchKernelGGL(tri_back_kernel, dim3(nmat), dim3(kBackThreads), 0, s, nmat, nsec,
+                     d_sec_n, d_npad, d_off, A, work, V, Y, kmax);
+  GXY_CHECK_LAUNCH();
+}
+
+}  // namespace gxy

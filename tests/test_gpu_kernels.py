@@ -159,30 +159,74 @@ def _check_eig(A, w, V, tol=None):
     assert np.max(np.abs(V.T @ V - np.eye(n))) <= 10 * tol * max(1, n / 100)
 
 
-@pytest.mark.parametrize("n", [1, 2, 5, 16, 31, 32, 33, 64, 100, 257])
-def test_eigh_psd(ctx, n):
+EIG_METHODS = [1, 2]   # block Jacobi, Householder + bisection + inverse iteration
+
+
+@pytest.mark.parametrize("method", EIG_METHODS)
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 16, 31, 32, 33, 40, 64, 65, 100, 127, 128, 257])
+def test_eigh_psd(ctx, n, method):
     rng = np.random.default_rng(n)
     X = rng.standard_normal((n, n + 3))
     A = X @ X.T
-    w, V = ctx.test_eigh(A)
+    w, V = ctx.test_eigh(A, method)
     _check_eig(A, w, V)
 
 
-def test_eigh_rank_deficient_and_degenerate(ctx):
+def test_eigh_above_tridiagonal_limit_uses_jacobi(ctx):
+    rng = np.random.default_rng(513)
+    X = rng.standard_normal((129, 140))
+    A = X @ X.T
+    w, V = ctx.test_eigh(A, 2)
+    _check_eig(A, w, V)
+    assert ctx.last_sweeps > 0
+
+
+@pytest.mark.parametrize("method", EIG_METHODS)
+def test_eigh_graded_spectrum(ctx, method):
+    """Spectrum over 14 decades, like the HOTRG environments: eigenvalues to
+    eps * lambda_max, residuals and orthogonality to the same class."""
+    rng = np.random.default_rng(17)
+    n = 120
+    Q = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    lam = np.exp(-np.linspace(0.0, 32.0, n))
+    A = (Q * lam) @ Q.T
+    A = 0.5 * (A + A.T)
+    w, V = ctx.test_eigh(A, method)
+    _check_eig(A, w, V)
+
+
+@pytest.mark.parametrize("method", EIG_METHODS)
+def test_eigh_rank_deficient_and_degenerate(ctx, method):
     rng = np.random.default_rng(7)
     Q = np.linalg.qr(rng.standard_normal((70, 70)))[0]
     lam = np.concatenate([np.full(10, 3.0), np.full(20, 1e-3), np.zeros(40)])
     A = (Q * lam) @ Q.T
     A = 0.5 * (A + A.T)
-    w, V = ctx.test_eigh(A)
+    w, V = ctx.test_eigh(A, method)
     _check_eig(A, w, V)
     assert np.sum(np.abs(w - 3.0) < 1e-12) == 10
 
 
-def test_eigh_diagonal_and_block(ctx):
+@pytest.mark.parametrize("method", EIG_METHODS)
+def test_eigh_diagonal_and_block(ctx, method):
     A = np.diag(np.arange(40, dtype=float)[::-1])
-    w, V = ctx.test_eigh(A)
-    assert np.array_equal(np.sort(w), np.arange(40, dtype=float))
+    w, V = ctx.test_eigh(A, method)
+    if method == 1:   # rotations never start: exact
+        assert np.array_equal(np.sort(w), np.arange(40, dtype=float))
+    else:             # bisection: to eps ||A||
+        assert np.max(np.abs(np.sort(w) - np.arange(40.0))) <= 4e-16 * 39
+    B = np.zeros((45, 45))
+    B[:20, :20] = 2.0 * np.eye(20) + 0.5
+    B[20:, 20:] = np.diag(np.linspace(0.1, 1.0, 25))
+    w, V = ctx.test_eigh(B, method)
+    _check_eig(B, w, V)
+
+
+def test_tridiagonal_eigenvalues_sorted_decreasing(ctx):
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((90, 95))
+    w, V = ctx.test_eigh(X @ X.T, 2)
+    assert np.all(np.diff(w) <= 0.0)
 
 
 @pytest.mark.parametrize("beta,delta,nmax", [(0.0, 0.5, 3), (0.5, 0.0, 10), (1.0, 0.5, 10),
