@@ -11,6 +11,15 @@ covers every step of the path.
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
 Prints one JSON line. value = coarse-graining steps per second (40 per run).
+Two more legs ride on the same line (both skippable):
+* "precision": the same workload with the projection contractions in FP32
+  and in split-BF16x3 (FP64 for the first 12 / 16 steps), steps/s and
+  |d ln Z/V| against the FP64 run;
+* "batched": a stratified 16-point subset of the 16 x 16 (beta, Delta) grid
+  (4 points per Dcut in {24, 32, 48, 64}), three runs per point (beta - db,
+  beta, beta + db; f and C_v), run as one batch on 8 worker streams after
+  the per-Dcut tile autotuner: points/s in FP64 and with BF16x3 + schedule,
+  and max |d f| of the latter against FP64.
 """
 
 from __future__ import annotations
@@ -32,6 +41,60 @@ PEAK_HBM_GBS = 8000.0
 def workload_point(dcut: int):
     from paper_2609_20536_amd import workloads as W
     return W.precision_point(dcut=dcut, prec=W.PREC_FP64, impurities=W.IMP_COS1 | W.IMP_COS2)
+
+
+def precision_leg(ctx, pt, r64):
+    """Steps/s and |d ln Z/V| of the reduced-precision contraction forms."""
+    from paper_2609_20536_amd import workloads as W
+    out = {}
+    for name, prec, k in (("fp32", W.PREC_FP32, 12), ("bf16x3", W.PREC_BF16X3, 16)):
+        q = pt.with_(prec=prec, fp64_steps=k)
+        ctx.run(q)
+        t0 = time.perf_counter()
+        r = ctx.run(q)
+        el = time.perf_counter() - t0
+        out[name] = {"fp64_steps": k, "steps_per_s": q.nsteps / el,
+                     "abs_dlnz_per_site": abs(r.lnz_per_site - r64.lnz_per_site)}
+    return out
+
+
+def batched_leg(ctx, note):
+    """Points/s of f and C_v over a stratified grid subset, one batch."""
+    from paper_2609_20536_amd import workloads as W
+    gp = W.grid_points()
+    sub = []
+    for d in W.GRID_DCUTS:
+        sub += [g for g in gp if g.dcut == d][:4]
+    db = W.BETA_FD_STEP
+
+    def runs(prec, k):
+        return [W.Point(beta=g.beta + s, delta=g.delta, nmax=10, dcut=g.dcut, nsteps=40,
+                        impurities=0, prec=prec, fp64_steps=k)
+                for g in sub for s in (-db, 0.0, db)]
+    tiles = ctx.autotune(W.Point(beta=1.0, delta=0.5, nmax=10, dcut=24, nsteps=10,
+                                 impurities=0), list(W.GRID_DCUTS))
+    note("bench: tile autotuner done")
+    out = {"points": len(sub), "runs_per_point": 3, "workers": 8,
+           "tiles": {str(k): v[0] for k, v in tiles.items()}}
+    res = {}
+    for name, prec, k in (("fp64", W.PREC_FP64, 0), ("bf16x3", W.PREC_BF16X3, 16)):
+        pts = runs(prec, k)
+        ctx.run_batch(pts[:3], workers=8)
+        t0 = time.perf_counter()
+        rr = ctx.run_batch(pts, workers=8)
+        el = time.perf_counter() - t0
+        if any(r.status != 0 for r in rr):
+            raise SystemExit(f"batched {name}: a run failed")
+        res[name] = rr
+        out[name + "_points_per_s"] = len(sub) / el
+        note(f"bench: batched {name} done in {el:.1f}s")
+    # f = -(1/beta) ln Z/V at the centre runs
+    df = 0.0
+    for i, g in enumerate(sub):
+        a, b = res["fp64"][3 * i + 1], res["bf16x3"][3 * i + 1]
+        df = max(df, abs(a.lnz_per_site - b.lnz_per_site) / g.beta)
+    out["max_abs_df_bf16x3_vs_fp64"] = df
+    return out
 
 
 def cpu_baseline(dcut: int, nimp: int, frac_cols: int = 8):
@@ -90,6 +153,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--dcut", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="one plain 1 GiB device copy first (known HBM bytes for counter scaling)")
     ap.add_argument("--phases", action="store_true", help="one extra untimed run with phase timers")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -101,6 +168,12 @@ def main():
     from paper_2609_20536_amd import hotrg as H
 
     pt = workload_point(args.dcut)
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")   # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     ctx = H.Context(0)
     ctx.reserve([pt])
     os.environ.pop("GXY_TIMING", None)
@@ -162,7 +235,7 @@ def main():
         },
         "roofline": {
             "bound": "mfma",
-            "kernel": "projection D^7 GEMM (gemm_f64_kernel, Y = X T)",
+            "kernel": "projection D^7 grouped GEMM (ggemm_kernel, Y = X T, FP64)",
             "achieved": hot_tflops,
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
@@ -176,6 +249,11 @@ def main():
     }
     if phases:
         line["phases_ms"] = phases
+    if not args.no_precision:
+        line["precision"] = precision_leg(ctx, pt, r)
+        note("bench: precision leg done")
+    if not args.no_batched:
+        line["batched"] = batched_leg(ctx, note)
     if not args.no_cpu_baseline:
         note("bench: timing the CPU oracle sample")
         line["cpu_baseline"] = cpu_baseline(pt.dcut, 2)
