@@ -17,9 +17,10 @@ Two more legs ride on the same line (both skippable):
   |d ln Z/V| against the FP64 run;
 * "batched": a stratified 16-point subset of the 16 x 16 (beta, Delta) grid
   (4 points per Dcut in {24, 32, 48, 64}), three runs per point (beta - db,
-  beta, beta + db; f and C_v), run as one batch on 8 worker streams after
-  the per-Dcut tile autotuner: points/s in FP64 and with BF16x3 + schedule,
-  and max |d f| of the latter against FP64.
+  beta, beta + db; f and C_v): points/s of the plain FP64 path (runs one
+  after another), and, after the per-Dcut tile autotuner, of one batch on 8
+  worker streams in FP64 and with BF16x3 + schedule; max |d f| of the
+  latter against FP64.
 """
 
 from __future__ import annotations
@@ -43,10 +44,37 @@ def workload_point(dcut: int):
     return W.precision_point(dcut=dcut, prec=W.PREC_FP64, impurities=W.IMP_COS1 | W.IMP_COS2)
 
 
+def measured_traffic():
+    """HBM bytes per launch of the D^7 GEMM from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, if the kernel and planner sources are
+    unchanged since the counters were taken (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "ygemm_d64_chains_fp64_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    return rec["hbm_bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
+
+
 def precision_leg(ctx, pt, r64):
-    """Steps/s and |d ln Z/V| of the reduced-precision contraction forms."""
+    """Reduced-precision contraction forms on the bench workload: steps/s and
+    |d ln Z/V| against the FP64 run, and d C_v from zero-field runs at
+    beta +- 1e-3 (C_v = beta^2 d^2(ln Z/V)/d beta^2, central differences)."""
     from paper_2609_20536_amd import workloads as W
     out = {}
+    db = W.BETA_FD_STEP
+
+    def cv(prec, k):
+        base = pt.with_(impurities=0, prec=prec, fp64_steps=k)
+        l = [ctx.run(base.with_(beta=pt.beta + s)).lnz_per_site for s in (-db, 0.0, db)]
+        return pt.beta ** 2 * (l[0] - 2.0 * l[1] + l[2]) / db ** 2
+    cv64 = cv(W.PREC_FP64, 0)
+    out["cv_fp64"] = cv64
     for name, prec, k in (("fp32", W.PREC_FP32, 12), ("bf16x3", W.PREC_BF16X3, 16)):
         q = pt.with_(prec=prec, fp64_steps=k)
         ctx.run(q)
@@ -54,7 +82,8 @@ def precision_leg(ctx, pt, r64):
         r = ctx.run(q)
         el = time.perf_counter() - t0
         out[name] = {"fp64_steps": k, "steps_per_s": q.nsteps / el,
-                     "abs_dlnz_per_site": abs(r.lnz_per_site - r64.lnz_per_site)}
+                     "abs_dlnz_per_site": abs(r.lnz_per_site - r64.lnz_per_site),
+                     "abs_dcv": abs(cv(prec, k) - cv64)}
     return out
 
 
@@ -75,19 +104,23 @@ def batched_leg(ctx, note):
                                  impurities=0), list(W.GRID_DCUTS))
     note("bench: tile autotuner done")
     out = {"points": len(sub), "runs_per_point": 3, "workers": 8,
+           "plain": "the same runs one after another on one stream (FP64)",
            "tiles": {str(k): v[0] for k, v in tiles.items()}}
     res = {}
-    for name, prec, k in (("fp64", W.PREC_FP64, 0), ("bf16x3", W.PREC_BF16X3, 16)):
+    for name, prec, k, workers in (("plain_fp64", W.PREC_FP64, 0, 1), ("fp64", W.PREC_FP64, 0, 8),
+                                   ("bf16x3", W.PREC_BF16X3, 16, 8)):
         pts = runs(prec, k)
-        ctx.run_batch(pts[:3], workers=8)
+        ctx.run_batch(pts[:3], workers=workers)
         t0 = time.perf_counter()
-        rr = ctx.run_batch(pts, workers=8)
+        rr = ctx.run_batch(pts, workers=workers)
         el = time.perf_counter() - t0
         if any(r.status != 0 for r in rr):
             raise SystemExit(f"batched {name}: a run failed")
         res[name] = rr
         out[name + "_points_per_s"] = len(sub) / el
-        note(f"bench: batched {name} done in {el:.1f}s")
+        note(f"bench: {name} ({workers} worker(s)) done in {el:.1f}s")
+    out["speedup_bf16x3_batched_vs_plain_fp64"] = (out["bf16x3_points_per_s"] /
+                                                   out["plain_fp64_points_per_s"])
     # f = -(1/beta) ln Z/V at the centre runs
     df = 0.0
     for i, g in enumerate(sub):
@@ -240,10 +273,11 @@ def main():
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
             "frac": hot_tflops / PEAK_FP64_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic() if args.dcut == 64 else None,
             "launches": int(launches),
             "avg_launch_ms": hot_avg_ms,
             "flops_per_launch": flops / max(launches, 1),
+            "algorithmic_bytes_per_launch": nbytes / max(launches, 1),
         },
         "cpu_baseline": None,
     }

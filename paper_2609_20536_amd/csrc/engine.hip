@@ -1114,7 +1114,7 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
         tab_cur += (int64_t)pt.tp.tab.size();
         grp_cur += (int64_t)pt.tp.groups.size();
         auto gy = [&](const Launch &L, const double *Xp, const double *Bp) {
-          hot_begin(ctx, s, L.flops, 0.0);
+          hot_begin(ctx, s, L.flops, L.bytes);
           run_launch(L, dg, dt, Xp, Bp, b.Y, 1.0, 0.0, s, sprec);
           hot_end(ctx, s);
         };

@@ -36,6 +36,7 @@ struct Launch {
   int32_t first_group = 0, ngroups = 0, total_tiles = 0, tile = 64;
   bool kfast_a = false, nfast_b = false;
   double flops = 0.0;  // algorithmic 2 M N K summed over groups
+  double bytes = 0.0;  // algorithmic FP64 bytes: A, B read once, C written once
 };
 
 struct TablePlan {

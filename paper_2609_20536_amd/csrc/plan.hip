@@ -91,6 +91,7 @@ Launch finish_launch(TablePlan &tp, const std::vector<GSpec> &gs, bool kfa, bool
     G.cc = g.cc;
     L.total_tiles += ((g.M + L.tile - 1) / L.tile) * ((g.N + L.tile - 1) / L.tile);
     L.flops += 2.0 * g.M * g.N * (double)g.K;
+    L.bytes += 8.0 * ((double)g.M * g.K + (double)g.K * g.N + (double)g.M * g.N);
     tp.groups.push_back(G);
     ++L.ngroups;
   }
