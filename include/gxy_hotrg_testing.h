@@ -46,6 +46,13 @@ gxy_status gxy_test_eigh(gxy_ctx *ctx, int32_t n, const double *A, double *w,
 gxy_status gxy_test_eigh_method(gxy_ctx *ctx, int32_t method, int32_t n, const double *A,
                                 double *w, double *V, int32_t *sweeps);
 
+/* As a run needs it: every eigenvalue, and eigenvectors for (at least) the
+ * kmax largest ones (1 <= kmax <= n). The tridiagonal path (n <= 1024,
+ * kmax <= 128) returns eigenvalues in decreasing order with the leading
+ * kmax columns of V filled (the rest zero); block Jacobi fills all. */
+gxy_status gxy_test_eigh_top(gxy_ctx *ctx, int32_t method, int32_t n, int32_t kmax,
+                             const double *A, double *w, double *V, int32_t *sweeps);
+
 /* Register layout of one FP64 16x16x4 matrix-core instruction: lane l
  * supplies a[l] and b[l]; out[4 l + r] receives accumulator register r of
  * lane l (accumulator initially zero). */

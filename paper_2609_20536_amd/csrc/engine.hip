@@ -1615,7 +1615,13 @@ gxy_status gxy_test_eigh(gxy_ctx *ctx, int32_t n, const double *A, double *w, do
 
 gxy_status gxy_test_eigh_method(gxy_ctx *ctx, int32_t method, int32_t n, const double *A,
                                 double *w, double *V, int32_t *sweeps) {
-  if (!ctx || n <= 0 || n > 8192 || !A || !w || !V || method < 0 || method > 2)
+  return gxy_test_eigh_top(ctx, method, n, n, A, w, V, sweeps);
+}
+
+gxy_status gxy_test_eigh_top(gxy_ctx *ctx, int32_t method, int32_t n, int32_t kmax,
+                             const double *A, double *w, double *V, int32_t *sweeps) {
+  if (!ctx || n <= 0 || n > 8192 || !A || !w || !V || method < 0 || method > 2 || kmax < 1 ||
+      kmax > n)
     return GXY_EINVAL;
   GXY_API_BEGIN
   GXY_HIP(hipSetDevice(ctx->device));
@@ -1660,7 +1666,7 @@ gxy_status gxy_test_eigh_method(gxy_ctx *ctx, int32_t method, int32_t n, const d
     GXY_HIP(hipMemcpyAsync(E, A, nn * sizeof(double), hipMemcpyHostToDevice, s));
     GXY_HIP(hipMemcpyAsync(E + nn, A, nn * sizeof(double), hipMemcpyHostToDevice, s));
     const SectorSolve sv =
-        solve_sectors(ctx, s, E, n, sec, m, (int32_t *)ctx->pinned, n, method);
+        solve_sectors(ctx, s, E, n, sec, m, (int32_t *)ctx->pinned, kmax, method);
     if (sweeps) *sweeps = sv.sweeps + sv.sweeps2;
     // eigenvalues: diagonal of the converged matrix; vectors: first n rows/cols
     GXY_HIP(hipMemcpy2DAsync(V, n * sizeof(double), sv.eb.V, np * sizeof(double),

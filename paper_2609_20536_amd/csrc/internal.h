@@ -192,7 +192,7 @@ void launch_eig_scaled_copy(int64_t n, double a, const double *x, double *y, hip
 // min(n, kmax) eigenvectors (row-major, column c = c-th largest); Y, work:
 // scratch shaped like A; status[mi] = 1 if QL did not converge (caller
 // zeroes it).
-constexpr int kTriMaxN = 512;
+constexpr int kTriMaxN = 1024;
 constexpr int kTriMaxVecs = 128;   // eigenvectors formed per matrix
 void launch_tri_eig(int nmat, int nsec, const int32_t *d_sec_n, const int32_t *d_npad,
                     const int64_t *d_off, double *A, double *V, double *Y, double *work,

@@ -8,10 +8,14 @@
 // (gathered into padded row-major storage, row stride npad).
 //
 //  1. tri_reduce: one workgroup per matrix reduces A to tridiagonal form
-//     T = H^T A H with n - 2 Householder reflectors (the reduction of the
-//     textbook symmetric QR algorithm). The two-sided rank-2 update keeps A
-//     exactly symmetric (both triangles receive the same two rounded
-//     products). Reflector j is kept in row j of A (right of the diagonal).
+//     T = H^T A H with n - 2 Householder reflectors, blocked: the reflectors
+//     v and w-vectors of a panel of 16 columns are applied to the trailing
+//     matrix together (as a rank-32 update), and within the panel each
+//     column and each matrix-vector product is corrected for the pending
+//     ones. The matrix is then read about once per column instead of three
+//     times. The update pairs the same rounded products for (i, k) and
+//     (k, i), so A stays exactly symmetric. Reflector j is kept in row j of
+//     A (right of the diagonal).
 //  2. tri_bisect: every eigenvalue of T by bisection on Sturm counts, one
 //     thread each (all of them enter the discarded weights).
 //  3. tri_invit: the leading kq = min(n, Dcut) eigenvectors of T, one thread
@@ -22,6 +26,8 @@
 //     vectors are mapped back through the reflectors into V (row-major,
 //     column c = c-th largest eigenvalue).
 #include <float.h>
+
+#include <algorithm>
 
 #include "internal.h"
 
@@ -49,12 +55,18 @@ __device__ double block_sum(double x, double *red) {
   return t;
 }
 
+// Panel width of the blocked reduction: the reflectors and w-vectors of kNb
+// consecutive columns are applied to the trailing matrix together.
+constexpr int kNb = 16;
+
 __global__ __launch_bounds__(kRedThreads) void tri_reduce_kernel(
     int nmat, int nsec, const int32_t *sec_n, const int32_t *npad, const int64_t *off,
-    double *A, double *work) {
+    double *A, double *work, double *panel) {
   __shared__ double v[kTriMaxN];
   __shared__ double w[kTriMaxN];
   __shared__ double red[kRedWaves];
+  __shared__ double q1[kNb], q2[kNb], vj_s[kNb], wj_s[kNb];
+  __shared__ double pv_s[kNb][64], pw_s[kNb][64];
   __shared__ double s_tau, s_scal;
   const int mi = blockIdx.x;
   if (mi >= nmat) return;
@@ -62,70 +74,161 @@ __global__ __launch_bounds__(kRedThreads) void tri_reduce_kernel(
   const int np = npad[mi];
   double *Am = A + off[mi];
   double *d = work + off[mi], *e = d + np, *tau = e + np;
+  // pending reflectors V[s][row] and w-vectors W[s][row] of the current
+  // panel, stored by column so that threads over rows read them coalesced
+  double *Vg = panel + off[mi], *Wg = Vg + (int64_t)n * kNb;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int j = 0; j + 2 < n; ++j) {
-    const int m = n - j - 1;
-    const double *rowj = Am + (int64_t)j * np + j + 1;   // column j below the diagonal
-    double part = 0.0;
-    for (int i = tid; i < m; i += kRedThreads) {
-      const double x = rowj[i];
-      v[i] = x;
-      if (i > 0) part += x * x;
-    }
-    const double sigma = block_sum(part, red);
-    if (tid == 0) {
-      const double alpha = v[0];
-      d[j] = Am[(int64_t)j * np + j];
-      if (sigma == 0.0) {
-        s_tau = 0.0;
-        s_scal = 0.0;
-        e[j] = alpha;
-      } else {
-        const double beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
-        s_tau = (beta - alpha) / beta;
-        s_scal = 1.0 / (alpha - beta);
-        e[j] = beta;
+  for (int j0 = 0; j0 < n - 2; j0 += kNb) {
+    const int jend = min(j0 + kNb, n - 2);
+    for (int j = j0; j < jend; ++j) {
+      const int t = j - j0;
+      const int m = n - j - 1;
+      if (tid < t) {
+        vj_s[tid] = Vg[(int64_t)tid * n + j];
+        wj_s[tid] = Wg[(int64_t)tid * n + j];
       }
-      tau[j] = s_tau;
-    }
-    __syncthreads();
-    const double tj = s_tau;
-    if (tj == 0.0) continue;   // uniform: no reflection needed
-    const double sc = s_scal;
-    double *roww = Am + (int64_t)j * np + j + 1;
-    for (int i = tid; i < m; i += kRedThreads) {
-      const double vi = (i == 0) ? 1.0 : v[i] * sc;
-      v[i] = vi;
-      roww[i] = vi;   // keep the reflector for the back-transformation
-    }
-    __syncthreads();
-    // p = tau A22 v (one wave per row, lanes along the row)
-    const double *A22 = Am + (int64_t)(j + 1) * np + (j + 1);
-    for (int i = wave; i < m; i += kRedWaves) {
-      const double *ri = A22 + (int64_t)i * np;
-      double acc = 0.0;
-      for (int k = lane; k < m; k += 64) acc += ri[k] * v[k];
-      acc = wave_sum(acc);
-      if (lane == 0) w[i] = tj * acc;
-    }
-    __syncthreads();
-    double pv = 0.0;
-    for (int i = tid; i < m; i += kRedThreads) pv += w[i] * v[i];
-    const double K = -0.5 * tj * block_sum(pv, red);
-    for (int i = tid; i < m; i += kRedThreads) w[i] += K * v[i];
-    __syncthreads();
-    // A22 -= v w^T + w v^T; the two products are rounded separately and added
-    // in either order, so entries (i, k) and (k, i) stay equal
-    double *B22 = Am + (int64_t)(j + 1) * np + (j + 1);
-    for (int i = wave; i < m; i += kRedWaves) {
-      double *ri = B22 + (int64_t)i * np;
-      const double vi = v[i], wi = w[i];
-      for (int k = lane; k < m; k += 64) {
-        const double upd = __dadd_rn(__dmul_rn(vi, w[k]), __dmul_rn(wi, v[k]));
-        ri[k] = ri[k] - upd;
+      __syncthreads();
+      // column j of the partly reduced matrix: A minus the pending
+      // V W^T + W V^T of this panel (row j of A by symmetry)
+      double part = 0.0;
+      for (int i = tid; i < m; i += kRedThreads) {
+        const int64_t r = j + 1 + i;
+        double x = Am[(int64_t)j * np + r];
+        for (int s2 = 0; s2 < t; ++s2)
+          x -= Vg[(int64_t)s2 * n + r] * wj_s[s2] + Wg[(int64_t)s2 * n + r] * vj_s[s2];
+        v[i] = x;
+        if (i > 0) part += x * x;
       }
+      const double sigma = block_sum(part, red);
+      if (tid == 0) {
+        double dj = Am[(int64_t)j * np + j];
+        for (int s2 = 0; s2 < t; ++s2) dj -= 2.0 * vj_s[s2] * wj_s[s2];
+        d[j] = dj;
+        const double alpha = v[0];
+        if (sigma == 0.0) {
+          s_tau = 0.0;
+          s_scal = 0.0;
+          e[j] = alpha;
+        } else {
+          const double beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
+          s_tau = (beta - alpha) / beta;
+          s_scal = 1.0 / (alpha - beta);
+          e[j] = beta;
+        }
+        tau[j] = s_tau;
+      }
+      __syncthreads();
+      const double tj = s_tau;
+      double *vcol = Vg + (int64_t)t * n, *wcol = Wg + (int64_t)t * n;
+      if (tj == 0.0) {   // uniform: no reflection; its panel column is zero
+        for (int i = tid; i < m; i += kRedThreads) {
+          vcol[j + 1 + i] = 0.0;
+          wcol[j + 1 + i] = 0.0;
+        }
+        __syncthreads();
+        continue;
+      }
+      const double sc = s_scal;
+      for (int i = tid; i < m; i += kRedThreads) {
+        const double vi = (i == 0) ? 1.0 : v[i] * sc;
+        v[i] = vi;
+        Am[(int64_t)j * np + j + 1 + i] = vi;   // reflector, for the back-transformation
+        vcol[j + 1 + i] = vi;
+      }
+      __syncthreads();
+      // q1 = W^T v, q2 = V^T v over the earlier panel columns
+      if (wave < t) {
+        const double *vs = Vg + (int64_t)wave * n + j + 1, *ws = Wg + (int64_t)wave * n + j + 1;
+        double a1 = 0.0, a2 = 0.0;
+        for (int i = lane; i < m; i += 64) {
+          a1 += ws[i] * v[i];
+          a2 += vs[i] * v[i];
+        }
+        a1 = wave_sum(a1);
+        a2 = wave_sum(a2);
+        if (lane == 0) {
+          q1[wave] = a1;
+          q2[wave] = a2;
+        }
+      }
+      // A22 v: each wave takes four rows at a time (lanes along the rows), so
+      // four independent load streams are in flight per wave
+      const double *A22 = Am + (int64_t)(j + 1) * np + (j + 1);
+      for (int i0 = 4 * wave; i0 < m; i0 += 4 * kRedWaves) {
+        const int nr = min(4, m - i0);
+        const double *r0 = A22 + (int64_t)i0 * np;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        for (int k = lane; k < m; k += 64) {
+          const double vk = v[k];
+          a0 += r0[k] * vk;
+          if (nr > 1) a1 += r0[np + k] * vk;
+          if (nr > 2) a2 += r0[2 * (int64_t)np + k] * vk;
+          if (nr > 3) a3 += r0[3 * (int64_t)np + k] * vk;
+        }
+        a0 = wave_sum(a0);
+        a1 = wave_sum(a1);
+        a2 = wave_sum(a2);
+        a3 = wave_sum(a3);
+        if (lane == 0) {
+          w[i0] = a0;
+          if (nr > 1) w[i0 + 1] = a1;
+          if (nr > 2) w[i0 + 2] = a2;
+          if (nr > 3) w[i0 + 3] = a3;
+        }
+      }
+      __syncthreads();
+      // p = tau (A22 v - V q1 - W q2)
+      double pvp = 0.0;
+      for (int i = tid; i < m; i += kRedThreads) {
+        const int64_t r = j + 1 + i;
+        double acc = w[i];
+        for (int s2 = 0; s2 < t; ++s2)
+          acc -= Vg[(int64_t)s2 * n + r] * q1[s2] + Wg[(int64_t)s2 * n + r] * q2[s2];
+        acc *= tj;
+        w[i] = acc;
+        pvp += acc * v[i];
+      }
+      const double K = -0.5 * tj * block_sum(pvp, red);
+      for (int i = tid; i < m; i += kRedThreads) wcol[j + 1 + i] = w[i] + K * v[i];
+      __syncthreads();
     }
-    __syncthreads();
+    // trailing matrix (rows and columns >= jend) -= V W^T + W V^T; each term
+    // pairs the same two rounded products for (r, c) and (c, r), so A stays
+    // exactly symmetric
+    const int tp = jend - j0;
+    for (int c0 = jend; c0 < n; c0 += 64) {
+      for (int e2 = tid; e2 < 64 * tp; e2 += kRedThreads) {
+        const int s2 = e2 / 64, cl = e2 % 64;
+        const int c = c0 + cl;
+        pv_s[s2][cl] = c < n ? Vg[(int64_t)s2 * n + c] : 0.0;
+        pw_s[s2][cl] = c < n ? Wg[(int64_t)s2 * n + c] : 0.0;
+      }
+      __syncthreads();
+      const int c = c0 + lane;
+      // four rows per wave at a time: their loads are independent
+      for (int r0 = jend + 4 * wave; r0 < n; r0 += 4 * kRedWaves) {
+        if (c < n) {
+          double u[4] = {0.0, 0.0, 0.0, 0.0};
+          for (int s2 = 0; s2 < tp; ++s2) {
+            const double pw = pw_s[s2][lane], pv = pv_s[s2][lane];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int r = min(r0 + q, n - 1);
+              u[q] = __dadd_rn(u[q], __dadd_rn(__dmul_rn(Vg[(int64_t)s2 * n + r], pw),
+                                               __dmul_rn(Wg[(int64_t)s2 * n + r], pv)));
+            }
+          }
+          double av[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            av[q] = r0 + q < n ? Am[(int64_t)(r0 + q) * np + c] : 0.0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (r0 + q < n) Am[(int64_t)(r0 + q) * np + c] = av[q] - u[q];
+        }
+      }
+      __syncthreads();
+    }
   }
   if (tid == 0) {
     if (n >= 2) {
@@ -378,24 +481,26 @@ __global__ __launch_bounds__(kInvThreads) void tri_invit_kernel(int nmat, int ns
 
 // Eigenvalues to diag(A); the leading kq eigenvectors of A = H Y, with
 // H = H_0 H_1 ... H_{n-3} (the last reflector applied first), written to V.
+// Columns are independent: workgroup (x, mi) takes columns x*16 .. x*16+15,
+// one per wave, so the waves never wait for each other.
 constexpr int kBackThreads = 1024;
+constexpr int kBackCols = kBackThreads / 64;
 
 __global__ __launch_bounds__(kBackThreads) void tri_back_kernel(
     int nmat, int nsec, const int32_t *sec_n, const int32_t *npad, const int64_t *off,
     double *A, const double *work, double *V, double *Y, int kmax) {
-  const int mi = blockIdx.x;
+  const int mi = blockIdx.y;
   if (mi >= nmat) return;
   const int n = sec_n[mi % nsec];
   const int np = npad[mi];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  constexpr int nwv = kBackThreads / 64;
   const double *dg = work + off[mi], *tau = dg + 2 * np, *lam = dg + 3 * np;
   double *Am = A + off[mi];
   double *Vm = V + off[mi];
   double *Ym = Y + off[mi];   // Y[c * np + r], c < kq
   const int kq = min(min(n, kmax), kMaxKq);
-  // each wave owns whole columns of Y: no waiting between waves here
-  for (int c = wave; c < kq; c += nwv) {
+  const int c = blockIdx.x * kBackCols + wave;
+  if (c < kq) {
     double *yc = Ym + (int64_t)c * np;
     for (int j = n - 3; j >= 0; --j) {
       const double tj = tau[j];
@@ -407,16 +512,19 @@ __global__ __launch_bounds__(kBackThreads) void tri_back_kernel(
       const double sdot = tj * wave_sum(acc);
       for (int i = lane; i < m; i += 64) yc[j + 1 + i] -= sdot * vj[i];
     }
+    for (int r = lane; r < n; r += 64) Vm[(int64_t)r * np + c] = yc[r];
   }
-  __syncthreads();
-  // outputs: V row-major (columns >= kq zero), eigenvalues on diag(A)
-  for (int64_t el = tid; el < (int64_t)n * np; el += kBackThreads) {
-    const int r = (int)(el / np), c = (int)(el % np);
-    Vm[el] = (c < kq && r < n) ? Ym[(int64_t)c * np + r] : 0.0;
+  if (blockIdx.x == 0) {
+    // columns kq .. np-1 of V are zero; eigenvalues on diag(A). The
+    // reflectors in A lie right of the diagonal, apart from these writes.
+    for (int64_t el = tid; el < (int64_t)n * (np - kq); el += kBackThreads) {
+      const int r = (int)(el / (np - kq)), cc = kq + (int)(el % (np - kq));
+      Vm[(int64_t)r * np + cc] = 0.0;
+    }
+    __syncthreads();
+    for (int cc = tid; cc < np; cc += kBackThreads)
+      Am[(int64_t)cc * np + cc] = cc < n ? lam[cc] : -1.0;
   }
-  __syncthreads();
-  for (int c = tid; c < np; c += kBackThreads)
-    Am[(int64_t)c * np + c] = c < n ? lam[c] : -1.0;
 }
 
 }  // namespace
@@ -426,8 +534,9 @@ void launch_tri_eig(int nmat, int nsec, const int32_t *d_sec_n, const int32_t *d
                     int32_t *d_status, int kmax, hipStream_t s) {
   (void)d_status;
   if (kmax > kMaxKq) fail(GXY_EUNSUPPORTED, "tridiagonal path: more than 128 vectors");
+  // Y serves as the panel scratch of the reduction (2 n kNb <= npad^2)
   hipLaunchKernelGGL(tri_reduce_kernel, dim3(nmat), dim3(kRedThreads), 0, s, nmat, nsec,
-                     d_sec_n, d_npad, d_off, A, work);
+                     d_sec_n, d_npad, d_off, A, work, Y);
   GXY_CHECK_LAUNCH();
   hipLaunchKernelGGL(tri_bisect_kernel, dim3(kTriMaxN / kBisThreads, nmat), dim3(kBisThreads),
                      0, s, nmat, nsec, d_sec_n, d_npad, d_off, work);
@@ -439,8 +548,9 @@ void launch_tri_eig(int nmat, int nsec, const int32_t *d_sec_n, const int32_t *d
   hipLaunchKernelGGL(tri_invit_kernel, dim3(nmat), dim3(kInvThreads), 0, s, nmat, nsec,
                      d_sec_n, d_npad, d_off, work, V, Y, kmax);
   GXY_CHECK_LAUNCH();
-  hipLaunchKernelGGL(tri_back_kernel, dim3(nmat), dim3(kBackThreads), 0, s, nmat, nsec,
-                     d_sec_n, d_npad, d_off, A, work, V, Y, kmax);
+  const int nx = (std::min(kmax, kMaxKq) + kBackCols - 1) / kBackCols;
+  hipLaunchKernelGGL(tri_back_kernel, dim3(std::max(nx, 1), nmat), dim3(kBackThreads), 0, s,
+                     nmat, nsec, d_sec_n, d_npad, d_off, A, work, V, Y, kmax);
   GXY_CHECK_LAUNCH();
 }
 

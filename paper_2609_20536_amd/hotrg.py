@@ -110,6 +110,8 @@ def load_library(path: str = LIB_PATH):
                           P(C.c_double), C.c_int32, P(C.c_double), C.c_int32, P(C.c_double)],
         "gxy_test_eigh_method": [C.c_void_p, C.c_int32, C.c_int32, P(C.c_double),
                                  P(C.c_double), P(C.c_double), P(C.c_int32)],
+        "gxy_test_eigh_top": [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, P(C.c_double),
+                              P(C.c_double), P(C.c_double), P(C.c_int32)],
         "gxy_test_eigh": [C.c_void_p, C.c_int32, P(C.c_double), P(C.c_double),
                           P(C.c_double), P(C.c_int32)],
         "gxy_test_mfma_layout": [C.c_void_p, P(C.c_double), P(C.c_double), P(C.c_double)],
@@ -332,9 +334,10 @@ class Context:
         self._check(rc, self.handle)
         return out
 
-    def test_eigh(self, A, method=0):
+    def test_eigh(self, A, method=0, kmax=None):
         """Eigenpairs of one symmetric matrix by the batched sector solver
-        (method 0: as a run chooses, 1: block Jacobi, 2: tridiagonal QL)."""
+        (method 0: as a run chooses, 1: block Jacobi, 2: tridiagonal path);
+        kmax: only the leading kmax eigenvectors are required."""
         import numpy as np
         A = np.ascontiguousarray(A, dtype=np.float64)
         n = A.shape[0]
@@ -346,8 +349,9 @@ class Context:
                             + 4 * (n + 16 * q * q + 256) + (1 << 20))
         dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))  # noqa: E731
         sw = C.c_int32(0)
-        self._check(self.lib.gxy_test_eigh_method(self.handle, int(method), n, dp(A), dp(w),
-                                                  dp(V), C.byref(sw)), self.handle)
+        k = n if kmax is None else int(kmax)
+        self._check(self.lib.gxy_test_eigh_top(self.handle, int(method), n, k, dp(A), dp(w),
+                                               dp(V), C.byref(sw)), self.handle)
         self.last_sweeps = sw.value
         return w, V
 

@@ -222,6 +222,27 @@ def test_eigh_diagonal_and_block(ctx, method):
     _check_eig(B, w, V)
 
 
+@pytest.mark.parametrize("n,kmax", [(300, 64), (513, 48), (777, 128), (1024, 64)])
+def test_tridiagonal_leading_vectors_of_large_sectors(ctx, n, kmax):
+    """Sector sizes of Dcut = 64 runs: all eigenvalues, the kmax leading
+    eigenvectors (residual and orthogonality at eps ||A||), graded spectrum."""
+    rng = np.random.default_rng(n)
+    Q = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    lam = np.exp(-np.linspace(0.0, 30.0, n))
+    lam[n // 3: n // 3 + 2] = lam[n // 3]                      # a degenerate pair
+    A = (Q * lam) @ Q.T
+    A = 0.5 * (A + A.T)
+    w, V = ctx.test_eigh(A, 2, kmax=kmax)
+    assert ctx.last_sweeps == 0                                # tridiagonal path taken
+    wr = np.sort(np.linalg.eigvalsh(A))[::-1]
+    scale = wr[0]
+    assert np.max(np.abs(w - wr)) <= 5e-15 * n * scale
+    Vk = V[:, :kmax]
+    assert np.max(np.abs(A @ Vk - Vk * w[:kmax])) <= 5e-14 * n ** 0.5 * scale
+    assert np.max(np.abs(Vk.T @ Vk - np.eye(kmax))) <= 1e-12
+    assert not np.any(V[:, kmax:])
+
+
 def test_tridiagonal_eigenvalues_sorted_decreasing(ctx):
     rng = np.random.default_rng(3)
     X = rng.standard_normal((90, 95))
