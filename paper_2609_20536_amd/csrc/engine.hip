@@ -38,6 +38,9 @@ namespace gxy {
 constexpr double kTieRel = 1e-12;
 constexpr double kSideTol = 1e-10;
 constexpr int kMaxSweeps = 120;
+// pinned host staging (1 MiB): the block-order table of a step goes here
+constexpr int64_t kPermPinnedOffset = 131072;   // in int32 units (512 KiB)
+constexpr int64_t kPermPinnedInts = 65536;
 constexpr int kLmax = 50;
 
 enum Sym { SYM_U1 = 0, SYM_NONE = 1, SYM_Z2 = 2 };
@@ -83,6 +86,7 @@ struct Plan {
   int64_t maxPD = 0;      // largest P (nf * dn)
   int maxDn = 0;
   int64_t chunk_elems = 0;  // X / Y chunk buffer elements
+  int64_t maxW = 0;         // largest fused (horizontal, vertical) dimension
   int nimp = 0;
   int64_t tab_env = 0, tab_proj = 0;  // offset-table entries (bounds)
   int64_t grp_env = 0, grp_proj = 0;  // group descriptors (bounds)
@@ -112,6 +116,7 @@ static Plan make_plan(const gxy_point &p, size_t chunk_bytes) {
     pl.maxPD = std::max(pl.maxPD, nf * sd.dn);
     pl.maxDn = std::max(pl.maxDn, sd.dn);
     per_a_max = std::max(per_a_max, (int64_t)sd.dh * sd.dv * sd.dh * sd.dv);
+    pl.maxW = std::max(pl.maxW, (int64_t)sd.dh * sd.dv);
     if (xs)
       Dv = sd.dn;
     else
@@ -164,6 +169,7 @@ struct Buffers {
   double *coef;                    // t, F, FM, FM1
   double *scal;                    // traces and result
   int64_t *tab_env, *tab_proj;     // charge-block offset tables
+  int32_t *perm;                   // inverse block order of the fused index
   GGroup *grp_env, *grp_proj;
   int64_t eig_elems, eig_q;
   int64_t sel_cap;
@@ -223,6 +229,7 @@ static size_t carve(const gxy_point &p, const Plan &pl, Carver &c, Buffers &b) {
   b.coef = c.take<double>(pl.d0 + 3 * (2 * qmax + 1));
   b.scal = c.take<double>(16);
   b.tab_env = c.take<int64_t>(pl.tab_env);
+  b.perm = c.take<int32_t>(std::max<int64_t>(pl.maxW, 1));
   b.tab_proj = c.take<int64_t>(pl.tab_proj);
   b.grp_env = c.take<GGroup>(pl.grp_env);
   b.grp_proj = c.take<GGroup>(pl.grp_proj);
@@ -1030,8 +1037,22 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
     }
     // ---- projection T' = P^T M P (and impurities), chunked over a ----
     tm.begin();
-    launch_swap_middle(b.T, b.T2, Dh, Dh, Dv, Dv, s);
-    for (int k = 0; k < nimp; ++k) launch_swap_middle(b.TX[k], b.TX2[k], Dh, Dh, Dv, Dv, s);
+    // bottom operands of the D^7 product: dense path [l][u][r][d]; charge
+    // blocks: both fused indices in block order (see plan.h)
+    StepLegs blk{Dh, Dv, 0, mod, lh, lv, {}};
+    if (sym == SYM_NONE) {
+      launch_swap_middle(b.T, b.T2, Dh, Dh, Dv, Dv, s);
+      for (int k = 0; k < nimp; ++k) launch_swap_middle(b.TX[k], b.TX2[k], Dh, Dh, Dv, Dv, s);
+    } else {
+      block_positions(blk);
+      const int64_t Wn = (int64_t)Dh * Dv;
+      if (Wn > pl.maxW || Wn > (int64_t)kPermPinnedInts) fail(GXY_ENOMEM, "block order table bound");
+      int32_t *hperm = hp + kPermPinnedOffset;
+      for (int64_t f = 0; f < Wn; ++f) hperm[blk.pos[f]] = (int32_t)f;
+      GXY_HIP(hipMemcpyAsync(b.perm, hperm, Wn * sizeof(int32_t), hipMemcpyHostToDevice, s));
+      launch_block_gather(b.T, b.T2, b.perm, Dh, Dv, s);
+      for (int k = 0; k < nimp; ++k) launch_block_gather(b.TX[k], b.TX2[k], b.perm, Dh, Dv, s);
+    }
     const int64_t per_a = (int64_t)Dh * Dv * Dh * Dv;
     const int ac_max = (int)std::max<int64_t>(1, std::min<int64_t>(Dn, pl.chunk_elems / per_a));
     const double W = (double)Dh * Dv;
@@ -1067,7 +1088,9 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
         const auto it = ctx->tile_for_dcut.find(p.dcut);
         if (it != ctx->tile_for_dcut.end()) proj_tile = it->second;
       }
-      const StepLegs SL{Dh, Dv, Dn, mod, lh, lv, new_lh, proj_tile};
+      StepLegs SL{Dh, Dv, Dn, mod, lh, lv, new_lh, proj_tile};
+      SL.pos = blk.pos;
+      SL.vrank = blk.vrank;
       const QSet s0{0};
       struct Part {
         int a0 = 0, ac = 0, k = -1;  // k = -1: pure tensor; else impurity k

@@ -141,6 +141,10 @@ void launch_swap_pairs(const double *in, double *out, int A, int B, int C,
 // out[a][c][b][d] = in[a][b][c][d]
 void launch_swap_middle(const double *in, double *out, int A, int B, int C,
                         int D, hipStream_t s);
+// out[P1 * W + P2] = in[l][r][u][d], (l, u) = pinv[P1], (r, d) = pinv[P2]
+// with pinv[P] = h * Dv + v and W = Dh * Dv.
+void launch_block_gather(const double *in, double *out, const int32_t *pinv, int Dh, int Dv,
+                         hipStream_t s);
 // out[0] += sum_{l,u} T[l][l][u][u] (out zeroed first)
 void launch_trace(const double *T, int Dh, int Dv, double *out, hipStream_t s);
 // fill

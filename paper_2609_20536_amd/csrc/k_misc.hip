@@ -86,6 +86,20 @@ __global__ void swap_middle_kernel(const double *in, double *out, int A, int B,
   }
 }
 
+// out[P1 * W + P2] = in[l][r][u][d] with (l, u) = pinv[P1], (r, d) = pinv[P2]
+// (pinv[P] = h * Dv + v, W = Dh * Dv): the bottom operand of the D^7 product
+// with both fused indices in block order.
+__global__ void block_gather_kernel(const double *in, double *out, const int32_t *pinv, int Dh,
+                                    int Dv) {
+  const int64_t W = (int64_t)Dh * Dv, total = W * W;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const int f1 = pinv[e / W], f2 = pinv[e % W];
+    const int l = f1 / Dv, u = f1 % Dv, r = f2 / Dv, d = f2 % Dv;
+    out[e] = in[(((int64_t)l * Dh + r) * Dv + u) * Dv + d];
+  }
+}
+
 __global__ void trace_kernel(const double *T, int Dh, int Dv, double *out) {
   __shared__ double red[kRedThreads];
   double acc = 0.0;
@@ -423,6 +437,14 @@ void launch_swap_middle(const double *in, double *out, int A, int B, int C, int 
   const int64_t n = (int64_t)A * B * C * D;
   hipLaunchKernelGGL(swap_middle_kernel, dim3(grid_for(n)), dim3(256), 0, s, in, out,
                      A, B, C, D);
+  GXY_CHECK_LAUNCH();
+}
+
+void launch_block_gather(const double *in, double *out, const int32_t *pinv, int Dh, int Dv,
+                         hipStream_t s) {
+  const int64_t n = (int64_t)Dh * Dv * Dh * Dv;
+  hipLaunchKernelGGL(block_gather_kernel, dim3(grid_for(n)), dim3(256), 0, s, in, out, pinv, Dh,
+                     Dv);
   GXY_CHECK_LAUNCH();
 }
 

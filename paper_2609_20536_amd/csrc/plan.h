@@ -52,17 +52,30 @@ struct StepLegs {
   int Dh, Dv, Dn, mod;
   std::vector<int> lh, lv, ln;  // labels of l/r legs, u/d legs, new a/b legs
   int tile = 0;  // projection tiles: 0 = chosen by tile fill, else 64 or 128
+  // Block order of a fused (horizontal h, vertical v) index: grouped by
+  // kappa = q_h - q_v (ascending), then h, then v. pos[h * Dv + v] is the
+  // position in that order; vrank[v] is v's rank among the vertical indices
+  // of its label, so that pos(h, v) = pos(h, v0) + vrank[v] - vrank[v0] for
+  // v, v0 of one label. Filled by block_positions.
+  std::vector<int64_t> pos;
+  std::vector<int32_t> vrank;
 };
+
+// Fills L.pos and L.vrank from the leg labels.
+void block_positions(StepLegs &L);
 
 // Environment Gram matrices of one side (right = false: E_L, else E_R):
 // three launches (top Gram, bottom Gram, E). Output layouts as in the dense
 // path: env [(x, i), (x', i')] with row length Dh*Dv; E [nf x nf].
 void plan_env(const StepLegs &L, bool right, TablePlan &tp, Launch out[3]);
 
-// Projection factors for output columns a in [a0, a1):
-//  X[a-a0][r1][u][l2][i] = sum_l1 P[(l1,l2),a] A[l1][r1][u][i]      (A in sA)
-//  Y[(a-a0,r1,u),(r2,d)] = sum_(l2,i) X[..] B2[(l2,i),(r2,d)]       (B in sB)
-//  T'[a][b][u][d]     += alpha sum_(r1,r2) Y[(a-a0,r1,u),(r2,d)] P[(r1,r2),b]
+// Projection factors for output columns a in [a0, a1), with the fused
+// (l2, i) and (r2, d) indices stored in block order (pos):
+//  X[a-a0][r1][u][pos(l2,i)] = sum_l1 P[(l1,l2),a] A[l1][r1][u][i]    (A in sA)
+//  Y[a-a0][r1][u][pos(r2,d)] = sum_(l2,i) X[..][pos(l2,i)] B2[pos(l2,i)][pos(r2,d)]
+//  T'[a][b][u][d]     += alpha sum_(r1,r2) Y[a-a0][r1][u][pos(r2,d)] P[(r1,r2),b]
+// with B2[pos(l2,i)][pos(r2,d)] = B[l2][r2][i][d] (B in sB). Every charge
+// block of the D^7 product Y = X B2 then reads and writes contiguous rows.
 Launch plan_proj_x(const StepLegs &L, int a0, int a1, const QSet &sA, TablePlan &tp);
 Launch plan_proj_y(const StepLegs &L, int a0, int a1, const QSet &sA, const QSet &sB,
                    TablePlan &tp);

@@ -7,6 +7,20 @@
 
 namespace gxy {
 
+void block_positions(StepLegs &L) {
+  const int Dh = L.Dh, Dv = L.Dv;
+  L.pos.assign((size_t)Dh * Dv, 0);
+  L.vrank.assign(Dv, 0);
+  std::map<int, int> seen;
+  for (int v = 0; v < Dv; ++v) L.vrank[v] = seen[qnorm(L.lv[v], L.mod)]++;
+  std::map<int, std::vector<int64_t>> by_kappa;   // fused h * Dv + v, h then v
+  for (int h = 0; h < Dh; ++h)
+    for (int v = 0; v < Dv; ++v) by_kappa[qnorm(L.lh[h] - L.lv[v], L.mod)].push_back((int64_t)h * Dv + v);
+  int64_t at = 0;
+  for (const auto &kv : by_kappa)
+    for (int64_t f : kv.second) L.pos[f] = at++;
+}
+
 QSet qset_negate(const QSet &s, int mod) {
   QSet o;
   for (int x : s) o.push_back(qnorm(-x, mod));
@@ -215,53 +229,62 @@ void plan_env(const StepLegs &S, bool right, TablePlan &tp, Launch out[3]) {
 
 Launch plan_proj_x(const StepLegs &S, int a0, int a1, const QSet &sA, TablePlan &tp) {
   const int Dh = S.Dh, Dv = S.Dv, Dn = S.Dn, mod = S.mod;
-  const int64_t per_a = (int64_t)Dh * Dv * Dh * Dv;
+  const int64_t W = (int64_t)Dh * Dv, per_a = W * W;
   const auto l1s = leg_buckets(S.lh, mod);
   // rows (a, l2) keyed by c = q_a - q_l2 (= q_l1); a varies fastest
   std::map<int, std::vector<PI>> rows;
   for (int l2 = 0; l2 < Dh; ++l2)
     for (int a = a0; a < a1; ++a) rows[qnorm(S.ln[a] - S.lh[l2], mod)].push_back(PI(a, l2));
-  // columns (r1, u, i) keyed by kc = q_r1 + q_u - q_i; group c takes the
-  // columns with c - kc in sA
-  std::map<int, std::pair<std::vector<int64_t>, std::vector<int64_t>>> cols;
+  // columns (r1, u, i) keyed by (kc = q_r1 + q_u - q_i, q_i); group (c, q_i)
+  // takes the columns with c - kc in sA. With q_i fixed, the output offset
+  // splits into a row part (pos of (l2, first i of the label)) and a column
+  // part (r1, u, rank of i in its label).
+  std::map<std::pair<int, int>, std::pair<std::vector<int64_t>, std::vector<int64_t>>> cols;
+  std::map<int, int> first_of;   // label -> first vertical index with it
+  for (int i = Dv - 1; i >= 0; --i) first_of[qnorm(S.lv[i], mod)] = i;
   for (int r1 = 0; r1 < Dh; ++r1)
     for (int u = 0; u < Dv; ++u)
       for (int i = 0; i < Dv; ++i) {
-        auto &c = cols[qnorm(S.lh[r1] + S.lv[u] - S.lv[i], mod)];
+        const int qi = qnorm(S.lv[i], mod);
+        auto &c = cols[std::make_pair(qnorm(S.lh[r1] + S.lv[u] - S.lv[i], mod), qi)];
         c.first.push_back((int64_t)r1 * Dv * Dv + (int64_t)u * Dv + i);
-        c.second.push_back((int64_t)r1 * Dv * Dh * Dv + (int64_t)u * Dh * Dv + i);
+        c.second.push_back((int64_t)r1 * Dv * W + (int64_t)u * W + S.vrank[i]);
       }
   std::vector<GSpec> gs;
   for (const auto &kv : rows) {
     const int c = kv.first;
-    std::vector<int64_t> ar, ac, br, bc, cr, cc;
-    for (const PI &p : kv.second) {
-      ar.push_back((int64_t)p.second * Dn + p.first);
-      cr.push_back((int64_t)(p.first - a0) * per_a + (int64_t)p.second * Dv);
-    }
+    std::vector<int64_t> ar, ac, br;
+    for (const PI &p : kv.second) ar.push_back((int64_t)p.second * Dn + p.first);
     auto il = l1s.find(c);
     if (il != l1s.end())
       for (int l1 : il->second) {
         ac.push_back((int64_t)l1 * Dh * Dn);
         br.push_back((int64_t)l1 * Dh * Dv * Dv);
       }
-    for (int sv : sA) {
-      auto ic = cols.find(qnorm(c - sv, mod));
-      if (ic == cols.end()) continue;
-      bc.insert(bc.end(), ic->second.first.begin(), ic->second.first.end());
-      cc.insert(cc.end(), ic->second.second.begin(), ic->second.second.end());
+    for (const auto &fq : first_of) {
+      const int qi = fq.first, i0 = fq.second;
+      std::vector<int64_t> bc, cc, cr;
+      for (int sv : sA) {
+        auto ic = cols.find(std::make_pair(qnorm(c - sv, mod), qi));
+        if (ic == cols.end()) continue;
+        bc.insert(bc.end(), ic->second.first.begin(), ic->second.first.end());
+        cc.insert(cc.end(), ic->second.second.begin(), ic->second.second.end());
+      }
+      if (bc.empty()) continue;
+      for (const PI &p : kv.second)
+        cr.push_back((int64_t)(p.first - a0) * per_a + S.pos[(size_t)p.second * Dv + i0]);
+      GSpec g;
+      g.M = (int32_t)ar.size();
+      g.N = (int32_t)bc.size();
+      g.K = (int32_t)ac.size();
+      g.ar = put(tp, ar);
+      g.ac = put(tp, ac);
+      g.br = put(tp, br);
+      g.bc = put(tp, bc);
+      g.cr = put(tp, cr);
+      g.cc = put(tp, cc);
+      gs.push_back(g);
     }
-    GSpec g;
-    g.M = (int32_t)ar.size();
-    g.N = (int32_t)bc.size();
-    g.K = (int32_t)ac.size();
-    g.ar = put(tp, ar);
-    g.ac = put(tp, ac);
-    g.br = put(tp, br);
-    g.bc = put(tp, bc);
-    g.cr = put(tp, cr);
-    g.cc = put(tp, cc);
-    gs.push_back(g);
   }
   return finish_launch(tp, gs, false, true, S.tile);
 }
@@ -278,12 +301,13 @@ Launch plan_proj_y(const StepLegs &S, int a0, int a1, const QSet &sA, const QSet
       for (int u = 0; u < Dv; ++u)
         rows_by_rho[qnorm(S.ln[a] - S.lh[r1] - S.lv[u], mod)].push_back(
             (((int64_t)(a - a0) * Dh + r1) * Dv + u) * W);
+  // (l2, i) and (r2, d) in block order: each kappa (nu) is one contiguous range
   for (int l2 = 0; l2 < Dh; ++l2)
     for (int i = 0; i < Dv; ++i)
-      ks_by_kappa[qnorm(S.lh[l2] - S.lv[i], mod)].push_back((int64_t)l2 * Dv + i);
+      ks_by_kappa[qnorm(S.lh[l2] - S.lv[i], mod)].push_back(S.pos[(size_t)l2 * Dv + i]);
   for (int r2 = 0; r2 < Dh; ++r2)
     for (int d = 0; d < Dv; ++d)
-      cols_by_nu[qnorm(S.lh[r2] - S.lv[d], mod)].push_back((int64_t)r2 * Dv + d);
+      cols_by_nu[qnorm(S.lh[r2] - S.lv[d], mod)].push_back(S.pos[(size_t)r2 * Dv + d]);
   std::vector<int> kappas;
   for (const auto &kv : rows_by_rho)
     for (int s : sA) kappas.push_back(qnorm(kv.first - s, mod));
@@ -324,47 +348,57 @@ Launch plan_proj_t(const StepLegs &S, int a0, int a1, const QSet &sY, TablePlan 
   const int64_t W = (int64_t)Dh * Dv, per_a = W * W;
   const auto bs = leg_buckets(S.ln, mod);
   const PairBuckets ks = pair_buckets(S.lh, S.lh, 1, 1, mod);  // q_r1 + q_r2
-  // rows (a, u, d) keyed by w = q_a - q_u + q_d; group sigma takes the rows
-  // with w - sigma in sY
-  std::map<int, std::pair<std::vector<int64_t>, std::vector<int64_t>>> rows;
+  // rows (a, u, d) keyed by (w = q_a - q_u + q_d, q_d); group (sigma, q_d)
+  // takes the rows with w - sigma in sY. With q_d fixed, Y's offset splits
+  // into a reduction part (r1, pos of (r2, first d of the label)) and a row
+  // part (a, u, rank of d in its label).
+  std::map<std::pair<int, int>, std::pair<std::vector<int64_t>, std::vector<int64_t>>> rows;
+  std::map<int, int> first_of;
+  for (int d = Dv - 1; d >= 0; --d) first_of[qnorm(S.lv[d], mod)] = d;
   for (int a = a0; a < a1; ++a)
     for (int u = 0; u < Dv; ++u)
       for (int d = 0; d < Dv; ++d) {
-        auto &r = rows[qnorm(S.ln[a] - S.lv[u] + S.lv[d], mod)];
-        r.first.push_back((int64_t)(a - a0) * per_a + (int64_t)u * W + d);
+        const int qd = qnorm(S.lv[d], mod);
+        auto &r = rows[std::make_pair(qnorm(S.ln[a] - S.lv[u] + S.lv[d], mod), qd)];
+        r.first.push_back((int64_t)(a - a0) * per_a + (int64_t)u * W + S.vrank[d]);
         r.second.push_back((int64_t)a * Dn * Dv * Dv + (int64_t)u * Dv + d);
       }
   std::vector<GSpec> gs;
   for (const auto &kv : bs) {
     const int sigma = kv.first;
-    std::vector<int64_t> ar, ac, br, bc, cr, cc;
-    for (int sv : sY) {
-      auto ir = rows.find(qnorm(sigma + sv, mod));
-      if (ir == rows.end()) continue;
-      ar.insert(ar.end(), ir->second.first.begin(), ir->second.first.end());
-      cr.insert(cr.end(), ir->second.second.begin(), ir->second.second.end());
-    }
+    std::vector<int64_t> br, bc, cc;
     auto ik = ks.find(sigma);
     if (ik != ks.end())
-      for (const PI &p : ik->second) {
-        ac.push_back((int64_t)p.first * Dv * W + (int64_t)p.second * Dv);
-        br.push_back(((int64_t)p.first * Dh + p.second) * Dn);
-      }
+      for (const PI &p : ik->second) br.push_back(((int64_t)p.first * Dh + p.second) * Dn);
     for (int b : kv.second) {
       bc.push_back(b);
       cc.push_back((int64_t)b * Dv * Dv);
     }
-    GSpec g;
-    g.M = (int32_t)ar.size();
-    g.N = (int32_t)bc.size();
-    g.K = (int32_t)ac.size();
-    g.ar = put(tp, ar);
-    g.ac = put(tp, ac);
-    g.br = put(tp, br);
-    g.bc = put(tp, bc);
-    g.cr = put(tp, cr);
-    g.cc = put(tp, cc);
-    gs.push_back(g);
+    for (const auto &fq : first_of) {
+      const int qd = fq.first, d0 = fq.second;
+      std::vector<int64_t> ar, cr, ac;
+      for (int sv : sY) {
+        auto ir = rows.find(std::make_pair(qnorm(sigma + sv, mod), qd));
+        if (ir == rows.end()) continue;
+        ar.insert(ar.end(), ir->second.first.begin(), ir->second.first.end());
+        cr.insert(cr.end(), ir->second.second.begin(), ir->second.second.end());
+      }
+      if (ar.empty()) continue;
+      if (ik != ks.end())
+        for (const PI &p : ik->second)
+          ac.push_back((int64_t)p.first * Dv * W + S.pos[(size_t)p.second * Dv + d0]);
+      GSpec g;
+      g.M = (int32_t)ar.size();
+      g.N = (int32_t)bc.size();
+      g.K = (int32_t)ac.size();
+      g.ar = put(tp, ar);
+      g.ac = put(tp, ac);
+      g.br = put(tp, br);
+      g.bc = put(tp, bc);
+      g.cr = put(tp, cr);
+      g.cc = put(tp, cc);
+      gs.push_back(g);
+    }
   }
   return finish_launch(tp, gs, false, true, S.tile);
 }
