@@ -213,6 +213,10 @@ def main():
     def note(msg):
         print(msg, file=sys.stderr, flush=True)
 
+    # projection tile for this Dcut, chosen by measurement (before any timing)
+    tuned = ctx.autotune(pt.with_(nsteps=8, impurities=0), [pt.dcut])
+    note(f"bench: tile autotuner: {tuned}")
+
     for i in range(args.warmup):
         t1 = time.perf_counter()
         ctx.run(pt)

@@ -653,6 +653,16 @@ struct SectorSolve {
   EigBatch eb;
   const int32_t *d_idx, *d_start, *d_n, *d_lab;
   int sweeps, sweeps2;  // block-Jacobi sweeps of the two stages
+  // tridiagonal path: eigenvalues are on diag(eb.A); the vectors are formed by
+  // vectors(d_side) once the side is known (d_side null: both sides)
+  bool vectors_pending = false;
+  int nmat = 0, nsec = 0, kmax = 0;
+  double *Y = nullptr, *work = nullptr;
+  void vectors(const double *d_side, hipStream_t s) const {
+    if (!vectors_pending) return;
+    launch_tri_vectors(nmat, nsec, d_n, eb.d_npad, eb.d_off, eb.A, eb.V, Y, work, kmax, d_side,
+                       s);
+  }
 };
 
 // Which batched eigensolver: where every sector has at most kTriMaxN rows and
@@ -744,21 +754,22 @@ static SectorSolve solve_sectors(gxy_ctx *ctx, hipStream_t s, const double *E, i
   for (int k = 0; k < nsec; ++k) maxn = std::max(maxn, (int)sec.n[k]);
   if (method == EIG_AUTO) method = eig_method_env();
   if (method != EIG_JACOBI && maxn <= kTriMaxN && std::min(kmax, maxn) <= kTriMaxVecs) {
-    // Householder tridiagonalisation + implicit QL + back-transformation
+    // Householder tridiagonalisation + bisection now; inverse iteration and
+    // back-transformation later, for the chosen side only
     EigBatch eg = eb;
     eg.V = nullptr;
     launch_eig_gather(E, nf, r.d_idx, r.d_start, r.d_n, nsec, eg, s);
-    launch_fill_i32(m.flags, nmat, 0, s);
-    launch_tri_eig(nmat, nsec, r.d_n, eb.d_npad, eb.d_off, m.A, m.V, m.B1, m.B2, m.flags,
-                   std::max(1, kmax), s);
-    GXY_HIP(hipMemcpyAsync(hp, m.flags, nmat * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    GXY_HIP(hipStreamSynchronize(s));
-    for (int k = 0; k < nmat; ++k)
-      if (hp[k]) fail(GXY_ENUMERIC, "tridiagonal QL did not converge");
+    launch_tri_values(nmat, nsec, r.d_n, eb.d_npad, eb.d_off, m.A, m.B1, m.B2, s);
     r.eb.A = m.A;
     r.eb.V = m.V;
     r.sweeps = 0;
     r.sweeps2 = 0;
+    r.vectors_pending = true;
+    r.nmat = nmat;
+    r.nsec = nsec;
+    r.kmax = std::max(1, kmax);
+    r.Y = m.B1;
+    r.work = m.B2;
     return r;
   }
   // batched products over the padded matrices: C = A B and C = A^T B
@@ -1013,6 +1024,7 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
       sa.d_pick_label = b.pick + 2 * Dn;
       sa.d_diag = b.diag;
       launch_select(sa, s);
+      sv.vectors(b.diag + 2, s);   // diag[2] = chosen side
       launch_build_projector(eb.V, eb.d_off, eb.d_npad, d_idx, d_start, d_n, b.pick,
                              b.pick + Dn, b.diag, nsec, (int)nf, Dn, b.P, s);
       GXY_HIP(hipMemcpyAsync(hp, b.pick + 2 * Dn, Dn * sizeof(int32_t),
@@ -1690,6 +1702,7 @@ gxy_status gxy_test_eigh_top(gxy_ctx *ctx, int32_t method, int32_t n, int32_t km
     GXY_HIP(hipMemcpyAsync(E + nn, A, nn * sizeof(double), hipMemcpyHostToDevice, s));
     const SectorSolve sv =
         solve_sectors(ctx, s, E, n, sec, m, (int32_t *)ctx->pinned, kmax, method);
+    sv.vectors(nullptr, s);
     if (sweeps) *sweeps = sv.sweeps + sv.sweeps2;
     // eigenvalues: diagonal of the converged matrix; vectors: first n rows/cols
     GXY_HIP(hipMemcpy2DAsync(V, n * sizeof(double), sv.eb.V, np * sizeof(double),

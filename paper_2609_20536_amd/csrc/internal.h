@@ -191,16 +191,20 @@ void launch_eig_identity(const EigBatch &b, double *V, hipStream_t s);
 void launch_eig_scaled_copy(int64_t n, double a, const double *x, double *y, hipStream_t s);
 
 // Tridiagonal path for sector matrices of at most kTriMaxN rows (one
-// workgroup per matrix). A: gathered padded matrices (overwritten: reflectors
-// right of the diagonal, sorted eigenvalues on the diagonal); V: leading
-// min(n, kmax) eigenvectors (row-major, column c = c-th largest); Y, work:
-// scratch shaped like A; status[mi] = 1 if QL did not converge (caller
-// zeroes it).
+// workgroup per matrix), in two stages. launch_tri_values: A (gathered
+// padded matrices) is overwritten with the reflectors right of the diagonal
+// and the decreasing eigenvalues on the diagonal; work (shaped like A) keeps
+// d, e, tau and the eigenvalues; Y is scratch. launch_tri_vectors: the
+// leading min(n, kmax) eigenvectors into V (row-major, column c = c-th
+// largest), for the matrices of side *d_side (0: the first nsec, 1: the
+// rest) or for all if d_side is null; Y is scratch.
 constexpr int kTriMaxN = 1024;
 constexpr int kTriMaxVecs = 128;   // eigenvectors formed per matrix
-void launch_tri_eig(int nmat, int nsec, const int32_t *d_sec_n, const int32_t *d_npad,
-                    const int64_t *d_off, double *A, double *V, double *Y, double *work,
-                    int32_t *d_status, int kmax, hipStream_t s);
+void launch_tri_values(int nmat, int nsec, const int32_t *d_sec_n, const int32_t *d_npad,
+                       const int64_t *d_off, double *A, double *Y, double *work, hipStream_t s);
+void launch_tri_vectors(int nmat, int nsec, const int32_t *d_sec_n, const int32_t *d_npad,
+                        const int64_t *d_off, const double *A, double *V, double *Y,
+                        const double *work, int kmax, const double *d_side, hipStream_t s);
 
 // --------------------------------------------------------------------------
 // selection and projector

@@ -22,9 +22,11 @@
 //     per vector, by inverse iteration on the pivoted LU factorisation of
 //     T - lambda I, then Gram-Schmidt across the workgroup (the textbook
 //     bisection + inverse iteration pair for selected eigenpairs).
-//  4. tri_back: eigenvalues (decreasing) go to the diagonal of A, the
-//     vectors are mapped back through the reflectors into V (row-major,
-//     column c = c-th largest eigenvalue).
+//  4. tri_back: the vectors are mapped back through the reflectors into V
+//     (row-major, column c = c-th largest eigenvalue).
+// Stages 1-2 (launch_tri_values) put the decreasing eigenvalues of every
+// matrix on the diagonal of A for the selection; stages 3-4
+// (launch_tri_vectors) can then be limited to the side the selection chose.
 #include <float.h>
 
 #include <algorithm>
@@ -310,14 +312,22 @@ __global__ __launch_bounds__(kBisThreads) void tri_bisect_kernel(int nmat, int n
   }
 }
 
-__global__ void tri_monotone_kernel(int nmat, int nsec, const int32_t *sec_n,
-                                    const int32_t *npad, const int64_t *off, double *work) {
-  const int mi = blockIdx.x * blockDim.x + threadIdx.x;
+// Make the eigenvalues non-increasing and put them on diag(A) (padding -1),
+// where the selection reads them. The reflectors lie right of the diagonal.
+__global__ void tri_values_kernel(int nmat, int nsec, const int32_t *sec_n,
+                                  const int32_t *npad, const int64_t *off, double *work,
+                                  double *A) {
+  const int mi = blockIdx.x;
   if (mi >= nmat) return;
   const int n = sec_n[mi % nsec];
   const int np = npad[mi];
   double *lam = work + off[mi] + 3 * np;
-  for (int k = 1; k < n; ++k) lam[k] = fmin(lam[k], lam[k - 1]);
+  if (threadIdx.x == 0)
+    for (int k = 1; k < n; ++k) lam[k] = fmin(lam[k], lam[k - 1]);
+  __syncthreads();
+  double *Am = A + off[mi];
+  for (int c = threadIdx.x; c < np; c += blockDim.x)
+    Am[(int64_t)c * np + c] = c < n ? lam[c] : -1.0;
 }
 
 // Leading kq eigenvectors of T by inverse iteration, one thread per vector:
@@ -343,7 +353,8 @@ __global__ __launch_bounds__(kInvThreads) void tri_invit_kernel(int nmat, int ns
                                                                 const int32_t *npad,
                                                                 const int64_t *off,
                                                                 const double *work, double *U,
-                                                                double *Y, int kmax) {
+                                                                double *Y, int kmax,
+                                                                const double *side) {
   __shared__ double ds[kTriMaxN], es[kTriMaxN];
   __shared__ double mu[kMaxKq];
   __shared__ double dot[kMaxKq];
@@ -351,6 +362,7 @@ __global__ __launch_bounds__(kInvThreads) void tri_invit_kernel(int nmat, int ns
   __shared__ double tnorm_s;
   const int mi = blockIdx.x;
   if (mi >= nmat) return;
+  if (side && (int)*side != mi / nsec) return;   // vectors of the chosen side only
   const int n = sec_n[mi % nsec];
   const int np = npad[mi];
   const int kq = min(min(n, kmax), kMaxKq);
@@ -488,14 +500,15 @@ constexpr int kBackCols = kBackThreads / 64;
 
 __global__ __launch_bounds__(kBackThreads) void tri_back_kernel(
     int nmat, int nsec, const int32_t *sec_n, const int32_t *npad, const int64_t *off,
-    double *A, const double *work, double *V, double *Y, int kmax) {
+    const double *A, const double *work, double *V, double *Y, int kmax, const double *side) {
   const int mi = blockIdx.y;
   if (mi >= nmat) return;
+  if (side && (int)*side != mi / nsec) return;
   const int n = sec_n[mi % nsec];
   const int np = npad[mi];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const double *dg = work + off[mi], *tau = dg + 2 * np, *lam = dg + 3 * np;
-  double *Am = A + off[mi];
+  const double *dg = work + off[mi], *tau = dg + 2 * np;
+  const double *Am = A + off[mi];
   double *Vm = V + off[mi];
   double *Ym = Y + off[mi];   // Y[c * np + r], c < kq
   const int kq = min(min(n, kmax), kMaxKq);
@@ -515,25 +528,18 @@ __global__ __launch_bounds__(kBackThreads) void tri_back_kernel(
     for (int r = lane; r < n; r += 64) Vm[(int64_t)r * np + c] = yc[r];
   }
   if (blockIdx.x == 0) {
-    // columns kq .. np-1 of V are zero; eigenvalues on diag(A). The
-    // reflectors in A lie right of the diagonal, apart from these writes.
+    // columns kq .. np-1 of V are zero
     for (int64_t el = tid; el < (int64_t)n * (np - kq); el += kBackThreads) {
       const int r = (int)(el / (np - kq)), cc = kq + (int)(el % (np - kq));
       Vm[(int64_t)r * np + cc] = 0.0;
     }
-    __syncthreads();
-    for (int cc = tid; cc < np; cc += kBackThreads)
-      Am[(int64_t)cc * np + cc] = cc < n ? lam[cc] : -1.0;
   }
 }
 
 }  // namespace
 
-void launch_tri_eig(int nmat, int nsec, const int32_t *d_sec_n, const int32_t *d_npad,
-                    const int64_t *d_off, double *A, double *V, double *Y, double *work,
-                    int32_t *d_status, int kmax, hipStream_t s) {
-  (void)d_status;
-  if (kmax > kMaxKq) fail(GXY_EUNSUPPORTED, "tridiagonal path: more than 128 vectors");
+void launch_tri_values(int nmat, int nsec, const int32_t *d_sec_n, const int32_t *d_npad,
+                       const int64_t *d_off, double *A, double *Y, double *work, hipStream_t s) {
   // Y serves as the panel scratch of the reduction (2 n kNb <= npad^2)
   hipLaunchKernelGGL(tri_reduce_kernel, dim3(nmat), dim3(kRedThreads), 0, s, nmat, nsec,
                      d_sec_n, d_npad, d_off, A, work, Y);
@@ -541,16 +547,22 @@ void launch_tri_eig(int nmat, int nsec, const int32_t *d_sec_n, const int32_t *d
   hipLaunchKernelGGL(tri_bisect_kernel, dim3(kTriMaxN / kBisThreads, nmat), dim3(kBisThreads),
                      0, s, nmat, nsec, d_sec_n, d_npad, d_off, work);
   GXY_CHECK_LAUNCH();
-  hipLaunchKernelGGL(tri_monotone_kernel, dim3((nmat + 63) / 64), dim3(64), 0, s, nmat, nsec,
-                     d_sec_n, d_npad, d_off, work);
+  hipLaunchKernelGGL(tri_values_kernel, dim3(nmat), dim3(256), 0, s, nmat, nsec, d_sec_n,
+                     d_npad, d_off, work, A);
   GXY_CHECK_LAUNCH();
+}
+
+void launch_tri_vectors(int nmat, int nsec, const int32_t *d_sec_n, const int32_t *d_npad,
+                        const int64_t *d_off, const double *A, double *V, double *Y,
+                        const double *work, int kmax, const double *d_side, hipStream_t s) {
+  if (kmax > kMaxKq) fail(GXY_EUNSUPPORTED, "tridiagonal path: more than 128 vectors");
   // V serves as the factor scratch of the inverse iteration until tri_back
   hipLaunchKernelGGL(tri_invit_kernel, dim3(nmat), dim3(kInvThreads), 0, s, nmat, nsec,
-                     d_sec_n, d_npad, d_off, work, V, Y, kmax);
+                     d_sec_n, d_npad, d_off, work, V, Y, kmax, d_side);
   GXY_CHECK_LAUNCH();
   const int nx = (std::min(kmax, kMaxKq) + kBackCols - 1) / kBackCols;
   hipLaunchKernelGGL(tri_back_kernel, dim3(std::max(nx, 1), nmat), dim3(kBackThreads), 0, s,
-                     nmat, nsec, d_sec_n, d_npad, d_off, A, work, V, Y, kmax);
+                     nmat, nsec, d_sec_n, d_npad, d_off, A, work, V, Y, kmax, d_side);
   GXY_CHECK_LAUNCH();
 }
 

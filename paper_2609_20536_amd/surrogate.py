@@ -35,11 +35,12 @@ LOG_TARGETS = 0b1100   # chi, chi_n enter the network as logarithms
 
 def grid_observables(ctx: Context, points: Sequence[Tuple[float, float]], dcut: int,
                      nmax: int = 10, nsteps: int = 40, workers: int = 8,
-                     prec: int = W.PREC_FP64, fp64_steps: int = 0) -> np.ndarray:
+                     prec: int = W.PREC_FP64, fp64_steps: int = 0,
+                     db: float = W.BETA_FD_STEP) -> np.ndarray:
     """(f, C_v, chi, chi_n) for each (beta, Delta); seven runs per point."""
     runs = []
     for b, d in points:
-        runs += W.observable_runs(b, d, dcut, nmax, nsteps, prec, fp64_steps)
+        runs += W.observable_runs(b, d, dcut, nmax, nsteps, prec, fp64_steps, db)
     res = ctx.run_batch(runs, workers=workers)
     bad = [i for i, r in enumerate(res) if r.status != 0]
     if bad:
@@ -49,14 +50,13 @@ def grid_observables(ctx: Context, points: Sequence[Tuple[float, float]], dcut: 
     mh = np.array([[res[7 * k + 3 + j].m_cos1 for j in range(2)] for k in range(n)])
     mh1 = np.array([[res[7 * k + 5 + j].m_cos2 for j in range(2)] for k in range(n)])
     beta = np.array([p[0] for p in points], dtype=np.float64)
-    return ctx.observables(beta, lnz, mh, mh1, W.BETA_FD_STEP, W.FIELD_FD_STEP,
-                           W.FIELD_FD_STEP)
+    return ctx.observables(beta, lnz, mh, mh1, db, W.FIELD_FD_STEP, W.FIELD_FD_STEP)
 
 
 def cv_along_beta(ctx: Context, delta: float, betas: Sequence[float], dcut: int,
-                  nmax: int, nsteps: int, workers: int = 8) -> np.ndarray:
+                  nmax: int, nsteps: int, workers: int = 8,
+                  db: float = W.BETA_FD_STEP) -> np.ndarray:
     """C_v(beta) at zero field from three runs per beta (beta, beta +- db)."""
-    db = W.BETA_FD_STEP
     runs = [W.Point(beta=b + s, delta=delta, nmax=nmax, dcut=dcut, nsteps=nsteps, impurities=0)
             for b in betas for s in (-db, 0.0, db)]
     res = ctx.run_batch(runs, workers=workers)
@@ -113,7 +113,7 @@ def gain_experiment(ctx: Context, deltas: Sequence[float] = (0.3, 0.6, 0.9),
                     train_grid: Tuple[int, int] = (21, 6), budget: int = 6,
                     reference_points: int = 41, beta_range: Tuple[float, float] = (0.5, 1.5),
                     epochs: int = 5000, workers: int = 8,
-                    window: float = 2.0) -> Dict[str, object]:
+                    window: float = 2.0, db: float = 0.02) -> Dict[str, object]:
     """C_v peak location along beta at fixed Delta, uniform vs surrogate-guided.
 
     Reference: the peak from a dense scan (reference_points betas). Uniform:
@@ -122,11 +122,16 @@ def gain_experiment(ctx: Context, deltas: Sequence[float] = (0.3, 0.6, 0.9),
     maximum at each Delta, and the same `budget` betas are spread over
     `window` coarse-grid spacings on either side of it. Both estimates use the
     parabola vertex through the largest sample and its neighbours.
+
+    C_v here is the central second difference with step db = 0.02 (the
+    scans' 1e-3 turns each change of the kept states between beta - db and
+    beta + db into a spike of order (jump in ln Z/V) / db^2; a wider step
+    damps those spikes by (0.02 / 0.001)^2 = 400 on the same smooth curve).
     """
     lo, hi = beta_range
     nb, nd = train_grid
     grid = [(lo + (hi - lo) * i / (nb - 1), j / (nd - 1)) for i in range(nb) for j in range(nd)]
-    Y = grid_observables(ctx, grid, dcut, nmax, nsteps, workers)
+    Y = grid_observables(ctx, grid, dcut, nmax, nsteps, workers, db=db)
     X = np.array(grid)
     net, hist = train(ctx, X, Y, epochs=epochs)
     out = {"deltas": list(deltas), "budget": budget, "train_points": len(grid),
@@ -134,15 +139,15 @@ def gain_experiment(ctx: Context, deltas: Sequence[float] = (0.3, 0.6, 0.9),
     spacing = (hi - lo) / (nb - 1)
     for d in deltas:
         ref_b = np.linspace(lo, hi, reference_points)
-        ref = peak_location(ref_b, cv_along_beta(ctx, d, ref_b, dcut, nmax, nsteps, workers))
+        ref = peak_location(ref_b, cv_along_beta(ctx, d, ref_b, dcut, nmax, nsteps, workers, db))
         uni_b = np.linspace(lo, hi, budget)
-        uni = peak_location(uni_b, cv_along_beta(ctx, d, uni_b, dcut, nmax, nsteps, workers))
+        uni = peak_location(uni_b, cv_along_beta(ctx, d, uni_b, dcut, nmax, nsteps, workers, db))
         lat = np.stack([np.linspace(lo, hi, 256), np.full(256, d)], axis=1)
         pred = net.predict(lat, bf16=True)
         bp = peak_location(lat[:, 0], pred[:, 1])
         g_lo, g_hi = max(lo, bp - window * spacing), min(hi, bp + window * spacing)
         gui_b = np.linspace(g_lo, g_hi, budget)
-        gui = peak_location(gui_b, cv_along_beta(ctx, d, gui_b, dcut, nmax, nsteps, workers))
+        gui = peak_location(gui_b, cv_along_beta(ctx, d, gui_b, dcut, nmax, nsteps, workers, db))
         out["rows"].append({"delta": d, "reference": ref, "uniform": uni, "proposed": bp,
                             "guided": gui, "err_uniform": abs(uni - ref),
                             "err_guided": abs(gui - ref)})

@@ -129,7 +129,7 @@ def grid_points(nb: int = 16, nd: int = 16, nmax: int = 10,
 
 def observable_runs(beta: float, delta: float, dcut: int, nmax: int = 10,
                     nsteps: int = 40, prec: int = PREC_FP64,
-                    fp64_steps: int = 0) -> List[Point]:
+                    fp64_steps: int = 0, db: float = BETA_FD_STEP) -> List[Point]:
     """The seven runs behind (f, C_v, chi, chi_n) at one (beta, Delta).
 
     Order: beta-db, beta, beta+db (zero field, no chains);
@@ -137,7 +137,7 @@ def observable_runs(beta: float, delta: float, dcut: int, nmax: int = 10,
     """
     base = Point(beta=beta, delta=delta, nmax=nmax, dcut=dcut, nsteps=nsteps,
                  impurities=0, prec=prec, fp64_steps=fp64_steps)
-    db, hc, dh = BETA_FD_STEP, FIELD_CENTER, FIELD_FD_STEP
+    hc, dh = FIELD_CENTER, FIELD_FD_STEP
     return [
         base.with_(beta=beta - db),
         base,
