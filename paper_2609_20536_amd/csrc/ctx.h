@@ -46,6 +46,10 @@ struct gxy_ctx {
   size_t arena_bytes = 0, arena_cur = 0;
   hipEvent_t arena_ev = nullptr;
   bool arena_pending = false;
+  hipEvent_t sel_ev = nullptr;  // selection results copied to the host
+  // side stream for the projection table copies, with one event per launch
+  hipStream_t copy_stream = nullptr;
+  std::vector<hipEvent_t> copy_ev;
   // projection tile per Dcut chosen by gxy_autotune (absent: by tile fill);
   // force_tile (64 / 128) overrides both while the autotuner measures
   std::map<int, int> tile_for_dcut;
@@ -53,7 +57,7 @@ struct gxy_ctx {
   bool hot_force = false;  // keep the contraction events on (autotuner)
   // batched runs: worker contexts, each with its own stream and workspace
   int batch_workers = 0;  // 0 = default
-  size_t chunk_bytes = 0;  // projection chunk bound (0: GXY_CHUNK_BYTES or 16 GiB)
+  size_t chunk_bytes = 0;  // projection chunk bound (0: GXY_CHUNK_BYTES or 32 GiB)
   std::vector<gxy_ctx *> children;
 };
 

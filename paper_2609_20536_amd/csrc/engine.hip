@@ -38,9 +38,10 @@ namespace gxy {
 constexpr double kTieRel = 1e-12;
 constexpr double kSideTol = 1e-10;
 constexpr int kMaxSweeps = 120;
-// pinned host staging (1 MiB): the block-order table of a step goes here
-constexpr int64_t kPermPinnedOffset = 131072;   // in int32 units (512 KiB)
-constexpr int64_t kPermPinnedInts = 65536;
+constexpr size_t kPlanAhead = 16;                // projection launches planned ahead
+// projection chunk bound over the three D^5 buffers (X, X of an impurity, Y):
+// 32 GiB keeps Dcut = 64 with both impurity chains in one chunk
+constexpr size_t kDefaultChunkBytes = (size_t)32 << 30;
 constexpr int kLmax = 50;
 
 enum Sym { SYM_U1 = 0, SYM_NONE = 1, SYM_Z2 = 2 };
@@ -90,6 +91,7 @@ struct Plan {
   int nimp = 0;
   int64_t tab_env = 0, tab_proj = 0;  // offset-table entries (bounds)
   int64_t grp_env = 0, grp_proj = 0;  // group descriptors (bounds)
+  int64_t proj_bytes = 0;             // projection slices of one step (bound)
 };
 
 static Plan make_plan(const gxy_point &p, size_t chunk_bytes) {
@@ -142,6 +144,11 @@ static Plan make_plan(const gxy_point &p, size_t chunk_bytes) {
     pl.tab_proj = std::max(pl.tab_proj, proj);
     pl.grp_env = std::max(pl.grp_env, 2 * (2 * MN + Dh * Dh) + 16);
     pl.grp_proj = std::max(pl.grp_proj, nch * nvar * (Dn * Dh + 2 * MN + Dn + 16));
+    // one slice per launch (groups, then tables), each rounded up to 64 bytes
+    const int64_t nlaunch = nch * (3 + 4 * pl.nimp);
+    pl.proj_bytes = std::max(pl.proj_bytes, 8 * pl.tab_proj +
+                                                (int64_t)sizeof(GGroup) * pl.grp_proj +
+                                                64 * nlaunch);
   }
   return pl;
 }
@@ -168,9 +175,10 @@ struct Buffers {
   double *nrm;                     // 3 * (nsteps + 1)
   double *coef;                    // t, F, FM, FM1
   double *scal;                    // traces and result
-  int64_t *tab_env, *tab_proj;     // charge-block offset tables
+  int64_t *tab_env;                // charge-block offset tables
+  char *proj_tab;                  // projection slices: groups + tables
   int32_t *perm;                   // inverse block order of the fused index
-  GGroup *grp_env, *grp_proj;
+  GGroup *grp_env;
   int64_t eig_elems, eig_q;
   int64_t sel_cap;
 };
@@ -230,9 +238,8 @@ static size_t carve(const gxy_point &p, const Plan &pl, Carver &c, Buffers &b) {
   b.scal = c.take<double>(16);
   b.tab_env = c.take<int64_t>(pl.tab_env);
   b.perm = c.take<int32_t>(std::max<int64_t>(pl.maxW, 1));
-  b.tab_proj = c.take<int64_t>(pl.tab_proj);
   b.grp_env = c.take<GGroup>(pl.grp_env);
-  b.grp_proj = c.take<GGroup>(pl.grp_proj);
+  b.proj_tab = c.take<char>(pl.proj_bytes);
   return c.off + 256;
 }
 
@@ -274,46 +281,83 @@ static void upload_plan(gxy_ctx *ctx, int j, const TablePlan &tp, int64_t *d_tab
   ctx->stage_used[j] = true;
 }
 
-// Projection tables of one step: each part is copied through its own slice of
-// a pinned arena (reset once the previous step's copies have completed).
-static void upload_part(gxy_ctx *ctx, const TablePlan &tp, int64_t *d_tab, int64_t tab_cap,
-                        GGroup *d_grp, int64_t grp_cap, hipStream_t s) {
-  if ((int64_t)tp.tab.size() > tab_cap || (int64_t)tp.groups.size() > grp_cap)
-    fail(GXY_ENOMEM, "charge-block table bound exceeded");
-  const size_t tb = tp.tab.size() * sizeof(int64_t), gb = tp.groups.size() * sizeof(GGroup);
-  const size_t need = (tb + gb + 255) & ~(size_t)255;
-  if (ctx->arena_cur + need > ctx->arena_bytes) {
-    // grow: wait for copies from the old arena before releasing it
-    if (ctx->arena) {
-      GXY_HIP(hipStreamSynchronize(s));
-      GXY_HIP(hipHostFree(ctx->arena));
-    }
-    const size_t nb = std::max(2 * ctx->arena_bytes, ctx->arena_cur + need + (64 << 20));
+// Projection tables of one step: every launch is planned on a host thread
+// and copied into its own slice of a pinned arena (its group descriptors,
+// then its offset tables); slices are taken by an atomic bump and the
+// device area mirrors the arena, so a slice's device copy is one contiguous
+// copy at the same offset. The copies run on a side stream and the compute
+// stream waits for each before its launch. The arena is reused once the
+// previous step's copies have completed.
+struct ProjArena {
+  char *base = nullptr;
+  int64_t cap = 0;
+  std::atomic<int64_t> used{0};
+  int32_t *perm = nullptr;  // block-order permutation of the step
+};
+
+static void proj_stage_begin(gxy_ctx *ctx, ProjArena &A, int64_t cap, int64_t perm_cap) {
+  if (ctx->arena_pending) GXY_HIP(hipEventSynchronize(ctx->arena_ev));
+  ctx->arena_pending = false;
+  const size_t cb = ((size_t)cap + 255) & ~(size_t)255;
+  const size_t need = cb + (size_t)perm_cap * sizeof(int32_t);
+  if (ctx->arena_bytes < need) {
+    if (ctx->arena) GXY_HIP(hipHostFree(ctx->arena));
     ctx->arena = nullptr;
-    GXY_HIP(hipHostMalloc(&ctx->arena, nb, hipHostMallocDefault));
-    ctx->arena_bytes = nb;
-    ctx->arena_cur = 0;
+    ctx->arena_bytes = 0;
+    GXY_HIP(hipHostMalloc(&ctx->arena, need, hipHostMallocDefault));
+    ctx->arena_bytes = need;
   }
-  char *h = (char *)ctx->arena + ctx->arena_cur;
-  memcpy(h, tp.tab.data(), tb);
-  memcpy(h + tb, tp.groups.data(), gb);
-  if (tb) GXY_HIP(hipMemcpyAsync(d_tab, h, tb, hipMemcpyHostToDevice, s));
-  if (gb) GXY_HIP(hipMemcpyAsync(d_grp, h + tb, gb, hipMemcpyHostToDevice, s));
-  ctx->arena_cur += need;
+  A.base = (char *)ctx->arena;
+  A.cap = cap;
+  A.used = 0;
+  A.perm = (int32_t *)(A.base + cb);
 }
 
-// After the last part of a step: the arena may be reused once this event
-// has completed.
+// After the last launch of a step: the arena may be reused once this event
+// has completed (every copy precedes its launch on the compute stream).
 static void proj_stage_done(gxy_ctx *ctx, hipStream_t s) {
   if (!ctx->arena_ev) GXY_HIP(hipEventCreateWithFlags(&ctx->arena_ev, hipEventDisableTiming));
   GXY_HIP(hipEventRecord(ctx->arena_ev, s));
   ctx->arena_pending = true;
 }
 
-static void proj_stage_begin(gxy_ctx *ctx) {
-  if (ctx->arena_pending) GXY_HIP(hipEventSynchronize(ctx->arena_ev));
-  ctx->arena_pending = false;
-  ctx->arena_cur = 0;
+// One planned projection launch and its slice of the arena.
+struct ProjJob {
+  Launch L;
+  int64_t off = 0, bytes = 0, ngrp = 0;
+  bool sent = false;
+};
+
+// Host-thread side: copy a finished plan into a fresh slice of the arena.
+static void stage_plan(ProjArena &A, const TablePlan &tp, const Launch &L, ProjJob &j) {
+  j.L = L;
+  j.ngrp = (int64_t)tp.groups.size();
+  const int64_t gb = j.ngrp * (int64_t)sizeof(GGroup);
+  const int64_t tb = (int64_t)tp.tab.size() * (int64_t)sizeof(int64_t);
+  j.bytes = (gb + tb + 63) & ~(int64_t)63;
+  j.off = A.used.fetch_add(j.bytes);
+  if (j.off + j.bytes > A.cap) fail(GXY_ENOMEM, "charge-block table bound exceeded");
+  if (gb) memcpy(A.base + j.off, tp.groups.data(), gb);
+  if (tb) memcpy(A.base + j.off + gb, tp.tab.data(), tb);
+}
+
+// Stream side: the slice's device copy (once per job) on the side stream,
+// ordered before the compute stream's next launch.
+static void send_plan(gxy_ctx *ctx, const ProjArena &A, ProjJob &j, char *d_area, hipStream_t s,
+                      size_t k) {
+  if (j.sent) return;
+  if (j.bytes) {
+    while (ctx->copy_ev.size() <= k) {
+      hipEvent_t e;
+      GXY_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      ctx->copy_ev.push_back(e);
+    }
+    GXY_HIP(hipMemcpyAsync(d_area + j.off, A.base + j.off, j.bytes, hipMemcpyHostToDevice,
+                           ctx->copy_stream));
+    GXY_HIP(hipEventRecord(ctx->copy_ev[k], ctx->copy_stream));
+    GXY_HIP(hipStreamWaitEvent(s, ctx->copy_ev[k], 0));
+  }
+  j.sent = true;
 }
 
 static void run_launch(const Launch &L, const GGroup *d_grp, const int64_t *d_tab,
@@ -849,7 +893,7 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
   validate(p);
   const hipStream_t s = ctx->stream;
   const size_t chunk_bytes =
-      ctx->chunk_bytes ? ctx->chunk_bytes : env_size("GXY_CHUNK_BYTES", (size_t)16 << 30);
+      ctx->chunk_bytes ? ctx->chunk_bytes : env_size("GXY_CHUNK_BYTES", kDefaultChunkBytes);
   const Plan pl = make_plan(p, chunk_bytes);
   Buffers b{};
   {
@@ -1024,14 +1068,18 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
       sa.d_pick_label = b.pick + 2 * Dn;
       sa.d_diag = b.diag;
       launch_select(sa, s);
-      sv.vectors(b.diag + 2, s);   // diag[2] = chosen side
-      launch_build_projector(eb.V, eb.d_off, eb.d_npad, d_idx, d_start, d_n, b.pick,
-                             b.pick + Dn, b.diag, nsec, (int)nf, Dn, b.P, s);
+      // the host needs only the kept labels and the summary; it plans the
+      // projection while the device forms the kept eigenvectors and P
       GXY_HIP(hipMemcpyAsync(hp, b.pick + 2 * Dn, Dn * sizeof(int32_t),
                              hipMemcpyDeviceToHost, s));
       double *hd = reinterpret_cast<double *>(hp + 512);
       GXY_HIP(hipMemcpyAsync(hd, b.diag, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
-      GXY_HIP(hipStreamSynchronize(s));
+      if (!ctx->sel_ev) GXY_HIP(hipEventCreateWithFlags(&ctx->sel_ev, hipEventDisableTiming));
+      GXY_HIP(hipEventRecord(ctx->sel_ev, s));
+      sv.vectors(b.diag + 2, s);   // diag[2] = chosen side
+      launch_build_projector(eb.V, eb.d_off, eb.d_npad, d_idx, d_start, d_n, b.pick,
+                             b.pick + Dn, b.diag, nsec, (int)nf, Dn, b.P, s);
+      GXY_HIP(hipEventSynchronize(ctx->sel_ev));
       new_lh.assign(hp, hp + Dn);
       info.eps_l = hd[0];
       info.eps_r = hd[1];
@@ -1058,12 +1106,7 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
     } else {
       block_positions(blk);
       const int64_t Wn = (int64_t)Dh * Dv;
-      if (Wn > pl.maxW || Wn > (int64_t)kPermPinnedInts) fail(GXY_ENOMEM, "block order table bound");
-      int32_t *hperm = hp + kPermPinnedOffset;
-      for (int64_t f = 0; f < Wn; ++f) hperm[blk.pos[f]] = (int32_t)f;
-      GXY_HIP(hipMemcpyAsync(b.perm, hperm, Wn * sizeof(int32_t), hipMemcpyHostToDevice, s));
-      launch_block_gather(b.T, b.T2, b.perm, Dh, Dv, s);
-      for (int k = 0; k < nimp; ++k) launch_block_gather(b.TX[k], b.TX2[k], b.perm, Dh, Dv, s);
+      if (Wn > pl.maxW) fail(GXY_ENOMEM, "block order table bound");
     }
     const int64_t per_a = (int64_t)Dh * Dv * Dh * Dv;
     const int ac_max = (int)std::max<int64_t>(1, std::min<int64_t>(Dn, pl.chunk_elems / per_a));
@@ -1090,11 +1133,17 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
         }
       }
     } else {
-      // charge-block launches. The tables of each (chunk, tensor pair) are
-      // built on host threads; each part is uploaded at its own place in the
-      // step's table area and launched as soon as it is ready, so the host
-      // builds the next part while the device runs the previous one.
-      proj_stage_begin(ctx);
+      // charge-block launches. Every launch of the step is planned on a host
+      // thread of its own (at most kPlanAhead ahead of the one the stream
+      // needs next) and staged in the pinned arena; the stream takes each as
+      // soon as it is ready, so the device runs one launch while the host
+      // plans the next.
+      ProjArena arena;
+      proj_stage_begin(ctx, arena, pl.proj_bytes, pl.maxW);
+      if (!ctx->copy_stream)
+        GXY_HIP(hipStreamCreateWithFlags(&ctx->copy_stream, hipStreamNonBlocking));
+      // (the host has seen the previous step's last launch complete, in
+      // proj_stage_begin, so the device slices are free for the side stream)
       int proj_tile = ctx->force_tile;
       if (!proj_tile) {
         const auto it = ctx->tile_for_dcut.find(p.dcut);
@@ -1104,66 +1153,105 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
       SL.pos = blk.pos;
       SL.vrank = blk.vrank;
       const QSet s0{0};
+      // launch kinds: pure X, Y, T'; impurity Y = X(T) T_X2, T' of it,
+      // X(T_X), Y = X(T_X) T2
+      enum { PX, PY, PT, IY, IT, IX2, IY2, NKIND };
       struct Part {
         int a0 = 0, ac = 0, k = -1;  // k = -1: pure tensor; else impurity k
-        TablePlan tp;
-        Launch x, y, t, x2, y2;      // impurity: y = (T, T_X), x2/y2 = (T_X, T)
+        ProjJob job[NKIND];
       };
-      std::vector<std::unique_ptr<Part>> parts;
+      std::vector<Part> parts;
       for (int a0 = 0; a0 < Dn; a0 += ac_max)
         for (int k = -1; k < nimp; ++k) {
-          auto pt = std::make_unique<Part>();
-          pt->a0 = a0;
-          pt->ac = std::min(ac_max, Dn - a0);
-          pt->k = k;
-          parts.push_back(std::move(pt));
+          Part pt;
+          pt.a0 = a0;
+          pt.ac = std::min(ac_max, Dn - a0);
+          pt.k = k;
+          parts.push_back(pt);
         }
-      std::vector<std::future<void>> built;
-      for (auto &up : parts) {
-        Part *pt = up.get();
-        built.push_back(std::async(std::launch::async, [pt, &SL, &s0, &imp_set]() {
-          const int a1 = pt->a0 + pt->ac;
-          if (pt->k < 0) {
-            pt->x = plan_proj_x(SL, pt->a0, a1, s0, pt->tp);
-            pt->y = plan_proj_y(SL, pt->a0, a1, s0, s0, pt->tp);
-            pt->t = plan_proj_t(SL, pt->a0, a1, s0, pt->tp);
-          } else {
-            const QSet &sk = imp_set[pt->k];
-            pt->y = plan_proj_y(SL, pt->a0, a1, s0, sk, pt->tp);
-            pt->t = plan_proj_t(SL, pt->a0, a1, sk, pt->tp);
-            pt->x2 = plan_proj_x(SL, pt->a0, a1, sk, pt->tp);
-            pt->y2 = plan_proj_y(SL, pt->a0, a1, sk, s0, pt->tp);
-          }
-        }));
+      // jobs in the order the stream consumes them
+      std::vector<std::pair<int, int>> order;
+      for (int i = 0; i < (int)parts.size(); ++i) {
+        if (parts[i].k < 0)
+          for (int kd : {PX, PY, PT}) order.push_back({i, kd});
+        else
+          for (int kd : {IY, IT, IX2, IY2}) order.push_back({i, kd});
+      }
+      auto plan_job = [&SL, &s0, &imp_set, &parts, &arena](int i, int kd) {
+        Part &pt = parts[i];
+        const int a0 = pt.a0, a1 = pt.a0 + pt.ac;
+        const QSet &sk = pt.k < 0 ? s0 : imp_set[pt.k];
+        TablePlan tp;
+        Launch L;
+        switch (kd) {
+          case PX: L = plan_proj_x(SL, a0, a1, s0, tp); break;
+          case PY: L = plan_proj_y(SL, a0, a1, s0, s0, tp); break;
+          case PT: L = plan_proj_t(SL, a0, a1, s0, tp); break;
+          case IY: L = plan_proj_y(SL, a0, a1, s0, sk, tp); break;
+          case IT: L = plan_proj_t(SL, a0, a1, sk, tp); break;
+          case IX2: L = plan_proj_x(SL, a0, a1, sk, tp); break;
+          default: L = plan_proj_y(SL, a0, a1, sk, s0, tp); break;
+        }
+        stage_plan(arena, tp, L, pt.job[kd]);
+      };
+      // declared after everything the threads use, so that unwinding joins
+      // them first
+      std::vector<std::future<void>> planned(order.size());
+      size_t spawned = 0;
+      auto spawn_upto = [&](size_t n) {
+        for (; spawned < std::min(n, order.size()); ++spawned) {
+          const auto o = order[spawned];
+          planned[spawned] = std::async(std::launch::async, plan_job, o.first, o.second);
+        }
+      };
+      spawn_upto(kPlanAhead);
+      {
+        // block-order bottom operands; the permutation is staged in the
+        // arena, whose previous copies have completed
+        const int64_t Wn = (int64_t)Dh * Dv;
+        for (int64_t f = 0; f < Wn; ++f) arena.perm[blk.pos[f]] = (int32_t)f;
+        GXY_HIP(hipMemcpyAsync(b.perm, arena.perm, Wn * sizeof(int32_t), hipMemcpyHostToDevice,
+                               s));
+        launch_block_gather(b.T, b.T2, b.perm, Dh, Dv, s);
+        for (int k = 0; k < nimp; ++k) launch_block_gather(b.TX[k], b.TX2[k], b.perm, Dh, Dv, s);
       }
       const int64_t nTn = (int64_t)Dn * Dn * Dv * Dv;
       launch_fill(b.Tn, nTn, 0.0, s);
       for (int k = 0; k < nimp; ++k) launch_fill(b.TXn[k], nTn, 0.0, s);
-      int64_t tab_cur = 0, grp_cur = 0;
-      for (size_t i = 0; i < parts.size(); ++i) {
-        built[i].get();
-        Part &pt = *parts[i];
-        int64_t *dt = b.tab_proj + tab_cur;
-        GGroup *dg = b.grp_proj + grp_cur;
-        upload_part(ctx, pt.tp, dt, pl.tab_proj - tab_cur, dg, pl.grp_proj - grp_cur, s);
-        tab_cur += (int64_t)pt.tp.tab.size();
-        grp_cur += (int64_t)pt.tp.groups.size();
-        auto gy = [&](const Launch &L, const double *Xp, const double *Bp) {
-          hot_begin(ctx, s, L.flops, L.bytes);
-          run_launch(L, dg, dt, Xp, Bp, b.Y, 1.0, 0.0, s, sprec);
-          hot_end(ctx, s);
-        };
-        if (pt.k < 0) {
-          run_launch(pt.x, dg, dt, b.P, b.T, b.X, 1.0, 0.0,  s, sprec);
-          gy(pt.y, b.X, b.T2);
-          run_launch(pt.t, dg, dt, b.Y, b.P, b.Tn, 1.0, 0.0,  s, sprec);
+      size_t next = 0;
+      auto take = [&](int i, int kd) -> ProjJob & {
+        // jobs are consumed in spawn order; an impurity T' is used twice
+        while (next < order.size() && (order[next].first < i ||
+                                       (order[next].first == i && order[next].second <= kd))) {
+          spawn_upto(next + 1 + kPlanAhead);
+          planned[next].get();
+          ++next;
+        }
+        ProjJob &j = parts[i].job[kd];
+        send_plan(ctx, arena, j, b.proj_tab, s, (size_t)i * NKIND + kd);
+        return j;
+      };
+      auto go = [&](ProjJob &j, const double *A, const double *B, double *C, double alpha,
+                    double beta, bool hot) {
+        const GGroup *dg = reinterpret_cast<const GGroup *>(b.proj_tab + j.off);
+        const int64_t *dt = reinterpret_cast<const int64_t *>(b.proj_tab + j.off +
+                                                              j.ngrp * (int64_t)sizeof(GGroup));
+        if (hot) hot_begin(ctx, s, j.L.flops, j.L.bytes);
+        run_launch(j.L, dg, dt, A, B, C, alpha, beta, s, sprec);
+        if (hot) hot_end(ctx, s);
+      };
+      for (int i = 0; i < (int)parts.size(); ++i) {
+        const int k = parts[i].k;
+        if (k < 0) {
+          go(take(i, PX), b.P, b.T, b.X, 1.0, 0.0, false);
+          go(take(i, PY), b.X, b.T2, b.Y, 1.0, 0.0, true);
+          go(take(i, PT), b.Y, b.P, b.Tn, 1.0, 0.0, false);
         } else {
-          const int k = pt.k;
-          gy(pt.y, b.X, b.TX2[k]);
-          run_launch(pt.t, dg, dt, b.Y, b.P, b.TXn[k], 0.5, 0.0,  s, sprec);
-          run_launch(pt.x2, dg, dt, b.P, b.TX[k], b.XI, 1.0, 0.0,  s, sprec);
-          gy(pt.y2, b.XI, b.T2);
-          run_launch(pt.t, dg, dt, b.Y, b.P, b.TXn[k], 0.5, 1.0,  s, sprec);
+          go(take(i, IY), b.X, b.TX2[k], b.Y, 1.0, 0.0, true);
+          go(take(i, IT), b.Y, b.P, b.TXn[k], 0.5, 0.0, false);
+          go(take(i, IX2), b.P, b.TX[k], b.XI, 1.0, 0.0, false);
+          go(take(i, IY2), b.XI, b.T2, b.Y, 1.0, 0.0, true);
+          go(take(i, IT), b.Y, b.P, b.TXn[k], 0.5, 1.0, false);
         }
       }
       proj_stage_done(ctx, s);
@@ -1244,7 +1332,7 @@ static void initial_tensor_only(gxy_ctx *ctx, const gxy_point &p, int which, dou
 
 static size_t workspace_for(const gxy_point &p) {
   validate(p);
-  const Plan pl = make_plan(p, env_size("GXY_CHUNK_BYTES", (size_t)16 << 30));
+  const Plan pl = make_plan(p, env_size("GXY_CHUNK_BYTES", kDefaultChunkBytes));
   Buffers b{};
   Carver c;
   return carve(p, pl, c, b);
@@ -1292,6 +1380,12 @@ gxy_status gxy_destroy(gxy_ctx *ctx) {
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   if (ctx->arena_ev) (void)hipEventDestroy(ctx->arena_ev);
+  if (ctx->sel_ev) (void)hipEventDestroy(ctx->sel_ev);
+  for (hipEvent_t e : ctx->copy_ev) (void)hipEventDestroy(e);
+  if (ctx->copy_stream) {
+    (void)hipStreamSynchronize(ctx->copy_stream);
+    (void)hipStreamDestroy(ctx->copy_stream);
+  }
   if (ctx->arena) (void)hipHostFree(ctx->arena);
   for (int j = 0; j < 3; ++j) {
     if (ctx->stage_ev[j]) (void)hipEventDestroy(ctx->stage_ev[j]);

@@ -227,6 +227,44 @@ void plan_env(const StepLegs &S, bool right, TablePlan &tp, Launch out[3]) {
   }
 }
 
+namespace {
+
+// Distinct normalised labels of one leg (ascending) with their indices
+// (ascending); slot[i] is the position of i's label in that list.
+struct LegLabels {
+  std::vector<int> q;
+  std::vector<std::vector<int>> members;
+};
+
+LegLabels leg_labels(const std::vector<int> &lab, int mod) {
+  LegLabels L;
+  for (int x : lab) L.q.push_back(qnorm(x, mod));
+  std::sort(L.q.begin(), L.q.end());
+  L.q.erase(std::unique(L.q.begin(), L.q.end()), L.q.end());
+  L.members.resize(L.q.size());
+  for (int i = 0; i < (int)lab.size(); ++i) {
+    const int s = (int)(std::lower_bound(L.q.begin(), L.q.end(), qnorm(lab[i], mod)) - L.q.begin());
+    L.members[s].push_back(i);
+  }
+  return L;
+}
+
+// Offset lists keyed by (integer key in [lo, hi], label slot).
+struct KeyedLists {
+  int lo = 0, nk = 0, nl = 0;
+  std::vector<std::vector<int64_t>> first, second;
+  KeyedLists(int lo_, int hi_, int nl_) : lo(lo_), nk(hi_ - lo_ + 1), nl(nl_) {
+    if (nk < 0) nk = 0;
+    first.resize((size_t)nk * nl);
+    second.resize((size_t)nk * nl);
+  }
+  int at(int key, int slot) const {
+    return (key < lo || key >= lo + nk) ? -1 : (key - lo) * nl + slot;
+  }
+};
+
+}  // namespace
+
 Launch plan_proj_x(const StepLegs &S, int a0, int a1, const QSet &sA, TablePlan &tp) {
   const int Dh = S.Dh, Dv = S.Dv, Dn = S.Dn, mod = S.mod;
   const int64_t W = (int64_t)Dh * Dv, per_a = W * W;
@@ -235,20 +273,31 @@ Launch plan_proj_x(const StepLegs &S, int a0, int a1, const QSet &sA, TablePlan 
   std::map<int, std::vector<PI>> rows;
   for (int l2 = 0; l2 < Dh; ++l2)
     for (int a = a0; a < a1; ++a) rows[qnorm(S.ln[a] - S.lh[l2], mod)].push_back(PI(a, l2));
-  // columns (r1, u, i) keyed by (kc = q_r1 + q_u - q_i, q_i); group (c, q_i)
-  // takes the columns with c - kc in sA. With q_i fixed, the output offset
-  // splits into a row part (pos of (l2, first i of the label)) and a column
-  // part (r1, u, rank of i in its label).
-  std::map<std::pair<int, int>, std::pair<std::vector<int64_t>, std::vector<int64_t>>> cols;
-  std::map<int, int> first_of;   // label -> first vertical index with it
-  for (int i = Dv - 1; i >= 0; --i) first_of[qnorm(S.lv[i], mod)] = i;
+  // columns (r1, u, i) keyed by (kc = q_r1 + q_u - q_i, label of i); group
+  // (c, label) takes the columns with c - kc in sA. With the label of i
+  // fixed, the output offset splits into a row part (pos of (l2, first i of
+  // the label)) and a column part (r1, u, rank of i in its label).
+  const LegLabels V = leg_labels(S.lv, mod);
+  const int nl = (int)V.q.size();
+  int lo = 0, hi = -1;
   for (int r1 = 0; r1 < Dh; ++r1)
     for (int u = 0; u < Dv; ++u)
-      for (int i = 0; i < Dv; ++i) {
-        const int qi = qnorm(S.lv[i], mod);
-        auto &c = cols[std::make_pair(qnorm(S.lh[r1] + S.lv[u] - S.lv[i], mod), qi)];
-        c.first.push_back((int64_t)r1 * Dv * Dv + (int64_t)u * Dv + i);
-        c.second.push_back((int64_t)r1 * Dv * W + (int64_t)u * W + S.vrank[i]);
+      for (int li = 0; li < nl; ++li) {
+        const int k = qnorm(S.lh[r1] + S.lv[u] - V.q[li], mod);
+        if (hi < lo) lo = hi = k;
+        lo = std::min(lo, k);
+        hi = std::max(hi, k);
+      }
+  KeyedLists cols(lo, hi, nl);
+  for (int r1 = 0; r1 < Dh; ++r1)
+    for (int u = 0; u < Dv; ++u)
+      for (int li = 0; li < nl; ++li) {
+        const int at = cols.at(qnorm(S.lh[r1] + S.lv[u] - V.q[li], mod), li);
+        auto &bf = cols.first[at], &bs = cols.second[at];
+        for (int i : V.members[li]) {
+          bf.push_back((int64_t)r1 * Dv * Dv + (int64_t)u * Dv + i);
+          bs.push_back((int64_t)r1 * Dv * W + (int64_t)u * W + S.vrank[i]);
+        }
       }
   std::vector<GSpec> gs;
   for (const auto &kv : rows) {
@@ -261,14 +310,14 @@ Launch plan_proj_x(const StepLegs &S, int a0, int a1, const QSet &sA, TablePlan 
         ac.push_back((int64_t)l1 * Dh * Dn);
         br.push_back((int64_t)l1 * Dh * Dv * Dv);
       }
-    for (const auto &fq : first_of) {
-      const int qi = fq.first, i0 = fq.second;
+    for (int li = 0; li < nl; ++li) {
+      const int i0 = V.members[li][0];
       std::vector<int64_t> bc, cc, cr;
       for (int sv : sA) {
-        auto ic = cols.find(std::make_pair(qnorm(c - sv, mod), qi));
-        if (ic == cols.end()) continue;
-        bc.insert(bc.end(), ic->second.first.begin(), ic->second.first.end());
-        cc.insert(cc.end(), ic->second.second.begin(), ic->second.second.end());
+        const int at = cols.at(qnorm(c - sv, mod), li);
+        if (at < 0) continue;
+        bc.insert(bc.end(), cols.first[at].begin(), cols.first[at].end());
+        cc.insert(cc.end(), cols.second[at].begin(), cols.second[at].end());
       }
       if (bc.empty()) continue;
       for (const PI &p : kv.second)
@@ -294,14 +343,28 @@ Launch plan_proj_y(const StepLegs &S, int a0, int a1, const QSet &sA, const QSet
   const int Dh = S.Dh, Dv = S.Dv, mod = S.mod;
   const int64_t W = (int64_t)Dh * Dv;
   // rho = q_a - q_r1 - q_u per row (a, r1, u); kappa = q_l2 - q_i per reduction
-  // index (l2, i); nu = q_r2 - q_d per column (r2, d).
-  std::map<int, std::vector<int64_t>> rows_by_rho, ks_by_kappa, cols_by_nu;
+  // index (l2, i); nu = q_r2 - q_d per column (r2, d). Each (a, r1) sends the
+  // u of one label to one rho, so the rows of a rho stay in (a, r1, u) order.
+  const LegLabels V = leg_labels(S.lv, mod);
+  const int nl = (int)V.q.size();
+  int lo = 0, hi = -1;
   for (int a = a0; a < a1; ++a)
     for (int r1 = 0; r1 < Dh; ++r1)
-      for (int u = 0; u < Dv; ++u)
-        rows_by_rho[qnorm(S.ln[a] - S.lh[r1] - S.lv[u], mod)].push_back(
-            (((int64_t)(a - a0) * Dh + r1) * Dv + u) * W);
+      for (int li = 0; li < nl; ++li) {
+        const int k = qnorm(S.ln[a] - S.lh[r1] - V.q[li], mod);
+        if (hi < lo) lo = hi = k;
+        lo = std::min(lo, k);
+        hi = std::max(hi, k);
+      }
+  KeyedLists rows_by_rho(lo, hi, 1);
+  for (int a = a0; a < a1; ++a)
+    for (int r1 = 0; r1 < Dh; ++r1)
+      for (int li = 0; li < nl; ++li) {
+        auto &v = rows_by_rho.first[rows_by_rho.at(qnorm(S.ln[a] - S.lh[r1] - V.q[li], mod), 0)];
+        for (int u : V.members[li]) v.push_back((((int64_t)(a - a0) * Dh + r1) * Dv + u) * W);
+      }
   // (l2, i) and (r2, d) in block order: each kappa (nu) is one contiguous range
+  std::map<int, std::vector<int64_t>> ks_by_kappa, cols_by_nu;
   for (int l2 = 0; l2 < Dh; ++l2)
     for (int i = 0; i < Dv; ++i)
       ks_by_kappa[qnorm(S.lh[l2] - S.lv[i], mod)].push_back(S.pos[(size_t)l2 * Dv + i]);
@@ -309,16 +372,19 @@ Launch plan_proj_y(const StepLegs &S, int a0, int a1, const QSet &sA, const QSet
     for (int d = 0; d < Dv; ++d)
       cols_by_nu[qnorm(S.lh[r2] - S.lv[d], mod)].push_back(S.pos[(size_t)r2 * Dv + d]);
   std::vector<int> kappas;
-  for (const auto &kv : rows_by_rho)
-    for (int s : sA) kappas.push_back(qnorm(kv.first - s, mod));
+  for (int k = 0; k < rows_by_rho.nk; ++k)
+    if (!rows_by_rho.first[k].empty())
+      for (int s : sA) kappas.push_back(qnorm(lo + k - s, mod));
   std::sort(kappas.begin(), kappas.end());
   kappas.erase(std::unique(kappas.begin(), kappas.end()), kappas.end());
   std::vector<GSpec> gs;
   for (int kappa : kappas) {
     std::vector<int64_t> rows, cols, ac, br;
-    for (const auto &kv : rows_by_rho)
-      if (in_set(qnorm(kv.first - kappa, mod), sA))
-        rows.insert(rows.end(), kv.second.begin(), kv.second.end());
+    for (int k = 0; k < rows_by_rho.nk; ++k) {
+      const auto &v = rows_by_rho.first[k];
+      if (!v.empty() && in_set(qnorm(lo + k - kappa, mod), sA))
+        rows.insert(rows.end(), v.begin(), v.end());
+    }
     for (const auto &kv : cols_by_nu)
       if (in_set(qnorm(kappa - kv.first, mod), sB))
         cols.insert(cols.end(), kv.second.begin(), kv.second.end());
@@ -348,20 +414,31 @@ Launch plan_proj_t(const StepLegs &S, int a0, int a1, const QSet &sY, TablePlan 
   const int64_t W = (int64_t)Dh * Dv, per_a = W * W;
   const auto bs = leg_buckets(S.ln, mod);
   const PairBuckets ks = pair_buckets(S.lh, S.lh, 1, 1, mod);  // q_r1 + q_r2
-  // rows (a, u, d) keyed by (w = q_a - q_u + q_d, q_d); group (sigma, q_d)
-  // takes the rows with w - sigma in sY. With q_d fixed, Y's offset splits
-  // into a reduction part (r1, pos of (r2, first d of the label)) and a row
-  // part (a, u, rank of d in its label).
-  std::map<std::pair<int, int>, std::pair<std::vector<int64_t>, std::vector<int64_t>>> rows;
-  std::map<int, int> first_of;
-  for (int d = Dv - 1; d >= 0; --d) first_of[qnorm(S.lv[d], mod)] = d;
+  // rows (a, u, d) keyed by (w = q_a - q_u + q_d, label of d); group
+  // (sigma, label) takes the rows with w - sigma in sY. With the label of d
+  // fixed, Y's offset splits into a reduction part (r1, pos of (r2, first d
+  // of the label)) and a row part (a, u, rank of d in its label).
+  const LegLabels V = leg_labels(S.lv, mod);
+  const int nl = (int)V.q.size();
+  int lo = 0, hi = -1;
   for (int a = a0; a < a1; ++a)
     for (int u = 0; u < Dv; ++u)
-      for (int d = 0; d < Dv; ++d) {
-        const int qd = qnorm(S.lv[d], mod);
-        auto &r = rows[std::make_pair(qnorm(S.ln[a] - S.lv[u] + S.lv[d], mod), qd)];
-        r.first.push_back((int64_t)(a - a0) * per_a + (int64_t)u * W + S.vrank[d]);
-        r.second.push_back((int64_t)a * Dn * Dv * Dv + (int64_t)u * Dv + d);
+      for (int li = 0; li < nl; ++li) {
+        const int k = qnorm(S.ln[a] - S.lv[u] + V.q[li], mod);
+        if (hi < lo) lo = hi = k;
+        lo = std::min(lo, k);
+        hi = std::max(hi, k);
+      }
+  KeyedLists rows(lo, hi, nl);
+  for (int a = a0; a < a1; ++a)
+    for (int u = 0; u < Dv; ++u)
+      for (int li = 0; li < nl; ++li) {
+        const int at = rows.at(qnorm(S.ln[a] - S.lv[u] + V.q[li], mod), li);
+        auto &rf = rows.first[at], &rs = rows.second[at];
+        for (int d : V.members[li]) {
+          rf.push_back((int64_t)(a - a0) * per_a + (int64_t)u * W + S.vrank[d]);
+          rs.push_back((int64_t)a * Dn * Dv * Dv + (int64_t)u * Dv + d);
+        }
       }
   std::vector<GSpec> gs;
   for (const auto &kv : bs) {
@@ -374,14 +451,14 @@ Launch plan_proj_t(const StepLegs &S, int a0, int a1, const QSet &sY, TablePlan 
       bc.push_back(b);
       cc.push_back((int64_t)b * Dv * Dv);
     }
-    for (const auto &fq : first_of) {
-      const int qd = fq.first, d0 = fq.second;
+    for (int li = 0; li < nl; ++li) {
+      const int d0 = V.members[li][0];
       std::vector<int64_t> ar, cr, ac;
       for (int sv : sY) {
-        auto ir = rows.find(std::make_pair(qnorm(sigma + sv, mod), qd));
-        if (ir == rows.end()) continue;
-        ar.insert(ar.end(), ir->second.first.begin(), ir->second.first.end());
-        cr.insert(cr.end(), ir->second.second.begin(), ir->second.second.end());
+        const int at = rows.at(qnorm(sigma + sv, mod), li);
+        if (at < 0) continue;
+        ar.insert(ar.end(), rows.first[at].begin(), rows.first[at].end());
+        cr.insert(cr.end(), rows.second[at].begin(), rows.second[at].end());
       }
       if (ar.empty()) continue;
       if (ik != ks.end())

@@ -75,3 +75,18 @@ def test_autotune_picks_a_tile_and_keeps_results(ctx):
         assert (tile == 64) == (ms64 <= ms128)
     after = ctx.run(pt)
     assert after.lnz_per_site == before.lnz_per_site
+
+
+@pytest.mark.parametrize("chunk_mb", [8, 96])
+def test_projection_chunks_do_not_change_results(ctx, chunk_mb, monkeypatch):
+    """Splitting the projection over the output index a (several chunks, each
+    with its own planned launches) gives the same bits as one chunk: every
+    element of X, Y and T' belongs to exactly one chunk and is reduced in the
+    same order."""
+    pts = [W.Point(beta=1.1, delta=0.6, nmax=5, dcut=24, nsteps=8, impurities=3),
+           W.Point(beta=0.9, delta=0.4, nmax=4, dcut=20, nsteps=7, h1=0.05, impurities=3)]
+    whole = [ctx.run(p) for p in pts]
+    monkeypatch.setenv("GXY_CHUNK_BYTES", str(chunk_mb << 20))
+    for p, w in zip(pts, whole):
+        r = ctx.run(p)
+        assert _same(r, w), (p, r, w)
