@@ -10,12 +10,11 @@
 //  1. tri_reduce: one workgroup per matrix reduces A to tridiagonal form
 //     T = H^T A H with n - 2 Householder reflectors, blocked: the reflectors
 //     v and w-vectors of a panel of 16 columns are applied to the trailing
-//     matrix together (as a rank-32 update), and within the panel each
-//     column and each matrix-vector product is corrected for the pending
-//     ones. The matrix is then read about once per column instead of three
-//     times. The update pairs the same rounded products for (i, k) and
-//     (k, i), so A stays exactly symmetric. Reflector j is kept in row j of
-//     A (right of the diagonal).
+//     matrix together (a rank-32 update on the matrix cores, computed for
+//     the tiles on and below the diagonal and written to both triangles, so
+//     A stays exactly symmetric), and within the panel each column and each
+//     matrix-vector product is corrected for the pending ones. Reflector j
+//     is kept in row j of A (right of the diagonal).
 //  2. tri_bisect: every eigenvalue of T by bisection on Sturm counts, one
 //     thread each (all of them enter the discarded weights).
 //  3. tri_invit: the leading kq = min(n, Dcut) eigenvectors of T, one thread
@@ -39,6 +38,9 @@ namespace {
 
 constexpr int kRedThreads = 1024;
 constexpr int kRedWaves = kRedThreads / 64;
+constexpr int kMvCols = kTriMaxN / 64;   // row segments of 64 per lane in A22 v
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ double wave_sum(double x) {
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
@@ -57,6 +59,25 @@ __device__ double block_sum(double x, double *red) {
   return t;
 }
 
+// Partial sums of A22 v over rows k in [k_lo, k_hi): acc[q] collects the
+// elements lane + 64 q (q < Q = ceil(m / 64)). Loads past m read the last
+// element of the row instead, so every lane loads unconditionally.
+template <int Q>
+__device__ __forceinline__ void mv_partial(const double *A22, int np, int m, int k_lo, int k_hi,
+                                           const double *v, int lane, double *acc) {
+#pragma unroll
+  for (int q = 0; q < Q; ++q) acc[q] = 0.0;
+  int idx[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) idx[q] = min(lane + 64 * q, m - 1);
+  for (int k = k_lo; k < k_hi; ++k) {
+    const double vk = v[k];
+    const double *ra = A22 + (int64_t)k * np;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) acc[q] += ra[idx[q]] * vk;
+  }
+}
+
 // Panel width of the blocked reduction: the reflectors and w-vectors of kNb
 // consecutive columns are applied to the trailing matrix together.
 constexpr int kNb = 16;
@@ -68,7 +89,7 @@ __global__ __launch_bounds__(kRedThreads) void tri_reduce_kernel(
   __shared__ double w[kTriMaxN];
   __shared__ double red[kRedWaves];
   __shared__ double q1[kNb], q2[kNb], vj_s[kNb], wj_s[kNb];
-  __shared__ double pv_s[kNb][64], pw_s[kNb][64];
+  __shared__ double red_w[kRedWaves / 2][kTriMaxN];
   __shared__ double s_tau, s_scal;
   const int mi = blockIdx.x;
   if (mi >= nmat) return;
@@ -153,29 +174,44 @@ __global__ __launch_bounds__(kRedThreads) void tri_reduce_kernel(
           q2[wave] = a2;
         }
       }
-      // A22 v: each wave takes four rows at a time (lanes along the rows), so
-      // four independent load streams are in flight per wave
-      const double *A22 = Am + (int64_t)(j + 1) * np + (j + 1);
-      for (int i0 = 4 * wave; i0 < m; i0 += 4 * kRedWaves) {
-        const int nr = min(4, m - i0);
-        const double *r0 = A22 + (int64_t)i0 * np;
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        for (int k = lane; k < m; k += 64) {
-          const double vk = v[k];
-          a0 += r0[k] * vk;
-          if (nr > 1) a1 += r0[np + k] * vk;
-          if (nr > 2) a2 += r0[2 * (int64_t)np + k] * vk;
-          if (nr > 3) a3 += r0[3 * (int64_t)np + k] * vk;
+      // A22 v, using the symmetry of A22: sum over k of v[k] times row k, so
+      // that lanes run along rows (coalesced) with no cross-lane sums. Each
+      // wave takes a range of k; the partial sums of the 16 waves are added
+      // in a fixed order through LDS.
+      double acc[kMvCols];
+      {
+        const double *A22 = Am + (int64_t)(j + 1) * np + (j + 1);
+        const int k_lo = (wave * m) / kRedWaves, k_hi = ((wave + 1) * m) / kRedWaves;
+        switch ((m + 63) >> 6) {
+#define GXY_MV(Q) \
+  case Q: mv_partial<Q>(A22, np, m, k_lo, k_hi, v, lane, acc); break;
+          GXY_MV(1) GXY_MV(2) GXY_MV(3) GXY_MV(4) GXY_MV(5) GXY_MV(6) GXY_MV(7) GXY_MV(8)
+          GXY_MV(9) GXY_MV(10) GXY_MV(11) GXY_MV(12) GXY_MV(13) GXY_MV(14) GXY_MV(15)
+          GXY_MV(16)
+#undef GXY_MV
+          default: break;
         }
-        a0 = wave_sum(a0);
-        a1 = wave_sum(a1);
-        a2 = wave_sum(a2);
-        a3 = wave_sum(a3);
-        if (lane == 0) {
-          w[i0] = a0;
-          if (nr > 1) w[i0 + 1] = a1;
-          if (nr > 2) w[i0 + 2] = a2;
-          if (nr > 3) w[i0 + 3] = a3;
+        if (wave >= kRedWaves / 2) {
+#pragma unroll
+          for (int q = 0; q < kMvCols; ++q) {
+            const int i = lane + 64 * q;
+            if (64 * q < m && i < m) red_w[wave - kRedWaves / 2][i] = acc[q];
+          }
+        }
+        __syncthreads();
+        if (wave < kRedWaves / 2) {
+#pragma unroll
+          for (int q = 0; q < kMvCols; ++q) {
+            const int i = lane + 64 * q;
+            if (64 * q < m && i < m) red_w[wave][i] = acc[q] + red_w[wave][i];
+          }
+        }
+        __syncthreads();
+        for (int i = tid; i < m; i += kRedThreads) {
+          double x = 0.0;
+#pragma unroll
+          for (int h = 0; h < kRedWaves / 2; ++h) x += red_w[h][i];
+          w[i] = x;
         }
       }
       __syncthreads();
@@ -194,43 +230,65 @@ __global__ __launch_bounds__(kRedThreads) void tri_reduce_kernel(
       for (int i = tid; i < m; i += kRedThreads) wcol[j + 1 + i] = w[i] + K * v[i];
       __syncthreads();
     }
-    // trailing matrix (rows and columns >= jend) -= V W^T + W V^T; each term
-    // pairs the same two rounded products for (r, c) and (c, r), so A stays
-    // exactly symmetric
+    // trailing matrix (rows and columns >= jend) -= U = V W^T + W V^T, as a
+    // K = 32 product on the matrix cores: U[r][c] = sum_k L[r][k] R[c][k]
+    // with L[r] = (V[.][r], W[.][r]) and R[c] = (W[.][c], V[.][c]) (zero past
+    // the panel width). Each wave takes 32 x 32 tiles on or below the
+    // diagonal and writes every new value to (r, c) and (c, r), so A stays
+    // exactly symmetric.
     const int tp = jend - j0;
-    for (int c0 = jend; c0 < n; c0 += 64) {
-      for (int e2 = tid; e2 < 64 * tp; e2 += kRedThreads) {
-        const int s2 = e2 / 64, cl = e2 % 64;
-        const int c = c0 + cl;
-        pv_s[s2][cl] = c < n ? Vg[(int64_t)s2 * n + c] : 0.0;
-        pw_s[s2][cl] = c < n ? Wg[(int64_t)s2 * n + c] : 0.0;
-      }
-      __syncthreads();
-      const int c = c0 + lane;
-      // four rows per wave at a time: their loads are independent
-      for (int r0 = jend + 4 * wave; r0 < n; r0 += 4 * kRedWaves) {
-        if (c < n) {
-          double u[4] = {0.0, 0.0, 0.0, 0.0};
-          for (int s2 = 0; s2 < tp; ++s2) {
-            const double pw = pw_s[s2][lane], pv = pv_s[s2][lane];
+    const int mt = n - jend;
+    const int nt = (mt + 31) / 32;
+    const int ntiles = nt * (nt + 1) / 2;
+    const int li = lane & 15, lk = lane >> 4;
+    for (int tix = wave; tix < ntiles; tix += kRedWaves) {
+      int I = (int)((sqrt(8.0 * tix + 1.0) - 1.0) * 0.5);
+      while (I * (I + 1) / 2 > tix) --I;
+      while ((I + 1) * (I + 2) / 2 <= tix) ++I;
+      const int J = tix - I * (I + 1) / 2;
+      const int r0 = jend + 32 * I, c0 = jend + 32 * J;
+      double4_t acc[2][2];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const int r = min(r0 + q, n - 1);
-              u[q] = __dadd_rn(u[q], __dadd_rn(__dmul_rn(Vg[(int64_t)s2 * n + r], pw),
-                                               __dmul_rn(Wg[(int64_t)s2 * n + r], pv)));
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = double4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < 32; kk += 4) {
+        const int k = kk + lk;
+        const int s2 = k & 15;
+        const double *Lp = (k < 16 ? Vg : Wg) + (int64_t)s2 * n;
+        const double *Rp = (k < 16 ? Wg : Vg) + (int64_t)s2 * n;
+        // (columns s2 >= tp of the panel hold stale values: read, then zero)
+        double fa[2], fb[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          const int r = r0 + 16 * a + li, c = c0 + 16 * a + li;
+          const double x = Lp[min(r, n - 1)], y = Rp[min(c, n - 1)];
+          fa[a] = (s2 < tp && r < n) ? x : 0.0;
+          fb[a] = (s2 < tp && c < n) ? y : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0, 0);
+      }
+      // accumulator register q of lane l: row l/16 + 4q, column l%16
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int r = r0 + 16 * a + lk + 4 * q, c = c0 + 16 * b + li;
+            if (r < n && c < n && (I != J || r >= c)) {
+              const double nv = Am[(int64_t)r * np + c] - acc[a][b][q];
+              Am[(int64_t)r * np + c] = nv;
+              if (r != c) Am[(int64_t)c * np + r] = nv;
             }
           }
-          double av[4];
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-            av[q] = r0 + q < n ? Am[(int64_t)(r0 + q) * np + c] : 0.0;
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-            if (r0 + q < n) Am[(int64_t)(r0 + q) * np + c] = av[q] - u[q];
-        }
-      }
-      __syncthreads();
     }
+    __syncthreads();
   }
   if (tid == 0) {
     if (n >= 2) {
