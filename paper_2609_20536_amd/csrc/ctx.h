@@ -41,11 +41,16 @@ struct gxy_ctx {
   size_t stage_bytes[3] = {0, 0, 0};
   hipEvent_t stage_ev[3] = {nullptr, nullptr, nullptr};
   bool stage_used[3] = {false, false, false};
-  // pinned arena for the projection tables of one step
-  void *arena = nullptr;
-  size_t arena_bytes = 0, arena_cur = 0;
-  hipEvent_t arena_ev = nullptr;
-  bool arena_pending = false;
+  // pinned arenas for the projection tables of a step, by step parity
+  void *arena[2] = {nullptr, nullptr};
+  size_t arena_bytes[2] = {0, 0};
+  hipEvent_t arena_ev[2] = {nullptr, nullptr};
+  bool arena_pending[2] = {false, false};
+  // second stream for the impurity projections, and the events that order
+  // it against the main stream (slots: see run_one)
+  hipStream_t imp_stream = nullptr;
+  hipEvent_t pipe_ev[8] = {nullptr, nullptr, nullptr, nullptr,
+                           nullptr, nullptr, nullptr, nullptr};
   hipEvent_t sel_ev = nullptr;  // selection results copied to the host
   // side stream for the projection table copies, with one event per launch
   hipStream_t copy_stream = nullptr;

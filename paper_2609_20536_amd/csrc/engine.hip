@@ -92,7 +92,12 @@ struct Plan {
   int64_t tab_env = 0, tab_proj = 0;  // offset-table entries (bounds)
   int64_t grp_env = 0, grp_proj = 0;  // group descriptors (bounds)
   int64_t proj_bytes = 0;             // projection slices of one step (bound)
+  // impurity projections on a second stream, one step behind the pure
+  // tensor's chain (charge blocks, impurities, one chunk per step)
+  bool overlap = false;
 };
+
+static int sym_of(const gxy_point &p);
 
 static Plan make_plan(const gxy_point &p, size_t chunk_bytes) {
   Plan pl;
@@ -129,6 +134,8 @@ static Plan make_plan(const gxy_point &p, size_t chunk_bytes) {
   int64_t ac = (int64_t)(chunk_bytes / (sizeof(double) * nbuf * per_a_max));
   ac = std::max<int64_t>(1, std::min<int64_t>(ac, pl.maxDn));
   pl.chunk_elems = ac * per_a_max;
+  pl.overlap = sym_of(p) != SYM_NONE && pl.nimp > 0 && ac >= pl.maxDn &&
+               !getenv("GXY_NO_OVERLAP");
   // bounds of the charge-block tables of one step (see plan.hip): every row,
   // reduction and column index appears in at most |S| <= 2 groups per table
   const int64_t nvar = 1 + 2 * pl.nimp;
@@ -157,8 +164,13 @@ struct Buffers {
   double *T, *Tn, *T2;             // site tensor, next, bottom-operand copy
   double *TX[2], *TXn[2], *TX2[2]; // impurity tensors
   double *envA, *envB, *E;         // environments
-  double *P;
-  double *X, *XI, *Y;              // projection chunks
+  double *P;                       // projector of the current step
+  double *X, *XI, *Y, *YI;         // projection chunks (YI: impurity stream)
+  // per step parity: what the impurity stream of step n reads while the
+  // pure chain runs step n + 1
+  double *Pb[2], *Xb[2], *T2b[2];
+  int32_t *permb[2];
+  char *tabb[2];
   double *eigA, *eigV, *eigQ, *eigB1, *eigB2;
   int64_t *gtab;
   GGroup *ggrp;
@@ -187,7 +199,9 @@ static size_t carve(const gxy_point &p, const Plan &pl, Carver &c, Buffers &b) {
   const int64_t T = pl.maxT;
   b.T = c.take<double>(T);
   b.Tn = c.take<double>(T);
-  b.T2 = c.take<double>(T);
+  b.T2b[0] = c.take<double>(T);
+  b.T2b[1] = pl.overlap ? c.take<double>(T) : b.T2b[0];
+  b.T2 = b.T2b[0];
   for (int k = 0; k < 2; ++k) {
     const bool on = k < pl.nimp;
     b.TX[k] = on ? c.take<double>(T) : nullptr;
@@ -198,10 +212,15 @@ static size_t carve(const gxy_point &p, const Plan &pl, Carver &c, Buffers &b) {
   b.envB = c.take<double>(T);
   const int64_t nf = pl.maxNF;
   b.E = c.take<double>(2 * nf * nf);
-  b.P = c.take<double>(std::max<int64_t>(pl.maxPD, 1));
-  b.X = c.take<double>(pl.chunk_elems);
+  b.Pb[0] = c.take<double>(std::max<int64_t>(pl.maxPD, 1));
+  b.Pb[1] = pl.overlap ? c.take<double>(std::max<int64_t>(pl.maxPD, 1)) : b.Pb[0];
+  b.P = b.Pb[0];
+  b.Xb[0] = c.take<double>(pl.chunk_elems);
+  b.Xb[1] = pl.overlap ? c.take<double>(pl.chunk_elems) : b.Xb[0];
+  b.X = b.Xb[0];
   b.XI = pl.nimp > 0 ? c.take<double>(pl.chunk_elems) : nullptr;
   b.Y = c.take<double>(pl.chunk_elems);
+  b.YI = pl.overlap ? c.take<double>(pl.chunk_elems) : b.Y;
   // eigen: per side sum of npad^2 <= nf^2 + 1023 nf
   b.eig_elems = 2 * (nf * nf + 1023 * nf);
   b.eigA = c.take<double>(std::max<int64_t>(b.eig_elems, 1));
@@ -237,9 +256,14 @@ static size_t carve(const gxy_point &p, const Plan &pl, Carver &c, Buffers &b) {
   b.coef = c.take<double>(pl.d0 + 3 * (2 * qmax + 1));
   b.scal = c.take<double>(16);
   b.tab_env = c.take<int64_t>(pl.tab_env);
-  b.perm = c.take<int32_t>(std::max<int64_t>(pl.maxW, 1));
+  for (int q = 0; q < 2; ++q) {
+    b.permb[q] = (q == 0 || pl.overlap) ? c.take<int32_t>(std::max<int64_t>(pl.maxW, 1))
+                                        : b.permb[0];
+    b.tabb[q] = (q == 0 || pl.overlap) ? c.take<char>(pl.proj_bytes) : b.tabb[0];
+  }
+  b.perm = b.permb[0];
+  b.proj_tab = b.tabb[0];
   b.grp_env = c.take<GGroup>(pl.grp_env);
-  b.proj_tab = c.take<char>(pl.proj_bytes);
   return c.off + 256;
 }
 
@@ -295,30 +319,40 @@ struct ProjArena {
   int32_t *perm = nullptr;  // block-order permutation of the step
 };
 
-static void proj_stage_begin(gxy_ctx *ctx, ProjArena &A, int64_t cap, int64_t perm_cap) {
-  if (ctx->arena_pending) GXY_HIP(hipEventSynchronize(ctx->arena_ev));
-  ctx->arena_pending = false;
+static void proj_stage_begin(gxy_ctx *ctx, int q, ProjArena &A, int64_t cap, int64_t perm_cap) {
+  if (ctx->arena_pending[q]) GXY_HIP(hipEventSynchronize(ctx->arena_ev[q]));
+  ctx->arena_pending[q] = false;
   const size_t cb = ((size_t)cap + 255) & ~(size_t)255;
   const size_t need = cb + (size_t)perm_cap * sizeof(int32_t);
-  if (ctx->arena_bytes < need) {
-    if (ctx->arena) GXY_HIP(hipHostFree(ctx->arena));
-    ctx->arena = nullptr;
-    ctx->arena_bytes = 0;
-    GXY_HIP(hipHostMalloc(&ctx->arena, need, hipHostMallocDefault));
-    ctx->arena_bytes = need;
+  if (ctx->arena_bytes[q] < need) {
+    if (ctx->arena[q]) GXY_HIP(hipHostFree(ctx->arena[q]));
+    ctx->arena[q] = nullptr;
+    ctx->arena_bytes[q] = 0;
+    GXY_HIP(hipHostMalloc(&ctx->arena[q], need, hipHostMallocDefault));
+    ctx->arena_bytes[q] = need;
   }
-  A.base = (char *)ctx->arena;
+  A.base = (char *)ctx->arena[q];
   A.cap = cap;
   A.used = 0;
   A.perm = (int32_t *)(A.base + cb);
 }
 
-// After the last launch of a step: the arena may be reused once this event
-// has completed (every copy precedes its launch on the compute stream).
-static void proj_stage_done(gxy_ctx *ctx, hipStream_t s) {
-  if (!ctx->arena_ev) GXY_HIP(hipEventCreateWithFlags(&ctx->arena_ev, hipEventDisableTiming));
-  GXY_HIP(hipEventRecord(ctx->arena_ev, s));
-  ctx->arena_pending = true;
+// After the last launch of a step that reads arena q's tables (on stream s):
+// the arena may be reused once this event has completed (every copy
+// precedes its launch).
+static void proj_stage_done(gxy_ctx *ctx, int q, hipStream_t s) {
+  if (!ctx->arena_ev[q])
+    GXY_HIP(hipEventCreateWithFlags(&ctx->arena_ev[q], hipEventDisableTiming));
+  GXY_HIP(hipEventRecord(ctx->arena_ev[q], s));
+  ctx->arena_pending[q] = true;
+}
+
+// Stream b waits for what stream a has been given so far (no-op for a == b).
+static void stream_after(gxy_ctx *ctx, hipStream_t b, hipStream_t a, int slot) {
+  if (a == b) return;
+  if (!ctx->pipe_ev[slot]) GXY_HIP(hipEventCreateWithFlags(&ctx->pipe_ev[slot], hipEventDisableTiming));
+  GXY_HIP(hipEventRecord(ctx->pipe_ev[slot], a));
+  GXY_HIP(hipStreamWaitEvent(b, ctx->pipe_ev[slot], 0));
 }
 
 // One planned projection launch and its slice of the arena.
@@ -905,6 +939,25 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
     carve(p, pl, c, b);
   }
   ensure_pinned(ctx, 1 << 20);
+  // impurity stream: the impurity projections of step n run there while the
+  // main stream goes on with step n + 1 (its environments and eigensolves
+  // leave most compute units idle). Event slots: 0 initial tensors, 1 X of
+  // the step ready, 2 norm of the step ready, 3 end of the run, 4 + parity
+  // the impurity stream is done with that parity's buffers.
+  if (pl.overlap && !ctx->imp_stream)
+    GXY_HIP(hipStreamCreateWithFlags(&ctx->imp_stream, hipStreamNonBlocking));
+  const hipStream_t si = pl.overlap ? ctx->imp_stream : s;
+  struct ImpGuard {
+    hipStream_t si, s;
+    ~ImpGuard() {
+      if (si != s) (void)hipStreamSynchronize(si);
+    }
+  } impg{si, s};
+  auto record_on = [&](hipStream_t st, int slot) {
+    if (!ctx->pipe_ev[slot])
+      GXY_HIP(hipEventCreateWithFlags(&ctx->pipe_ev[slot], hipEventDisableTiming));
+    GXY_HIP(hipEventRecord(ctx->pipe_ev[slot], st));
+  };
   Timer tm;
   tm.on = env_flag("GXY_TIMING");
   ctx->hot_on = tm.on || ctx->hot_force || env_flag("GXY_HOT_EVENTS");
@@ -957,6 +1010,7 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
   launch_fro_norm(b.T, nT, b.partial, b.nrm, s);
   launch_scale(b.T, nT, b.nrm + 2, s);
   for (int k = 0; k < nimp; ++k) launch_scale(b.TX[k], nT, b.nrm + 2, s);
+  stream_after(ctx, si, s, 0);
   tm.end(0);
 
   const int mod = (sym == SYM_U1) ? 0 : (sym == SYM_Z2 ? 2 : 1);
@@ -984,13 +1038,22 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
   int32_t *hp = (int32_t *)ctx->pinned;
   for (int n = 1; n <= p.nsteps; ++n) {
     const StepDims &sd = pl.steps[n - 1];
+    // buffers of this step's parity; the impurity stream read them last in
+    // step n - 2
+    const int par = n & 1;
+    b.P = b.Pb[par];
+    b.X = b.Xb[par];
+    b.T2 = b.T2b[par];
+    b.perm = b.permb[par];
+    b.proj_tab = b.tabb[par];
+    if (si != s && n > 2) GXY_HIP(hipStreamWaitEvent(s, ctx->pipe_ev[4 + par], 0));
     if (sd.xstep) {
       // T[l][r][u][d] -> T[u][d][l][r]
       tm.begin();
       launch_swap_pairs(b.T, b.Tn, Dh, Dh, Dv, Dv, s);
       std::swap(b.T, b.Tn);
       for (int k = 0; k < nimp; ++k) {
-        launch_swap_pairs(b.TX[k], b.TXn[k], Dh, Dh, Dv, Dv, s);
+        launch_swap_pairs(b.TX[k], b.TXn[k], Dh, Dh, Dv, Dv, si);
         std::swap(b.TX[k], b.TXn[k]);
       }
       std::swap(Dh, Dv);
@@ -1139,11 +1202,12 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
       // soon as it is ready, so the device runs one launch while the host
       // plans the next.
       ProjArena arena;
-      proj_stage_begin(ctx, arena, pl.proj_bytes, pl.maxW);
+      proj_stage_begin(ctx, par, arena, pl.proj_bytes, pl.maxW);
       if (!ctx->copy_stream)
         GXY_HIP(hipStreamCreateWithFlags(&ctx->copy_stream, hipStreamNonBlocking));
-      // (the host has seen the previous step's last launch complete, in
-      // proj_stage_begin, so the device slices are free for the side stream)
+      // (proj_stage_begin has seen the last launches that read this
+      // parity's device slices complete, two steps ago, so the side stream
+      // may overwrite them)
       int proj_tile = ctx->force_tile;
       if (!proj_tile) {
         const auto it = ctx->tile_for_dcut.find(p.dcut);
@@ -1213,11 +1277,18 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
         GXY_HIP(hipMemcpyAsync(b.perm, arena.perm, Wn * sizeof(int32_t), hipMemcpyHostToDevice,
                                s));
         launch_block_gather(b.T, b.T2, b.perm, Dh, Dv, s);
-        for (int k = 0; k < nimp; ++k) launch_block_gather(b.TX[k], b.TX2[k], b.perm, Dh, Dv, s);
       }
       const int64_t nTn = (int64_t)Dn * Dn * Dv * Dv;
       launch_fill(b.Tn, nTn, 0.0, s);
-      for (int k = 0; k < nimp; ++k) launch_fill(b.TXn[k], nTn, 0.0, s);
+      // the impurity stream's share (once it has the step's X, T2, P, perm)
+      bool imp_started = false;
+      auto imp_start = [&]() {
+        if (imp_started) return;
+        imp_started = true;
+        stream_after(ctx, si, s, 1);
+        for (int k = 0; k < nimp; ++k) launch_block_gather(b.TX[k], b.TX2[k], b.perm, Dh, Dv, si);
+        for (int k = 0; k < nimp; ++k) launch_fill(b.TXn[k], nTn, 0.0, si);
+      };
       size_t next = 0;
       auto take = [&](int i, int kd) -> ProjJob & {
         // jobs are consumed in spawn order; an impurity T' is used twice
@@ -1227,34 +1298,37 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
           planned[next].get();
           ++next;
         }
-        ProjJob &j = parts[i].job[kd];
-        send_plan(ctx, arena, j, b.proj_tab, s, (size_t)i * NKIND + kd);
-        return j;
+        return parts[i].job[kd];
       };
       auto go = [&](ProjJob &j, const double *A, const double *B, double *C, double alpha,
-                    double beta, bool hot) {
+                    double beta, bool hot, hipStream_t st, size_t slot) {
+        send_plan(ctx, arena, j, b.proj_tab, st, slot);
         const GGroup *dg = reinterpret_cast<const GGroup *>(b.proj_tab + j.off);
         const int64_t *dt = reinterpret_cast<const int64_t *>(b.proj_tab + j.off +
                                                               j.ngrp * (int64_t)sizeof(GGroup));
-        if (hot) hot_begin(ctx, s, j.L.flops, j.L.bytes);
-        run_launch(j.L, dg, dt, A, B, C, alpha, beta, s, sprec);
-        if (hot) hot_end(ctx, s);
+        if (hot) hot_begin(ctx, st, j.L.flops, j.L.bytes);
+        run_launch(j.L, dg, dt, A, B, C, alpha, beta, st, sprec);
+        if (hot) hot_end(ctx, st);
       };
+      // (with chunks, both streams are the main one: the next chunk's X
+      // overwrites the X the impurity launches read)
       for (int i = 0; i < (int)parts.size(); ++i) {
         const int k = parts[i].k;
+        const size_t sl = (size_t)i * NKIND;
         if (k < 0) {
-          go(take(i, PX), b.P, b.T, b.X, 1.0, 0.0, false);
-          go(take(i, PY), b.X, b.T2, b.Y, 1.0, 0.0, true);
-          go(take(i, PT), b.Y, b.P, b.Tn, 1.0, 0.0, false);
+          go(take(i, PX), b.P, b.T, b.X, 1.0, 0.0, false, s, sl + PX);
+          if (nimp > 0) imp_start();
+          go(take(i, PY), b.X, b.T2, b.Y, 1.0, 0.0, true, s, sl + PY);
+          go(take(i, PT), b.Y, b.P, b.Tn, 1.0, 0.0, false, s, sl + PT);
         } else {
-          go(take(i, IY), b.X, b.TX2[k], b.Y, 1.0, 0.0, true);
-          go(take(i, IT), b.Y, b.P, b.TXn[k], 0.5, 0.0, false);
-          go(take(i, IX2), b.P, b.TX[k], b.XI, 1.0, 0.0, false);
-          go(take(i, IY2), b.XI, b.T2, b.Y, 1.0, 0.0, true);
-          go(take(i, IT), b.Y, b.P, b.TXn[k], 0.5, 1.0, false);
+          go(take(i, IY), b.X, b.TX2[k], b.YI, 1.0, 0.0, true, si, sl + IY);
+          go(take(i, IT), b.YI, b.P, b.TXn[k], 0.5, 0.0, false, si, sl + IT);
+          go(take(i, IX2), b.P, b.TX[k], b.XI, 1.0, 0.0, false, si, sl + IX2);
+          go(take(i, IY2), b.XI, b.T2, b.YI, 1.0, 0.0, true, si, sl + IY2);
+          go(take(i, IT), b.YI, b.P, b.TXn[k], 0.5, 1.0, false, si, sl + IT);
         }
       }
-      proj_stage_done(ctx, s);
+      if (si != s) record_on(si, 4 + par);
     }
     tm.end(4);
     tm.begin();
@@ -1263,16 +1337,20 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
     launch_fro_norm(b.Tn, nT, b.partial, b.nrm + 3 * n, s);
     launch_scale(b.Tn, nT, b.nrm + 3 * n + 2, s);
     std::swap(b.T, b.Tn);
+    stream_after(ctx, si, s, 2);
     for (int k = 0; k < nimp; ++k) {
-      launch_scale(b.TXn[k], nT, b.nrm + 3 * n + 2, s);
+      launch_scale(b.TXn[k], nT, b.nrm + 3 * n + 2, si);
       std::swap(b.TX[k], b.TXn[k]);
     }
+    // the step's tables have been read by both streams' launches once the
+    // impurity stream gets here
+    if (sym != SYM_NONE) proj_stage_done(ctx, par, si);
     lh = new_lh;
     if (sd.xstep) {
       launch_swap_pairs(b.T, b.Tn, Dh, Dh, Dv, Dv, s);
       std::swap(b.T, b.Tn);
       for (int k = 0; k < nimp; ++k) {
-        launch_swap_pairs(b.TX[k], b.TXn[k], Dh, Dh, Dv, Dv, s);
+        launch_swap_pairs(b.TX[k], b.TXn[k], Dh, Dh, Dv, Dv, si);
         std::swap(b.TX[k], b.TXn[k]);
       }
       std::swap(Dh, Dv);
@@ -1285,6 +1363,7 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
     log.steps.push_back(info);
   }
   // ---- trace and result ----
+  stream_after(ctx, s, si, 3);
   double *tr = b.scal, *tr1 = b.scal + 1, *tr2 = b.scal + 2, *rr = b.scal + 4;
   launch_trace(b.T, Dh, Dv, tr, s);
   const double *trk[2] = {nullptr, nullptr};
@@ -1376,17 +1455,21 @@ gxy_status gxy_destroy(gxy_ctx *ctx) {
   }
   ctx->children.clear();
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->imp_stream) (void)hipStreamSynchronize(ctx->imp_stream);
+  if (ctx->copy_stream) (void)hipStreamSynchronize(ctx->copy_stream);
   if (ctx->ws && ctx->ws_owned) (void)hipFree(ctx->ws);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
-  if (ctx->arena_ev) (void)hipEventDestroy(ctx->arena_ev);
+  for (int q = 0; q < 2; ++q) {
+    if (ctx->arena_ev[q]) (void)hipEventDestroy(ctx->arena_ev[q]);
+    if (ctx->arena[q]) (void)hipHostFree(ctx->arena[q]);
+  }
+  for (hipEvent_t e : ctx->pipe_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (ctx->imp_stream) (void)hipStreamDestroy(ctx->imp_stream);
   if (ctx->sel_ev) (void)hipEventDestroy(ctx->sel_ev);
   for (hipEvent_t e : ctx->copy_ev) (void)hipEventDestroy(e);
-  if (ctx->copy_stream) {
-    (void)hipStreamSynchronize(ctx->copy_stream);
-    (void)hipStreamDestroy(ctx->copy_stream);
-  }
-  if (ctx->arena) (void)hipHostFree(ctx->arena);
+  if (ctx->copy_stream) (void)hipStreamDestroy(ctx->copy_stream);
   for (int j = 0; j < 3; ++j) {
     if (ctx->stage_ev[j]) (void)hipEventDestroy(ctx->stage_ev[j]);
     if (ctx->stage[j]) (void)hipHostFree(ctx->stage[j]);
