@@ -18,9 +18,9 @@ Two more legs ride on the same line (both skippable):
 * "batched": a stratified 16-point subset of the 16 x 16 (beta, Delta) grid
   (4 points per Dcut in {24, 32, 48, 64}), three runs per point (beta - db,
   beta, beta + db; f and C_v): points/s of the plain FP64 path (runs one
-  after another), and, after the per-Dcut tile autotuner, of one batch on 8
-  worker streams in FP64 and with BF16x3 + schedule; max |d f| of the
-  latter against FP64.
+  after another), and, after the per-Dcut tile autotuner, of one batch on 16
+  worker streams (16 hardware queues for the process) in FP64 and with
+  BF16x3 + schedule; max |d f| of the latter against FP64.
 """
 
 from __future__ import annotations
@@ -32,6 +32,11 @@ import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
+# hardware queues of this process (HIP reads it when it starts): the batched
+# leg runs BATCH_WORKERS streams, and streams beyond the queue count share
+# queues, which serialises their kernels
+BATCH_WORKERS = 16
+os.environ.setdefault("GPU_MAX_HW_QUEUES", str(BATCH_WORKERS))
 sys.path.insert(0, ROOT)
 
 METRIC = "HOTRG steps/s & MFMA util at D=64; batched (β,Δ) points/s at |δf|≤1e-9"
@@ -103,12 +108,14 @@ def batched_leg(ctx, note):
     tiles = ctx.autotune(W.Point(beta=1.0, delta=0.5, nmax=10, dcut=24, nsteps=10,
                                  impurities=0), list(W.GRID_DCUTS))
     note("bench: tile autotuner done")
-    out = {"points": len(sub), "runs_per_point": 3, "workers": 8,
+    out = {"points": len(sub), "runs_per_point": 3, "workers": BATCH_WORKERS,
+           "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
            "plain": "the same runs one after another on one stream (FP64)",
            "tiles": {str(k): v[0] for k, v in tiles.items()}}
     res = {}
-    for name, prec, k, workers in (("plain_fp64", W.PREC_FP64, 0, 1), ("fp64", W.PREC_FP64, 0, 8),
-                                   ("bf16x3", W.PREC_BF16X3, 16, 8)):
+    for name, prec, k, workers in (("plain_fp64", W.PREC_FP64, 0, 1),
+                                   ("fp64", W.PREC_FP64, 0, BATCH_WORKERS),
+                                   ("bf16x3", W.PREC_BF16X3, 16, BATCH_WORKERS)):
         pts = runs(prec, k)
         ctx.run_batch(pts[:3], workers=workers)
         t0 = time.perf_counter()

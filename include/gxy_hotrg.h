@@ -143,7 +143,11 @@ gxy_status gxy_run(gxy_ctx *ctx, const gxy_point *pt, gxy_result *out);
  * queue by W host threads, each driving its own worker context: own
  * non-blocking stream, own device workspace (library-allocated, projection
  * chunks of at most 4 GiB), the caller's autotuned tiles. Small-Dcut runs
- * overlap the launch and host latency of the large ones. Results are in
+ * overlap the launch and host latency of the large ones. Workers keep to
+ * their one stream; HIP maps streams onto GPU_MAX_HW_QUEUES hardware queues
+ * per process (4 unless set before HIP starts), and streams that share a
+ * queue run their kernels one after another, so W workers want at least W
+ * queues. Results are in
  * input order and identical, bit for bit, to gxy_run of each point. Per-run
  * status in out[i].status (failed runs: NaN outputs); GXY_EPARTIAL if any
  * run failed, GXY_EDEVICE (remaining runs not started) on a device error. */

@@ -63,6 +63,7 @@ struct gxy_ctx {
   // batched runs: worker contexts, each with its own stream and workspace
   int batch_workers = 0;  // 0 = default
   size_t chunk_bytes = 0;  // projection chunk bound (0: GXY_CHUNK_BYTES or 32 GiB)
+  bool worker = false;     // batch worker: one stream, no side streams
   std::vector<gxy_ctx *> children;
 };
 

@@ -99,7 +99,7 @@ struct Plan {
 
 static int sym_of(const gxy_point &p);
 
-static Plan make_plan(const gxy_point &p, size_t chunk_bytes) {
+static Plan make_plan(const gxy_point &p, size_t chunk_bytes, bool allow_overlap = true) {
   Plan pl;
   pl.d0 = 2 * p.nmax + 1;
   int Dh = pl.d0, Dv = pl.d0;
@@ -134,7 +134,7 @@ static Plan make_plan(const gxy_point &p, size_t chunk_bytes) {
   int64_t ac = (int64_t)(chunk_bytes / (sizeof(double) * nbuf * per_a_max));
   ac = std::max<int64_t>(1, std::min<int64_t>(ac, pl.maxDn));
   pl.chunk_elems = ac * per_a_max;
-  pl.overlap = sym_of(p) != SYM_NONE && pl.nimp > 0 && ac >= pl.maxDn &&
+  pl.overlap = allow_overlap && sym_of(p) != SYM_NONE && pl.nimp > 0 && ac >= pl.maxDn &&
                !getenv("GXY_NO_OVERLAP");
   // bounds of the charge-block tables of one step (see plan.hip): every row,
   // reduction and column index appears in at most |S| <= 2 groups per table
@@ -380,7 +380,9 @@ static void stage_plan(ProjArena &A, const TablePlan &tp, const Launch &L, ProjJ
 static void send_plan(gxy_ctx *ctx, const ProjArena &A, ProjJob &j, char *d_area, hipStream_t s,
                       size_t k) {
   if (j.sent) return;
-  if (j.bytes) {
+  if (j.bytes && ctx->worker) {   // batch worker: copy on its own stream
+    GXY_HIP(hipMemcpyAsync(d_area + j.off, A.base + j.off, j.bytes, hipMemcpyHostToDevice, s));
+  } else if (j.bytes) {
     while (ctx->copy_ev.size() <= k) {
       hipEvent_t e;
       GXY_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -928,7 +930,9 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
   const hipStream_t s = ctx->stream;
   const size_t chunk_bytes =
       ctx->chunk_bytes ? ctx->chunk_bytes : env_size("GXY_CHUNK_BYTES", kDefaultChunkBytes);
-  const Plan pl = make_plan(p, chunk_bytes);
+  // batch workers keep to their one stream: many workers already fill the
+  // device, and every extra stream shares the few hardware queues
+  const Plan pl = make_plan(p, chunk_bytes, !ctx->worker);
   Buffers b{};
   {
     Carver c0;
@@ -1203,7 +1207,7 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
       // plans the next.
       ProjArena arena;
       proj_stage_begin(ctx, par, arena, pl.proj_bytes, pl.maxW);
-      if (!ctx->copy_stream)
+      if (!ctx->copy_stream && !ctx->worker)
         GXY_HIP(hipStreamCreateWithFlags(&ctx->copy_stream, hipStreamNonBlocking));
       // (proj_stage_begin has seen the last launches that read this
       // parity's device slices complete, two steps ago, so the side stream
@@ -1595,6 +1599,7 @@ gxy_status gxy_run_batch(gxy_ctx *ctx, const gxy_point *pts, int32_t n, gxy_resu
         c->device = ctx->device;
         c->stream = cs;
         c->chunk_bytes = (size_t)4 << 30;   // smaller projection chunks per worker
+        c->worker = true;
         ctx->children.push_back(c);
       }
       hipEvent_t ev = nullptr;
