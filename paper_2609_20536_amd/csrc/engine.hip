@@ -839,7 +839,9 @@ static SectorSolve solve_sectors(gxy_ctx *ctx, hipStream_t s, const double *E, i
     EigBatch eg = eb;
     eg.V = nullptr;
     launch_eig_gather(E, nf, r.d_idx, r.d_start, r.d_n, nsec, eg, s);
-    launch_tri_values(nmat, nsec, r.d_n, eb.d_npad, eb.d_off, m.A, m.B1, m.B2, s);
+    std::vector<int> hn(sec.n.begin(), sec.n.end());
+    launch_tri_values(nmat, nsec, hn.data(), r.d_n, eb.d_npad, eb.d_off, m.A, m.B1, m.V, m.B2,
+                      !ctx->worker, s);
     r.eb.A = m.A;
     r.eb.V = m.V;
     r.sweeps = 0;

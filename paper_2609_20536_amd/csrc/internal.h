@@ -190,18 +190,25 @@ void launch_eig_identity(const EigBatch &b, double *V, hipStream_t s);
 // y = a x over n elements
 void launch_eig_scaled_copy(int64_t n, double a, const double *x, double *y, hipStream_t s);
 
-// Tridiagonal path for sector matrices of at most kTriMaxN rows (one
-// workgroup per matrix), in two stages. launch_tri_values: A (gathered
-// padded matrices) is overwritten with the reflectors right of the diagonal
-// and the decreasing eigenvalues on the diagonal; work (shaped like A) keeps
-// d, e, tau and the eigenvalues; Y is scratch. launch_tri_vectors: the
+// Tridiagonal path for sector matrices of at most kTriMaxN rows, in two
+// stages. launch_tri_values: A (gathered padded matrices) is overwritten
+// with the reflectors right of the diagonal and the decreasing eigenvalues
+// on the diagonal; work (shaped like A) keeps d, e, tau and the eigenvalues;
+// Y and X (shaped like A) are scratch; h_sec_n holds the nsec sector sizes
+// on the host. With allow_multi the reduction shares each large matrix
+// between several workgroups of one cooperative launch when the device can
+// hold the whole grid at once (GXY_TRI_MULTI=0 keeps one workgroup per
+// matrix); callers that may run two such launches at once (batch workers)
+// pass false, since two half-placed cooperative grids would wait on each
+// other. launch_tri_vectors: the
 // leading min(n, kmax) eigenvectors into V (row-major, column c = c-th
 // largest), for the matrices of side *d_side (0: the first nsec, 1: the
 // rest) or for all if d_side is null; Y is scratch.
 constexpr int kTriMaxN = 1024;
 constexpr int kTriMaxVecs = 128;   // eigenvectors formed per matrix
-void launch_tri_values(int nmat, int nsec, const int32_t *d_sec_n, const int32_t *d_npad,
-                       const int64_t *d_off, double *A, double *Y, double *work, hipStream_t s);
+void launch_tri_values(int nmat, int nsec, const int *h_sec_n, const int32_t *d_sec_n,
+                       const int32_t *d_npad, const int64_t *d_off, double *A, double *Y,
+                       double *X, double *work, bool allow_multi, hipStream_t s);
 void launch_tri_vectors(int nmat, int nsec, const int32_t *d_sec_n, const int32_t *d_npad,
                         const int64_t *d_off, const double *A, double *V, double *Y,
                         const double *work, int kmax, const double *d_side, hipStream_t s);

@@ -1,4 +1,4 @@
-// Batched FP64 symmetric eigensolver for sector matrices of up to 512 rows:
+// Batched FP64 symmetric eigensolver for sector matrices of up to 1024 rows:
 // Householder tridiagonalisation, bisection for every eigenvalue, inverse
 // iteration for the leading eigenvectors, back-transformation.
 //
@@ -14,7 +14,9 @@
 //     the tiles on and below the diagonal and written to both triangles, so
 //     A stays exactly symmetric), and within the panel each column and each
 //     matrix-vector product is corrected for the pending ones. Reflector j
-//     is kept in row j of A (right of the diagonal).
+//     is kept in row j of A (right of the diagonal). Sectors of at least
+//     768 rows are shared by up to 8 workgroups of one cooperative launch
+//     (a grid barrier per column).
 //  2. tri_bisect: every eigenvalue of T by bisection on Sturm counts, one
 //     thread each (all of them enter the discarded weights).
 //  3. tri_invit: the leading kq = min(n, Dcut) eigenvectors of T, one thread
@@ -27,10 +29,15 @@
 // matrix on the diagonal of A for the selection; stages 3-4
 // (launch_tri_vectors) can then be limited to the side the selection chose.
 #include <float.h>
+#include <stdlib.h>
 
 #include <algorithm>
 
+#include <hip/hip_cooperative_groups.h>
+
 #include "internal.h"
+
+namespace cg = cooperative_groups;
 
 namespace gxy {
 
@@ -82,215 +89,302 @@ __device__ __forceinline__ void mv_partial(const double *A22, int np, int m, int
 // consecutive columns are applied to the trailing matrix together.
 constexpr int kNb = 16;
 
-__global__ __launch_bounds__(kRedThreads) void tri_reduce_kernel(
-    int nmat, int nsec, const int32_t *sec_n, const int32_t *npad, const int64_t *off,
-    double *A, double *work, double *panel) {
+// Sharing pays only for the largest sectors: every column costs a grid
+// barrier, and the shared matrices' workgroups hold their compute units while
+// they wait. Measured on one matrix: 1024 rows 2.5x faster shared, 540 rows
+// no faster alone and slower beside concurrent GEMMs.
+constexpr int kMultiMinRows = 768;
+
+// Workgroups that share one matrix in the multi-workgroup reduction: about
+// 96 rows of A22 each, at most 8, and few enough that their private panels
+// (2 kNb n values each) fit in the matrix's npad^2 scratch slot.
+__host__ __device__ inline int tri_groups(int n) {
+  const int np = (n + 31) / 32 * 32;
+  int g = (n + 95) / 96;
+  if (g > 8) g = 8;
+  if (g > np / 32) g = np / 32;
+  return g < 1 ? 1 : g;
+}
+
+// The reduction of one matrix, by G workgroups (MULTI) or one. With MULTI the
+// grid is launched cooperatively: the G workgroups of a matrix each form
+// the column, its reflector and w-vector redundantly (identical values from
+// identical inputs, in a private copy of the panel), split the rows of the
+// matrix-vector product between them, and add their partial sums after a
+// grid barrier, from a buffer that alternates between columns; the trailing
+// update's tiles are split between them too, followed by a second barrier.
+// Every workgroup runs the same number of barriers (ncols columns).
+template <bool MULTI>
+__device__ void tri_reduce_body(int nmat, int nsec, const int32_t *sec_n, const int32_t *npad,
+                                const int64_t *off, double *A, double *work, double *panel,
+                                double *xch, int ncols, bool grouped) {
   __shared__ double v[kTriMaxN];
   __shared__ double w[kTriMaxN];
   __shared__ double red[kRedWaves];
   __shared__ double q1[kNb], q2[kNb], vj_s[kNb], wj_s[kNb];
   __shared__ double red_w[kRedWaves / 2][kTriMaxN];
   __shared__ double s_tau, s_scal;
-  const int mi = blockIdx.x;
-  if (mi >= nmat) return;
-  const int n = sec_n[mi % nsec];
+  int mi = blockIdx.x, g = 0, G = 1;
+  if (MULTI) {
+    int b = blockIdx.x;
+    for (mi = 0; mi < nmat; ++mi) {
+      G = tri_groups(sec_n[mi % nsec]);
+      if (b < G) break;
+      b -= G;
+    }
+    g = b;
+  }
+  if (!MULTI && mi >= nmat) return;
+  // (with MULTI the grid holds exactly the sum of G over the matrices; a
+  // surplus workgroup would only take part in the barriers)
+  const bool idle = mi >= nmat;
+  if (idle) mi = nmat - 1;
+  const int n = idle ? 0 : sec_n[mi % nsec];
   const int np = npad[mi];
+  if (!MULTI) ncols = n - 2;
   double *Am = A + off[mi];
   double *d = work + off[mi], *e = d + np, *tau = e + np;
   // pending reflectors V[s][row] and w-vectors W[s][row] of the current
   // panel, stored by column so that threads over rows read them coalesced
-  double *Vg = panel + off[mi], *Wg = Vg + (int64_t)n * kNb;
+  double *Vg = panel + off[mi] + (int64_t)g * 2 * kNb * n, *Wg = Vg + (int64_t)n * kNb;
+  double *xm = xch + off[mi];   // [2][G][n] partial sums of A22 v
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int j0 = 0; j0 < n - 2; j0 += kNb) {
-    const int jend = min(j0 + kNb, n - 2);
-    for (int j = j0; j < jend; ++j) {
+  const bool lead = (g == 0);
+  for (int j0 = 0; j0 < ncols; j0 += kNb) {
+    const int jend = min(j0 + kNb, n - 2);   // <= j0: this matrix is done
+    const int jlast = min(j0 + kNb, ncols);
+    for (int j = j0; j < jlast; ++j) {
+      const bool act = j < n - 2;   // uniform over the workgroup
       const int t = j - j0;
       const int m = n - j - 1;
-      if (tid < t) {
-        vj_s[tid] = Vg[(int64_t)tid * n + j];
-        wj_s[tid] = Wg[(int64_t)tid * n + j];
-      }
-      __syncthreads();
-      // column j of the partly reduced matrix: A minus the pending
-      // V W^T + W V^T of this panel (row j of A by symmetry)
-      double part = 0.0;
-      for (int i = tid; i < m; i += kRedThreads) {
-        const int64_t r = j + 1 + i;
-        double x = Am[(int64_t)j * np + r];
-        for (int s2 = 0; s2 < t; ++s2)
-          x -= Vg[(int64_t)s2 * n + r] * wj_s[s2] + Wg[(int64_t)s2 * n + r] * vj_s[s2];
-        v[i] = x;
-        if (i > 0) part += x * x;
-      }
-      const double sigma = block_sum(part, red);
-      if (tid == 0) {
-        double dj = Am[(int64_t)j * np + j];
-        for (int s2 = 0; s2 < t; ++s2) dj -= 2.0 * vj_s[s2] * wj_s[s2];
-        d[j] = dj;
-        const double alpha = v[0];
-        if (sigma == 0.0) {
-          s_tau = 0.0;
-          s_scal = 0.0;
-          e[j] = alpha;
-        } else {
-          const double beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
-          s_tau = (beta - alpha) / beta;
-          s_scal = 1.0 / (alpha - beta);
-          e[j] = beta;
+      double tj = 0.0;
+      if (act) {
+        if (tid < t) {
+          vj_s[tid] = Vg[(int64_t)tid * n + j];
+          wj_s[tid] = Wg[(int64_t)tid * n + j];
         }
-        tau[j] = s_tau;
+        __syncthreads();
+        // column j of the partly reduced matrix: A minus the pending
+        // V W^T + W V^T of this panel (row j of A by symmetry)
+        double part = 0.0;
+        for (int i = tid; i < m; i += kRedThreads) {
+          const int64_t r = j + 1 + i;
+          double x = Am[(int64_t)j * np + r];
+          for (int s2 = 0; s2 < t; ++s2)
+            x -= Vg[(int64_t)s2 * n + r] * wj_s[s2] + Wg[(int64_t)s2 * n + r] * vj_s[s2];
+          v[i] = x;
+          if (i > 0) part += x * x;
+        }
+        const double sigma = block_sum(part, red);
+        if (tid == 0) {
+          double dj = Am[(int64_t)j * np + j];
+          for (int s2 = 0; s2 < t; ++s2) dj -= 2.0 * vj_s[s2] * wj_s[s2];
+          const double alpha = v[0];
+          double ej;
+          if (sigma == 0.0) {
+            s_tau = 0.0;
+            s_scal = 0.0;
+            ej = alpha;
+          } else {
+            const double beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
+            s_tau = (beta - alpha) / beta;
+            s_scal = 1.0 / (alpha - beta);
+            ej = beta;
+          }
+          if (lead) {
+            d[j] = dj;
+            e[j] = ej;
+            tau[j] = s_tau;
+          }
+        }
+        __syncthreads();
+        tj = s_tau;
       }
-      __syncthreads();
-      const double tj = s_tau;
       double *vcol = Vg + (int64_t)t * n, *wcol = Wg + (int64_t)t * n;
-      if (tj == 0.0) {   // uniform: no reflection; its panel column is zero
+      const bool refl = act && tj != 0.0;   // uniform over the matrix's workgroups
+      if (act && !refl) {   // no reflection: its panel column is zero
         for (int i = tid; i < m; i += kRedThreads) {
           vcol[j + 1 + i] = 0.0;
           wcol[j + 1 + i] = 0.0;
         }
+      }
+      if (refl) {
+        const double sc = s_scal;
+        for (int i = tid; i < m; i += kRedThreads) {
+          const double vi = (i == 0) ? 1.0 : v[i] * sc;
+          v[i] = vi;
+          // reflector, for the back-transformation, into row j of A (with
+          // MULTI only after the barrier below: the other workgroups of the
+          // matrix read row j to form the column)
+          if (!MULTI) Am[(int64_t)j * np + j + 1 + i] = vi;
+          vcol[j + 1 + i] = vi;
+        }
         __syncthreads();
-        continue;
-      }
-      const double sc = s_scal;
-      for (int i = tid; i < m; i += kRedThreads) {
-        const double vi = (i == 0) ? 1.0 : v[i] * sc;
-        v[i] = vi;
-        Am[(int64_t)j * np + j + 1 + i] = vi;   // reflector, for the back-transformation
-        vcol[j + 1 + i] = vi;
-      }
-      __syncthreads();
-      // q1 = W^T v, q2 = V^T v over the earlier panel columns
-      if (wave < t) {
-        const double *vs = Vg + (int64_t)wave * n + j + 1, *ws = Wg + (int64_t)wave * n + j + 1;
-        double a1 = 0.0, a2 = 0.0;
-        for (int i = lane; i < m; i += 64) {
-          a1 += ws[i] * v[i];
-          a2 += vs[i] * v[i];
+        // q1 = W^T v, q2 = V^T v over the earlier panel columns
+        if (wave < t) {
+          const double *vs = Vg + (int64_t)wave * n + j + 1, *ws = Wg + (int64_t)wave * n + j + 1;
+          double a1 = 0.0, a2 = 0.0;
+          for (int i = lane; i < m; i += 64) {
+            a1 += ws[i] * v[i];
+            a2 += vs[i] * v[i];
+          }
+          a1 = wave_sum(a1);
+          a2 = wave_sum(a2);
+          if (lane == 0) {
+            q1[wave] = a1;
+            q2[wave] = a2;
+          }
         }
-        a1 = wave_sum(a1);
-        a2 = wave_sum(a2);
-        if (lane == 0) {
-          q1[wave] = a1;
-          q2[wave] = a2;
-        }
-      }
-      // A22 v, using the symmetry of A22: sum over k of v[k] times row k, so
-      // that lanes run along rows (coalesced) with no cross-lane sums. Each
-      // wave takes a range of k; the partial sums of the 16 waves are added
-      // in a fixed order through LDS.
-      double acc[kMvCols];
-      {
+        // A22 v, using the symmetry of A22: sum over k of v[k] times row k,
+        // so that lanes run along rows (coalesced) with no cross-lane sums.
+        // The k range is split into G x 16 parts (G = tri_groups(n) in a
+        // launch whose largest sector has at least kMultiMinRows rows, else
+        // 1): group h's 16
+        // parts (one per wave) are added in a fixed order through LDS, then
+        // the group sums in order of h. With MULTI group h is workgroup h of
+        // the matrix; one workgroup alone runs the groups one after another
+        // (grouped; else it takes one group), so both give the same bits.
+        const int Gl = MULTI ? 1 : (grouped ? tri_groups(n) : 1);
+        const int Gt = MULTI ? G : Gl;
         const double *A22 = Am + (int64_t)(j + 1) * np + (j + 1);
-        const int k_lo = (wave * m) / kRedWaves, k_hi = ((wave + 1) * m) / kRedWaves;
-        switch ((m + 63) >> 6) {
+        for (int hh = 0; hh < Gl; ++hh) {
+          const int h = MULTI ? g : hh;
+          double acc[kMvCols];
+          const int part_id = h * kRedWaves + wave, nparts = Gt * kRedWaves;
+          const int k_lo = (int)(((int64_t)part_id * m) / nparts);
+          const int k_hi = (int)(((int64_t)(part_id + 1) * m) / nparts);
+          switch ((m + 63) >> 6) {
 #define GXY_MV(Q) \
   case Q: mv_partial<Q>(A22, np, m, k_lo, k_hi, v, lane, acc); break;
-          GXY_MV(1) GXY_MV(2) GXY_MV(3) GXY_MV(4) GXY_MV(5) GXY_MV(6) GXY_MV(7) GXY_MV(8)
-          GXY_MV(9) GXY_MV(10) GXY_MV(11) GXY_MV(12) GXY_MV(13) GXY_MV(14) GXY_MV(15)
-          GXY_MV(16)
+            GXY_MV(1) GXY_MV(2) GXY_MV(3) GXY_MV(4) GXY_MV(5) GXY_MV(6) GXY_MV(7) GXY_MV(8)
+            GXY_MV(9) GXY_MV(10) GXY_MV(11) GXY_MV(12) GXY_MV(13) GXY_MV(14) GXY_MV(15)
+            GXY_MV(16)
 #undef GXY_MV
-          default: break;
-        }
-        if (wave >= kRedWaves / 2) {
+            default: break;
+          }
+          if (wave >= kRedWaves / 2) {
 #pragma unroll
-          for (int q = 0; q < kMvCols; ++q) {
-            const int i = lane + 64 * q;
-            if (64 * q < m && i < m) red_w[wave - kRedWaves / 2][i] = acc[q];
+            for (int q = 0; q < kMvCols; ++q) {
+              const int i = lane + 64 * q;
+              if (64 * q < m && i < m) red_w[wave - kRedWaves / 2][i] = acc[q];
+            }
+          }
+          __syncthreads();
+          if (wave < kRedWaves / 2) {
+#pragma unroll
+            for (int q = 0; q < kMvCols; ++q) {
+              const int i = lane + 64 * q;
+              if (64 * q < m && i < m) red_w[wave][i] = acc[q] + red_w[wave][i];
+            }
+          }
+          __syncthreads();
+          double *xo = xm + ((int64_t)(j & 1) * G + g) * n;
+          for (int i = tid; i < m; i += kRedThreads) {
+            double x = 0.0;
+#pragma unroll
+            for (int h8 = 0; h8 < kRedWaves / 2; ++h8) x += red_w[h8][i];
+            if (MULTI)
+              xo[i] = x;
+            else
+              w[i] = (hh == 0 ? 0.0 : w[i]) + x;
+          }
+          __syncthreads();
+        }
+      }
+      if (MULTI) cg::this_grid().sync();
+      if (refl) {
+        if (MULTI) {
+          const double *xi = xm + (int64_t)(j & 1) * G * n;
+          for (int i = tid; i < m; i += kRedThreads) {
+            double x = 0.0;
+            for (int h = 0; h < G; ++h) x += xi[(int64_t)h * n + i];
+            w[i] = x;
+            if (lead) Am[(int64_t)j * np + j + 1 + i] = v[i];
           }
         }
         __syncthreads();
-        if (wave < kRedWaves / 2) {
-#pragma unroll
-          for (int q = 0; q < kMvCols; ++q) {
-            const int i = lane + 64 * q;
-            if (64 * q < m && i < m) red_w[wave][i] = acc[q] + red_w[wave][i];
-          }
-        }
-        __syncthreads();
+        // p = tau (A22 v - V q1 - W q2)
+        double pvp = 0.0;
         for (int i = tid; i < m; i += kRedThreads) {
-          double x = 0.0;
-#pragma unroll
-          for (int h = 0; h < kRedWaves / 2; ++h) x += red_w[h][i];
-          w[i] = x;
+          const int64_t r = j + 1 + i;
+          double a = w[i];
+          for (int s2 = 0; s2 < t; ++s2)
+            a -= Vg[(int64_t)s2 * n + r] * q1[s2] + Wg[(int64_t)s2 * n + r] * q2[s2];
+          a *= tj;
+          w[i] = a;
+          pvp += a * v[i];
         }
+        const double K = -0.5 * tj * block_sum(pvp, red);
+        for (int i = tid; i < m; i += kRedThreads) wcol[j + 1 + i] = w[i] + K * v[i];
       }
-      __syncthreads();
-      // p = tau (A22 v - V q1 - W q2)
-      double pvp = 0.0;
-      for (int i = tid; i < m; i += kRedThreads) {
-        const int64_t r = j + 1 + i;
-        double acc = w[i];
-        for (int s2 = 0; s2 < t; ++s2)
-          acc -= Vg[(int64_t)s2 * n + r] * q1[s2] + Wg[(int64_t)s2 * n + r] * q2[s2];
-        acc *= tj;
-        w[i] = acc;
-        pvp += acc * v[i];
-      }
-      const double K = -0.5 * tj * block_sum(pvp, red);
-      for (int i = tid; i < m; i += kRedThreads) wcol[j + 1 + i] = w[i] + K * v[i];
       __syncthreads();
     }
     // trailing matrix (rows and columns >= jend) -= U = V W^T + W V^T, as a
     // K = 32 product on the matrix cores: U[r][c] = sum_k L[r][k] R[c][k]
     // with L[r] = (V[.][r], W[.][r]) and R[c] = (W[.][c], V[.][c]) (zero past
-    // the panel width). Each wave takes 32 x 32 tiles on or below the
-    // diagonal and writes every new value to (r, c) and (c, r), so A stays
-    // exactly symmetric.
-    const int tp = jend - j0;
-    const int mt = n - jend;
-    const int nt = (mt + 31) / 32;
-    const int ntiles = nt * (nt + 1) / 2;
-    const int li = lane & 15, lk = lane >> 4;
-    for (int tix = wave; tix < ntiles; tix += kRedWaves) {
-      int I = (int)((sqrt(8.0 * tix + 1.0) - 1.0) * 0.5);
-      while (I * (I + 1) / 2 > tix) --I;
-      while ((I + 1) * (I + 2) / 2 <= tix) ++I;
-      const int J = tix - I * (I + 1) / 2;
-      const int r0 = jend + 32 * I, c0 = jend + 32 * J;
-      double4_t acc[2][2];
+    // the panel width). The waves of the matrix's workgroups take 32 x 32
+    // tiles on or below the diagonal and write every new value to (r, c)
+    // and (c, r), so A stays exactly symmetric.
+    if (jend > j0) {
+      const int tp = jend - j0;
+      const int mt = n - jend;
+      const int nt = (mt + 31) / 32;
+      const int ntiles = nt * (nt + 1) / 2;
+      const int li = lane & 15, lk = lane >> 4;
+      for (int tix = g * kRedWaves + wave; tix < ntiles; tix += G * kRedWaves) {
+        int I = (int)((sqrt(8.0 * tix + 1.0) - 1.0) * 0.5);
+        while (I * (I + 1) / 2 > tix) --I;
+        while ((I + 1) * (I + 2) / 2 <= tix) ++I;
+        const int J = tix - I * (I + 1) / 2;
+        const int r0 = jend + 32 * I, c0 = jend + 32 * J;
+        double4_t acc[2][2];
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = double4_t{0.0, 0.0, 0.0, 0.0};
+          for (int b = 0; b < 2; ++b) acc[a][b] = double4_t{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int kk = 0; kk < 32; kk += 4) {
-        const int k = kk + lk;
-        const int s2 = k & 15;
-        const double *Lp = (k < 16 ? Vg : Wg) + (int64_t)s2 * n;
-        const double *Rp = (k < 16 ? Wg : Vg) + (int64_t)s2 * n;
-        // (columns s2 >= tp of the panel hold stale values: read, then zero)
-        double fa[2], fb[2];
+        for (int kk = 0; kk < 32; kk += 4) {
+          const int k = kk + lk;
+          const int s2 = k & 15;
+          const double *Lp = (k < 16 ? Vg : Wg) + (int64_t)s2 * n;
+          const double *Rp = (k < 16 ? Wg : Vg) + (int64_t)s2 * n;
+          // (columns s2 >= tp of the panel hold stale values: read, then zero)
+          double fa[2], fb[2];
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          const int r = r0 + 16 * a + li, c = c0 + 16 * a + li;
-          const double x = Lp[min(r, n - 1)], y = Rp[min(c, n - 1)];
-          fa[a] = (s2 < tp && r < n) ? x : 0.0;
-          fb[a] = (s2 < tp && c < n) ? y : 0.0;
+          for (int a = 0; a < 2; ++a) {
+            const int r = r0 + 16 * a + li, c = c0 + 16 * a + li;
+            const double x = Lp[min(r, n - 1)], y = Rp[min(c, n - 1)];
+            fa[a] = (s2 < tp && r < n) ? x : 0.0;
+            fb[a] = (s2 < tp && c < n) ? y : 0.0;
+          }
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+              acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0, 0);
         }
+        // accumulator register q of lane l: row l/16 + 4q, column l%16
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
           for (int b = 0; b < 2; ++b)
-            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0, 0);
-      }
-      // accumulator register q of lane l: row l/16 + 4q, column l%16
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int r = r0 + 16 * a + lk + 4 * q, c = c0 + 16 * b + li;
-            if (r < n && c < n && (I != J || r >= c)) {
-              const double nv = Am[(int64_t)r * np + c] - acc[a][b][q];
-              Am[(int64_t)r * np + c] = nv;
-              if (r != c) Am[(int64_t)c * np + r] = nv;
+            for (int q = 0; q < 4; ++q) {
+              const int r = r0 + 16 * a + lk + 4 * q, c = c0 + 16 * b + li;
+              if (r < n && c < n && (I != J || r >= c)) {
+                const double nv = Am[(int64_t)r * np + c] - acc[a][b][q];
+                Am[(int64_t)r * np + c] = nv;
+                if (r != c) Am[(int64_t)c * np + r] = nv;
+              }
             }
-          }
+      }
     }
-    __syncthreads();
+    if (MULTI)
+      cg::this_grid().sync();
+    else
+      __syncthreads();
   }
-  if (tid == 0) {
+  if (!idle && tid == 0 && lead) {
     if (n >= 2) {
       d[n - 2] = Am[(int64_t)(n - 2) * np + (n - 2)];
       e[n - 2] = Am[(int64_t)(n - 2) * np + (n - 1)];
@@ -300,6 +394,18 @@ __global__ __launch_bounds__(kRedThreads) void tri_reduce_kernel(
     e[n - 1] = 0.0;
     tau[n - 1] = 0.0;
   }
+}
+
+__global__ __launch_bounds__(kRedThreads) void tri_reduce_kernel(
+    int nmat, int nsec, const int32_t *sec_n, const int32_t *npad, const int64_t *off,
+    double *A, double *work, double *panel, int grouped) {
+  tri_reduce_body<false>(nmat, nsec, sec_n, npad, off, A, work, panel, nullptr, 0, grouped != 0);
+}
+
+__global__ __launch_bounds__(kRedThreads) void tri_reduce_multi_kernel(
+    int nmat, int nsec, const int32_t *sec_n, const int32_t *npad, const int64_t *off,
+    double *A, double *work, double *panel, double *xch, int ncols) {
+  tri_reduce_body<true>(nmat, nsec, sec_n, npad, off, A, work, panel, xch, ncols, true);
 }
 
 // Eigenvalues of T by bisection on Sturm counts, one thread per eigenvalue
@@ -596,12 +702,45 @@ __global__ __launch_bounds__(kBackThreads) void tri_back_kernel(
 
 }  // namespace
 
-void launch_tri_values(int nmat, int nsec, const int32_t *d_sec_n, const int32_t *d_npad,
-                       const int64_t *d_off, double *A, double *Y, double *work, hipStream_t s) {
-  // Y serves as the panel scratch of the reduction (2 n kNb <= npad^2)
-  hipLaunchKernelGGL(tri_reduce_kernel, dim3(nmat), dim3(kRedThreads), 0, s, nmat, nsec,
-                     d_sec_n, d_npad, d_off, A, work, Y);
-  GXY_CHECK_LAUNCH();
+void launch_tri_values(int nmat, int nsec, const int *h_sec_n, const int32_t *d_sec_n,
+                       const int32_t *d_npad, const int64_t *d_off, double *A, double *Y,
+                       double *X, double *work, bool allow_multi, hipStream_t s) {
+  // Y serves as the panel scratch of the reduction (G private panels of
+  // 2 n kNb values per matrix <= npad^2), X as the exchange of partial
+  // matrix-vector products (2 G n <= npad^2)
+  int blocks = 0, ncols = 0;
+  for (int k = 0; k < nmat; ++k) {
+    const int n = h_sec_n[k % nsec];
+    blocks += tri_groups(n);
+    ncols = std::max(ncols, n - 2);
+  }
+  // co-resident workgroups of the multi-workgroup kernel (per process, one
+  // device type; 0 without cooperative launch)
+  static const int co_resident = []() {
+    int dev = 0, per_cu = 0, cus = 0, coop = 0;
+    GXY_HIP(hipGetDevice(&dev));
+    GXY_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+    GXY_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    GXY_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void *>(tri_reduce_multi_kernel), kRedThreads, 0));
+    return coop ? per_cu * cus : 0;
+  }();
+  const char *env = getenv("GXY_TRI_MULTI");
+  // (a launch whose largest sector qualifies groups the sums the shared way
+  // even on one workgroup per matrix, so the bits do not depend on whether
+  // the cooperative launch was possible)
+  const bool grouped = ncols + 2 >= kMultiMinRows;
+  const bool multi = allow_multi && !(env && env[0] == '0') && grouped && blocks > nmat &&
+                     blocks <= co_resident;
+  if (multi) {
+    void *args[] = {&nmat, &nsec, &d_sec_n, &d_npad, &d_off, &A, &work, &Y, &X, &ncols};
+    GXY_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(tri_reduce_multi_kernel),
+                                       dim3(blocks), dim3(kRedThreads), args, 0, s));
+  } else {
+    hipLaunchKernelGGL(tri_reduce_kernel, dim3(nmat), dim3(kRedThreads), 0, s, nmat, nsec,
+                       d_sec_n, d_npad, d_off, A, work, Y, grouped ? 1 : 0);
+    GXY_CHECK_LAUNCH();
+  }
   hipLaunchKernelGGL(tri_bisect_kernel, dim3(kTriMaxN / kBisThreads, nmat), dim3(kBisThreads),
                      0, s, nmat, nsec, d_sec_n, d_npad, d_off, work);
   GXY_CHECK_LAUNCH();

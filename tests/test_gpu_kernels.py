@@ -243,6 +243,22 @@ def test_tridiagonal_leading_vectors_of_large_sectors(ctx, n, kmax):
     assert not np.any(V[:, kmax:])
 
 
+@pytest.mark.parametrize("n", [800, 1024])
+def test_tridiagonal_shared_reduction_same_bits(ctx, n, monkeypatch):
+    """Sectors of at least 768 rows are reduced by several workgroups of one
+    cooperative launch (grid barrier per column); the matrix-vector sums are
+    grouped the same way as when one workgroup runs the groups in turn, so
+    both give the same eigenvalues and vectors bit for bit."""
+    rng = np.random.default_rng(n + 1)
+    X = rng.standard_normal((n, n + 7))
+    A = X @ X.T
+    w1, V1 = ctx.test_eigh(A, 2, kmax=64)
+    monkeypatch.setenv("GXY_TRI_MULTI", "0")
+    w0, V0 = ctx.test_eigh(A, 2, kmax=64)
+    assert np.array_equal(w0, w1)
+    assert np.array_equal(V0, V1)
+
+
 def test_tridiagonal_eigenvalues_sorted_decreasing(ctx):
     rng = np.random.default_rng(3)
     X = rng.standard_normal((90, 95))
