@@ -197,7 +197,8 @@ void launch_eig_scaled_copy(int64_t n, double a, const double *x, double *y, hip
 // Y and X (shaped like A) are scratch; h_sec_n holds the nsec sector sizes
 // on the host. With allow_multi the reduction shares each large matrix
 // between several workgroups of one cooperative launch when the device can
-// hold the whole grid at once (GXY_TRI_MULTI=0 keeps one workgroup per
+// hold the whole grid at once (GXY_TRI_MULTI_MIN: smallest shared sector,
+// rows) (GXY_TRI_MULTI=0 keeps one workgroup per
 // matrix); callers that may run two such launches at once (batch workers)
 // pass false, since two half-placed cooperative grids would wait on each
 // other. launch_tri_vectors: the

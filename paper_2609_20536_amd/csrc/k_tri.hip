@@ -15,8 +15,8 @@
 //     A stays exactly symmetric), and within the panel each column and each
 //     matrix-vector product is corrected for the pending ones. Reflector j
 //     is kept in row j of A (right of the diagonal). Sectors of at least
-//     768 rows are shared by up to 8 workgroups of one cooperative launch
-//     (a grid barrier per column).
+//     384 rows are shared by up to 8 workgroups of one cooperative launch
+//     (a barrier of the matrix's workgroups per column).
 //  2. tri_bisect: every eigenvalue of T by bisection on Sturm counts, one
 //     thread each (all of them enter the discarded weights).
 //  3. tri_invit: the leading kq = min(n, Dcut) eigenvectors of T, one thread
@@ -33,11 +33,7 @@
 
 #include <algorithm>
 
-#include <hip/hip_cooperative_groups.h>
-
 #include "internal.h"
-
-namespace cg = cooperative_groups;
 
 namespace gxy {
 
@@ -89,11 +85,11 @@ __device__ __forceinline__ void mv_partial(const double *A22, int np, int m, int
 // consecutive columns are applied to the trailing matrix together.
 constexpr int kNb = 16;
 
-// Sharing pays only for the largest sectors: every column costs a grid
-// barrier, and the shared matrices' workgroups hold their compute units while
-// they wait. Measured on one matrix: 1024 rows 2.5x faster shared, 540 rows
-// no faster alone and slower beside concurrent GEMMs.
-constexpr int kMultiMinRows = 768;
+// Sharing pays only for large sectors: every column costs a barrier of the
+// matrix's workgroups, and they hold their compute units while they wait.
+// Bench workload (largest sectors near 540 rows): 29.0 steps/s with the
+// threshold at 512 rows, 29.9 at 384, 29.8 at 256, 28.9 at 768.
+constexpr int kMultiMinRows = 384;
 
 // Workgroups that share one matrix in the multi-workgroup reduction: about
 // 96 rows of A22 each, at most 8, and few enough that their private panels
@@ -106,18 +102,45 @@ __host__ __device__ inline int tri_groups(int n) {
   return g < 1 ? 1 : g;
 }
 
+// Barrier of the G workgroups sharing one matrix: a counter per matrix
+// (zeroed before the launch) that every workgroup raises once per barrier;
+// number b waits until it reads G (b + 1). Release on the increment and
+// acquire on the polling load, at device scope, carry the workgroups' global
+// writes across. The wait is bounded (about a second): should a workgroup
+// of the matrix never arrive, the others mark the matrix's diagonal NaN and
+// go on, so the kernel always ends.
+constexpr int64_t kBarrierSpins = (int64_t)1 << 24;
+
+__device__ void matrix_barrier(int32_t *cnt, int G, int b, double *fail_mark) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const int target = G * (b + 1);
+    int64_t spins = 0;
+    while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(2);
+      if (++spins > kBarrierSpins) {
+        *fail_mark = __builtin_nan("");
+        break;
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // The reduction of one matrix, by G workgroups (MULTI) or one. With MULTI the
-// grid is launched cooperatively: the G workgroups of a matrix each form
-// the column, its reflector and w-vector redundantly (identical values from
-// identical inputs, in a private copy of the panel), split the rows of the
+// grid is launched cooperatively (so all its workgroups are resident
+// together): the G workgroups of a matrix each form the column, its
+// reflector and w-vector redundantly (identical values from identical
+// inputs, in a private copy of the panel), split the rows of the
 // matrix-vector product between them, and add their partial sums after a
-// grid barrier, from a buffer that alternates between columns; the trailing
-// update's tiles are split between them too, followed by a second barrier.
-// Every workgroup runs the same number of barriers (ncols columns).
+// barrier of the matrix's workgroups, from a buffer that alternates between
+// columns; the trailing update's tiles are split between them too, followed
+// by a second barrier.
 template <bool MULTI>
 __device__ void tri_reduce_body(int nmat, int nsec, const int32_t *sec_n, const int32_t *npad,
                                 const int64_t *off, double *A, double *work, double *panel,
-                                double *xch, int ncols, bool grouped) {
+                                double *xch, bool grouped) {
   __shared__ double v[kTriMaxN];
   __shared__ double w[kTriMaxN];
   __shared__ double red[kRedWaves];
@@ -141,13 +164,16 @@ __device__ void tri_reduce_body(int nmat, int nsec, const int32_t *sec_n, const 
   if (idle) mi = nmat - 1;
   const int n = idle ? 0 : sec_n[mi % nsec];
   const int np = npad[mi];
-  if (!MULTI) ncols = n - 2;
+  const int ncols = n - 2;
   double *Am = A + off[mi];
   double *d = work + off[mi], *e = d + np, *tau = e + np;
   // pending reflectors V[s][row] and w-vectors W[s][row] of the current
   // panel, stored by column so that threads over rows read them coalesced
   double *Vg = panel + off[mi] + (int64_t)g * 2 * kNb * n, *Wg = Vg + (int64_t)n * kNb;
   double *xm = xch + off[mi];   // [2][G][n] partial sums of A22 v
+  // barrier counter of the matrix, after d, e, tau and the eigenvalues
+  int32_t *cnt = reinterpret_cast<int32_t *>(work + off[mi] + 4 * (int64_t)np);
+  int nbar = 0;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool lead = (g == 0);
   for (int j0 = 0; j0 < ncols; j0 += kNb) {
@@ -291,7 +317,7 @@ __device__ void tri_reduce_body(int nmat, int nsec, const int32_t *sec_n, const 
           __syncthreads();
         }
       }
-      if (MULTI) cg::this_grid().sync();
+      if (MULTI) matrix_barrier(cnt, G, nbar++, d);
       if (refl) {
         if (MULTI) {
           const double *xi = xm + (int64_t)(j & 1) * G * n;
@@ -380,7 +406,7 @@ __device__ void tri_reduce_body(int nmat, int nsec, const int32_t *sec_n, const 
       }
     }
     if (MULTI)
-      cg::this_grid().sync();
+      matrix_barrier(cnt, G, nbar++, d);
     else
       __syncthreads();
   }
@@ -399,13 +425,21 @@ __device__ void tri_reduce_body(int nmat, int nsec, const int32_t *sec_n, const 
 __global__ __launch_bounds__(kRedThreads) void tri_reduce_kernel(
     int nmat, int nsec, const int32_t *sec_n, const int32_t *npad, const int64_t *off,
     double *A, double *work, double *panel, int grouped) {
-  tri_reduce_body<false>(nmat, nsec, sec_n, npad, off, A, work, panel, nullptr, 0, grouped != 0);
+  tri_reduce_body<false>(nmat, nsec, sec_n, npad, off, A, work, panel, nullptr, grouped != 0);
 }
 
 __global__ __launch_bounds__(kRedThreads) void tri_reduce_multi_kernel(
     int nmat, int nsec, const int32_t *sec_n, const int32_t *npad, const int64_t *off,
-    double *A, double *work, double *panel, double *xch, int ncols) {
-  tri_reduce_body<true>(nmat, nsec, sec_n, npad, off, A, work, panel, xch, ncols, true);
+    double *A, double *work, double *panel, double *xch) {
+  tri_reduce_body<true>(nmat, nsec, sec_n, npad, off, A, work, panel, xch, true);
+}
+
+// zero the barrier counter of every matrix
+__global__ void tri_counters_kernel(int nmat, const int32_t *npad, const int64_t *off,
+                                    double *work) {
+  const int mi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (mi < nmat)
+    *reinterpret_cast<int32_t *>(work + off[mi] + 4 * (int64_t)npad[mi]) = 0;
 }
 
 // Eigenvalues of T by bisection on Sturm counts, one thread per eigenvalue
@@ -729,11 +763,16 @@ void launch_tri_values(int nmat, int nsec, const int *h_sec_n, const int32_t *d_
   // (a launch whose largest sector qualifies groups the sums the shared way
   // even on one workgroup per matrix, so the bits do not depend on whether
   // the cooperative launch was possible)
-  const bool grouped = ncols + 2 >= kMultiMinRows;
+  const char *env_min = getenv("GXY_TRI_MULTI_MIN");   // rows; default kMultiMinRows
+  const int min_rows = env_min ? atoi(env_min) : kMultiMinRows;
+  const bool grouped = ncols + 2 >= min_rows;
   const bool multi = allow_multi && !(env && env[0] == '0') && grouped && blocks > nmat &&
                      blocks <= co_resident;
   if (multi) {
-    void *args[] = {&nmat, &nsec, &d_sec_n, &d_npad, &d_off, &A, &work, &Y, &X, &ncols};
+    hipLaunchKernelGGL(tri_counters_kernel, dim3((nmat + 255) / 256), dim3(256), 0, s, nmat,
+                       d_npad, d_off, work);
+    GXY_CHECK_LAUNCH();
+    void *args[] = {&nmat, &nsec, &d_sec_n, &d_npad, &d_off, &A, &work, &Y, &X};
     GXY_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(tri_reduce_multi_kernel),
                                        dim3(blocks), dim3(kRedThreads), args, 0, s));
   } else {

@@ -245,8 +245,9 @@ def test_tridiagonal_leading_vectors_of_large_sectors(ctx, n, kmax):
 
 @pytest.mark.parametrize("n", [800, 1024])
 def test_tridiagonal_shared_reduction_same_bits(ctx, n, monkeypatch):
-    """Sectors of at least 768 rows are reduced by several workgroups of one
-    cooperative launch (grid barrier per column); the matrix-vector sums are
+    """Sectors of at least 384 rows are reduced by several workgroups of one
+    cooperative launch (a barrier of the matrix's workgroups per column); the
+    matrix-vector sums are
     grouped the same way as when one workgroup runs the groups in turn, so
     both give the same eigenvalues and vectors bit for bit."""
     rng = np.random.default_rng(n + 1)
