@@ -536,6 +536,7 @@ __global__ void tri_values_kernel(int nmat, int nsec, const int32_t *sec_n,
 // Gram-Schmidt, twice, in decreasing eigenvalue order, and unit 2-norm.
 // Y[c * np + i]: vector c; U: factor scratch laid out [3][n][kq].
 constexpr int kInvThreads = 256;
+constexpr int kInvChunk = 8;   // rows per chunk of the factor / solve recurrences
 constexpr int kMaxKq = kTriMaxVecs;
 
 __device__ __forceinline__ double start_value(int i, int c) {
@@ -606,33 +607,55 @@ __global__ __launch_bounds__(kInvThreads) void tri_invit_kernel(int nmat, int ns
         for (int i = 0; i < n; ++i) x[i] = start_value(i, c);
         for (int it = 0; it < 3; ++it) {
           // factor T - m I with row interchanges while eliminating the
-          // right-hand side x; row i of U is (u0, u1, u2) at columns i..i+2
+          // right-hand side x; row i of U is (u0, u1, u2) at columns i..i+2.
+          // Rows go in chunks of kInvChunk: the chunk's loads are issued
+          // together, its stores after it, so the recurrence waits on
+          // memory once per chunk instead of once per row.
           double a = ds[0] - m, bsup = es[0], y = x[0];
-          for (int i = 0; i < n - 1; ++i) {
-            const double csub = es[i];            // T[i+1][i]
-            const double anext = ds[i + 1] - m;   // T[i+1][i+1]
-            const double bnext = i + 1 < n - 1 ? es[i + 1] : 0.0;
-            const double ynext = x[i + 1];
-            const int64_t at = (int64_t)i * kb + t;
-            if (fabs(a) >= fabs(csub)) {
-              const double piv = (a != 0.0) ? a : tiny;
-              const double l = csub / piv;
-              u0[at] = piv;
-              u1[at] = bsup;
-              u2[at] = 0.0;
-              x[i] = y;
-              a = anext - l * bsup;
-              bsup = bnext;
-              y = ynext - l * y;
-            } else {
-              const double l = a / csub;
-              u0[at] = csub;
-              u1[at] = anext;
-              u2[at] = bnext;
-              x[i] = ynext;
-              a = bsup - l * anext;
-              bsup = -l * bnext;
-              y = y - l * ynext;
+          for (int i0 = 0; i0 < n - 1; i0 += kInvChunk) {
+            const int cnt = min(kInvChunk, n - 1 - i0);
+            double xn[kInvChunk], o0[kInvChunk], o1[kInvChunk], o2[kInvChunk], ox[kInvChunk];
+#pragma unroll
+            for (int q = 0; q < kInvChunk; ++q) xn[q] = x[min(i0 + q + 1, n - 1)];
+#pragma unroll
+            for (int q = 0; q < kInvChunk; ++q) {
+              if (q < cnt) {
+                const int i = i0 + q;
+                const double csub = es[i];            // T[i+1][i]
+                const double anext = ds[i + 1] - m;   // T[i+1][i+1]
+                const double bnext = i + 1 < n - 1 ? es[i + 1] : 0.0;
+                const double ynext = xn[q];
+                if (fabs(a) >= fabs(csub)) {
+                  const double piv = (a != 0.0) ? a : tiny;
+                  const double l = csub / piv;
+                  o0[q] = piv;
+                  o1[q] = bsup;
+                  o2[q] = 0.0;
+                  ox[q] = y;
+                  a = anext - l * bsup;
+                  bsup = bnext;
+                  y = ynext - l * y;
+                } else {
+                  const double l = a / csub;
+                  o0[q] = csub;
+                  o1[q] = anext;
+                  o2[q] = bnext;
+                  ox[q] = ynext;
+                  a = bsup - l * anext;
+                  bsup = -l * bnext;
+                  y = y - l * ynext;
+                }
+              }
+            }
+#pragma unroll
+            for (int q = 0; q < kInvChunk; ++q) {
+              if (q < cnt) {
+                const int64_t at = (int64_t)(i0 + q) * kb + t;
+                u0[at] = o0[q];
+                u1[at] = o1[q];
+                u2[at] = o2[q];
+                x[i0 + q] = ox[q];
+              }
             }
           }
           {
@@ -640,15 +663,34 @@ __global__ __launch_bounds__(kInvThreads) void tri_invit_kernel(int nmat, int ns
             u0[at] = (a != 0.0) ? a : tiny;
             x[n - 1] = y;
           }
-          // back substitution, then scale by the largest entry
+          // back substitution (rows in chunks as above), then scale by the
+          // largest entry
           double xmax = 0.0, x1 = 0.0, x2 = 0.0;
-          for (int i = n - 1; i >= 0; --i) {
-            const int64_t at = (int64_t)i * kb + t;
-            const double v = (x[i] - u1[at] * x1 - u2[at] * x2) / u0[at];
-            x[i] = v;
-            x2 = x1;
-            x1 = v;
-            xmax = fmax(xmax, fabs(v));
+          for (int i1 = n - 1; i1 >= 0; i1 -= kInvChunk) {
+            const int cnt = min(kInvChunk, i1 + 1);
+            double b0[kInvChunk], b1[kInvChunk], b2[kInvChunk], bx[kInvChunk];
+#pragma unroll
+            for (int q = 0; q < kInvChunk; ++q) {
+              const int i = max(i1 - q, 0);
+              const int64_t at = (int64_t)i * kb + t;
+              b0[q] = u0[at];
+              b1[q] = u1[at];
+              b2[q] = u2[at];
+              bx[q] = x[i];
+            }
+#pragma unroll
+            for (int q = 0; q < kInvChunk; ++q) {
+              if (q < cnt) {
+                const double v = (bx[q] - b1[q] * x1 - b2[q] * x2) / b0[q];
+                bx[q] = v;
+                x2 = x1;
+                x1 = v;
+                xmax = fmax(xmax, fabs(v));
+              }
+            }
+#pragma unroll
+            for (int q = 0; q < kInvChunk; ++q)
+              if (q < cnt) x[i1 - q] = bx[q];
           }
           const double inv = xmax > 0.0 ? 1.0 / xmax : 1.0;
           for (int i = 0; i < n; ++i) x[i] *= inv;
