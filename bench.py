@@ -32,11 +32,12 @@ import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
-# hardware queues of this process (HIP reads it when it starts): the batched
-# leg runs BATCH_WORKERS streams, and streams beyond the queue count share
-# queues, which serialises their kernels
+# hardware queues of this process (HIP reads it when it starts; an inherited
+# smaller value is raised): the batched leg runs BATCH_WORKERS streams, and
+# streams beyond the queue count share queues, which serialises their kernels
 BATCH_WORKERS = 16
-os.environ.setdefault("GPU_MAX_HW_QUEUES", str(BATCH_WORKERS))
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < BATCH_WORKERS:
+    os.environ["GPU_MAX_HW_QUEUES"] = str(BATCH_WORKERS)
 sys.path.insert(0, ROOT)
 
 METRIC = "HOTRG steps/s & MFMA util at D=64; batched (β,Δ) points/s at |δf|≤1e-9"
