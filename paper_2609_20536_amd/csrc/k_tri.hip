@@ -536,6 +536,7 @@ __global__ void tri_values_kernel(int nmat, int nsec, const int32_t *sec_n,
 // Gram-Schmidt, twice, in decreasing eigenvalue order, and unit 2-norm.
 // Y[c * np + i]: vector c; U: factor scratch laid out [3][n][kq].
 constexpr int kInvThreads = 256;
+constexpr int kCgsThreads = 1024;
 constexpr int kInvChunk = 8;   // rows per chunk of the factor / solve recurrences
 constexpr int kMaxKq = kTriMaxVecs;
 
@@ -556,8 +557,6 @@ __global__ __launch_bounds__(kInvThreads) void tri_invit_kernel(int nmat, int ns
                                                                 const double *side) {
   __shared__ double ds[kTriMaxN], es[kTriMaxN];
   __shared__ double mu[kMaxKq];
-  __shared__ double dot[kMaxKq];
-  __shared__ double red[kInvThreads / 64];
   __shared__ double tnorm_s;
   const int mi = blockIdx.x;
   if (mi >= nmat) return;
@@ -568,7 +567,7 @@ __global__ __launch_bounds__(kInvThreads) void tri_invit_kernel(int nmat, int ns
   const double *dg = work + off[mi], *eg = dg + np, *lam = dg + 3 * np;
   double *Um = U + off[mi];
   double *Ym = Y + off[mi];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x;
   for (int i = tid; i < n; i += kInvThreads) {
     ds[i] = dg[i];
     es[i] = i < n - 1 ? eg[i] : 0.0;
@@ -699,34 +698,56 @@ __global__ __launch_bounds__(kInvThreads) void tri_invit_kernel(int nmat, int ns
     }
     __syncthreads();
   }
-  // classical Gram-Schmidt, twice, in order c = 0, 1, ...
+}
+
+// Classical Gram-Schmidt, twice, over the inverse-iteration vectors of a
+// matrix, in order c = 0, 1, ...; the vector being orthogonalised stays in
+// LDS over its two passes; 16 waves take the dot products.
+__global__ __launch_bounds__(kCgsThreads) void tri_cgs_kernel(int nmat, int nsec,
+                                                             const int32_t *sec_n,
+                                                             const int32_t *npad,
+                                                             const int64_t *off, double *Y,
+                                                             int kmax, const double *side) {
+  __shared__ double xs[kTriMaxN];
+  __shared__ double dot[kMaxKq];
+  __shared__ double red[kCgsThreads / 64];
+  const int mi = blockIdx.x;
+  if (mi >= nmat) return;
+  if (side && (int)*side != mi / nsec) return;
+  const int n = sec_n[mi % nsec];
+  const int np = npad[mi];
+  const int kq = min(min(n, kmax), kMaxKq);
+  double *Ym = Y + off[mi];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int c = 0; c < kq; ++c) {
     double *xc = Ym + (int64_t)c * np;
+    for (int i = tid; i < n; i += kCgsThreads) xs[i] = xc[i];
+    __syncthreads();
     for (int pass = 0; pass < 2; ++pass) {
-      for (int j = wave; j < c; j += kInvThreads / 64) {
+      for (int j = wave; j < c; j += kCgsThreads / 64) {
         const double *xj = Ym + (int64_t)j * np;
         double acc = 0.0;
-        for (int i = lane; i < n; i += 64) acc += xj[i] * xc[i];
+        for (int i = lane; i < n; i += 64) acc += xj[i] * xs[i];
         acc = wave_sum(acc);
         if (lane == 0) dot[j] = acc;
       }
       __syncthreads();
-      for (int i = tid; i < n; i += kInvThreads) {
-        double v = xc[i];
+      for (int i = tid; i < n; i += kCgsThreads) {
+        double v = xs[i];
         for (int j = 0; j < c; ++j) v -= dot[j] * Ym[(int64_t)j * np + i];
-        xc[i] = v;
+        xs[i] = v;
       }
       __syncthreads();
     }
     double part = 0.0;
-    for (int i = tid; i < n; i += kInvThreads) part += xc[i] * xc[i];
+    for (int i = tid; i < n; i += kCgsThreads) part += xs[i] * xs[i];
     part = wave_sum(part);
     if (lane == 0) red[wave] = part;
     __syncthreads();
     double nrm2 = 0.0;
-    for (int w = 0; w < kInvThreads / 64; ++w) nrm2 += red[w];
+    for (int w = 0; w < kCgsThreads / 64; ++w) nrm2 += red[w];
     const double inv = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
-    for (int i = tid; i < n; i += kInvThreads) xc[i] *= inv;
+    for (int i = tid; i < n; i += kCgsThreads) xc[i] = xs[i] * inv;
     __syncthreads();
   }
 }
@@ -837,6 +858,9 @@ void launch_tri_vectors(int nmat, int nsec, const int32_t *d_sec_n, const int32_
   // V serves as the factor scratch of the inverse iteration until tri_back
   hipLaunchKernelGGL(tri_invit_kernel, dim3(nmat), dim3(kInvThreads), 0, s, nmat, nsec,
                      d_sec_n, d_npad, d_off, work, V, Y, kmax, d_side);
+  GXY_CHECK_LAUNCH();
+  hipLaunchKernelGGL(tri_cgs_kernel, dim3(nmat), dim3(kCgsThreads), 0, s, nmat, nsec, d_sec_n,
+                     d_npad, d_off, Y, kmax, d_side);
   GXY_CHECK_LAUNCH();
   const int nx = (std::min(kmax, kMaxKq) + kBackCols - 1) / kBackCols;
   hipLaunchKernelGGL(tri_back_kernel, dim3(std::max(nx, 1), nmat), dim3(kBackThreads), 0, s,
