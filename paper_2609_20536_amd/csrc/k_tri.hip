@@ -759,9 +759,60 @@ __global__ __launch_bounds__(kCgsThreads) void tri_cgs_kernel(int nmat, int nsec
 constexpr int kBackThreads = 1024;
 constexpr int kBackCols = kBackThreads / 64;
 
+// One wave's column y (held in registers: lane l keeps rows l + 64 q, q < Q)
+// through the reflectors j = n-3 .. 0, in blocks of kBackBlk staged in LDS
+// by the whole workgroup (vb[t][r] = v_j[r] for r > j, else 0).
+constexpr int kBackBlk = 16;
+
+template <int Q>
+__device__ __forceinline__ void back_column(const double *Am, const double *tau, int n, int np,
+                                            double *yc, bool active, double (*vb)[kTriMaxN],
+                                            int lane, int tid) {
+  double y[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int r = lane + 64 * q;
+    y[q] = (active && r < n) ? yc[r] : 0.0;
+  }
+  for (int jb = n - 3; jb >= 0; jb -= kBackBlk) {
+    const int nb = min(kBackBlk, jb + 1);   // reflectors jb, jb-1, .., jb-nb+1
+    __syncthreads();
+    for (int e = tid; e < nb * n; e += kBackThreads) {
+      const int t = e / n, r = e % n;
+      const int j = jb - t;
+      vb[t][r] = r > j ? Am[(int64_t)j * np + r] : 0.0;
+    }
+    __syncthreads();
+    if (active) {
+      for (int t = 0; t < nb; ++t) {
+        const double tj = tau[jb - t];
+        if (tj == 0.0) continue;
+        double vv[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          const int r = lane + 64 * q;
+          vv[q] = r < n ? vb[t][min(r, n - 1)] : 0.0;
+        }
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) acc += vv[q] * y[q];
+        const double sdot = tj * wave_sum(acc);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) y[q] -= sdot * vv[q];
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int r = lane + 64 * q;
+    if (active && r < n) yc[r] = y[q];
+  }
+}
+
 __global__ __launch_bounds__(kBackThreads) void tri_back_kernel(
     int nmat, int nsec, const int32_t *sec_n, const int32_t *npad, const int64_t *off,
     const double *A, const double *work, double *V, double *Y, int kmax, const double *side) {
+  __shared__ double vb[kBackBlk][kTriMaxN];
   const int mi = blockIdx.y;
   if (mi >= nmat) return;
   if (side && (int)*side != mi / nsec) return;
@@ -774,20 +825,19 @@ __global__ __launch_bounds__(kBackThreads) void tri_back_kernel(
   double *Ym = Y + off[mi];   // Y[c * np + r], c < kq
   const int kq = min(min(n, kmax), kMaxKq);
   const int c = blockIdx.x * kBackCols + wave;
-  if (c < kq) {
-    double *yc = Ym + (int64_t)c * np;
-    for (int j = n - 3; j >= 0; --j) {
-      const double tj = tau[j];
-      if (tj == 0.0) continue;
-      const double *vj = Am + (int64_t)j * np + j + 1;   // v[0] = 1 stored explicitly
-      const int m = n - j - 1;
-      double acc = 0.0;
-      for (int i = lane; i < m; i += 64) acc += vj[i] * yc[j + 1 + i];
-      const double sdot = tj * wave_sum(acc);
-      for (int i = lane; i < m; i += 64) yc[j + 1 + i] -= sdot * vj[i];
-    }
-    for (int r = lane; r < n; r += 64) Vm[(int64_t)r * np + c] = yc[r];
+  const bool active = c < kq;
+  double *yc = Ym + (int64_t)(active ? c : 0) * np;
+  switch ((n + 63) >> 6) {
+#define GXY_BK(Q) \
+  case Q: back_column<Q>(Am, tau, n, np, yc, active, vb, lane, tid); break;
+    GXY_BK(1) GXY_BK(2) GXY_BK(3) GXY_BK(4) GXY_BK(5) GXY_BK(6) GXY_BK(7) GXY_BK(8)
+    GXY_BK(9) GXY_BK(10) GXY_BK(11) GXY_BK(12) GXY_BK(13) GXY_BK(14) GXY_BK(15) GXY_BK(16)
+#undef GXY_BK
+    default: break;
   }
+  __syncthreads();
+  if (active)
+    for (int r = lane; r < n; r += 64) Vm[(int64_t)r * np + c] = yc[r];
   if (blockIdx.x == 0) {
     // columns kq .. np-1 of V are zero
     for (int64_t el = tid; el < (int64_t)n * (np - kq); el += kBackThreads) {
