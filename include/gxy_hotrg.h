@@ -26,6 +26,28 @@
  *     returns results to host memory synchronises that stream before
  *     returning. One context must not be used by two host threads at once.
  *   - Nothing is printed unless the environment variable GXY_LOG is set.
+ *   - A run uses two more streams of its own: one for the copies of the
+ *     projection's offset tables and, for charge-block runs with impurity
+ *     chains whose projection fits one chunk, one for the impurity
+ *     projections of step n, which overlap the environments and eigensolves
+ *     of step n + 1 (events order them; results are the same bits either
+ *     way).
+ *
+ * Environment variables (read at each run unless noted)
+ *   GXY_LOG                log error messages to stderr
+ *   GXY_CHUNK_BYTES        bound of the projection's three D^5 buffers
+ *                          (default 32 GiB; batch workers 4 GiB)
+ *   GXY_NO_OVERLAP         keep the impurity projections on the main stream
+ *   GXY_EIG                jacobi | tri: force one sector eigensolver
+ *   GXY_JACOBI_MAX_SWEEPS  sweep limit of block Jacobi (default 120)
+ *   GXY_TRI_MULTI          0: one workgroup per sector in the tridiagonal
+ *                          reduction
+ *   GXY_TRI_MULTI_MIN      smallest sector (rows) shared between workgroups
+ *                          (default 384)
+ *   GXY_BATCH_WORKERS      default worker count of gxy_run_batch (4)
+ *   GXY_TIMING             phase timers (gxy_phase_times)
+ *   GXY_HOT_EVENTS         events around every launch of the D^7 product
+ *                          (gxy_hot_kernel_stats)
  */
 #ifndef GXY_HOTRG_H
 #define GXY_HOTRG_H
