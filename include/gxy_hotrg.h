@@ -44,6 +44,9 @@
  *                          reduction
  *   GXY_TRI_MULTI_MIN      smallest sector (rows) shared between workgroups
  *                          (default 384)
+ *   GXY_PROJ_TILE          64 | 128 | 256: projection tile for every run
+ *                          (else the autotuned one for the Dcut, else by
+ *                          tile fill); results do not depend on it
  *   GXY_BATCH_WORKERS      default worker count of gxy_run_batch (4)
  *   GXY_TIMING             phase timers (gxy_phase_times)
  *   GXY_HOT_EVENTS         events around every launch of the D^7 product
@@ -180,13 +183,13 @@ gxy_status gxy_run_batch(gxy_ctx *ctx, const gxy_point *pts, int32_t n,
 gxy_status gxy_set_batch_workers(gxy_ctx *ctx, int32_t workers);
 
 /* Measure, for each Dcut in dcuts[0..n), the projection contractions with
- * 64 x 64 and with 128 x 128 output tiles on the run templ (with that
- * Dcut; its second run is timed, the first warms up) and keep the faster
- * tile for later runs at that Dcut on this context (and its batch
- * workers). tiles[i] (optional) receives the choice, ms[2 i], ms[2 i + 1]
- * (optional) the summed time of the D^7 products for 64 and 128. The tile
- * does not change any result: every output element is accumulated over
- * the same k-slices in the same order. */
+ * 64 x 64, 128 x 128 and 256 x 128 output tiles (tile 64, 128, 256) on the
+ * run templ (with that Dcut; its second run is timed, the first warms up)
+ * and keep the fastest tile for later runs at that Dcut on this context
+ * (and its batch workers). tiles[i] (optional) receives the choice,
+ * ms[3 i .. 3 i + 2] (optional) the summed time of the D^7 products for 64,
+ * 128 and 256. The tile does not change any result: every output element
+ * is accumulated over the same k-slices in the same order. */
 gxy_status gxy_autotune(gxy_ctx *ctx, const gxy_point *templ, const int32_t *dcuts,
                         int32_t n, int32_t *tiles, double *ms);
 

@@ -1216,6 +1216,11 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
       // may overwrite them)
       int proj_tile = ctx->force_tile;
       if (!proj_tile) {
+        const char *ev = getenv("GXY_PROJ_TILE");
+        const int t = ev ? atoi(ev) : 0;
+        if (t == 64 || t == 128 || t == 256) proj_tile = t;
+      }
+      if (!proj_tile) {
         const auto it = ctx->tile_for_dcut.find(p.dcut);
         if (it != ctx->tile_for_dcut.end()) proj_tile = it->second;
       }
@@ -1676,7 +1681,9 @@ gxy_status gxy_autotune(gxy_ctx *ctx, const gxy_point *templ, const int32_t *dcu
     gxy::validate(p);
     double best_ms = 0.0;
     int best = 0;
-    for (int tile : {64, 128}) {
+    const int cand[3] = {64, 128, 256};
+    for (int ti = 0; ti < 3; ++ti) {
+      const int tile = cand[ti];
       ctx->force_tile = tile;
       ctx->hot_force = true;
       double st[4] = {0, 0, 0, 0};
@@ -1694,7 +1701,7 @@ gxy_status gxy_autotune(gxy_ctx *ctx, const gxy_point *templ, const int32_t *dcu
         throw;
       }
       for (int j = 0; j < 4; ++j) st[j] = ctx->hot_stats[j];
-      if (ms) ms[2 * i + (tile == 128)] = st[1];
+      if (ms) ms[3 * i + ti] = st[1];
       if (best == 0 || st[1] < best_ms) {
         best = tile;
         best_ms = st[1];

@@ -90,9 +90,14 @@ struct GGroup {
   int64_t ar, ac, br, bc, cr, cc;
 };
 
-// Many independent sub-products in one launch (charge blocks). Tile size is
-// tile x tile (64 or 128) for every group of the launch. prec (gxy_precision)
-// selects what the matrix cores compute in; operands and C stay FP64.
+// Output tile of a grouped launch: 64 (64 x 64), 128 (128 x 128) or 256
+// (256 rows x 128 columns).
+inline int tile_rows(int tile) { return tile; }
+inline int tile_cols(int tile) { return tile == 256 ? 128 : tile; }
+
+// Many independent sub-products in one launch (charge blocks), one output
+// tile shape for every group of the launch. prec (gxy_precision) selects
+// what the matrix cores compute in; operands and C stay FP64.
 struct GroupedGemm {
   int32_t ngroups, total_tiles, tile, prec;
   const GGroup *groups;

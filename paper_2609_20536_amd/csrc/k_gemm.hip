@@ -395,7 +395,9 @@ void launch_grouped(const GroupedGemm &g, hipStream_t s) {
 template <int PREC>
 void launch_grouped_prec(const GroupedGemm &g, hipStream_t s) {
   constexpr int BK = PREC == kB3 ? 32 : 16;
-  if (g.tile == 128)
+  if (g.tile == 256)
+    launch_grouped<256, 128, BK, 4, 2, PREC>(g, s);
+  else if (g.tile == 128)
     launch_grouped<128, 128, BK, 4, 2, PREC>(g, s);
   else
     launch_grouped<64, 64, BK, 2, 2, PREC>(g, s);

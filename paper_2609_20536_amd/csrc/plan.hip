@@ -103,7 +103,8 @@ Launch finish_launch(TablePlan &tp, const std::vector<GSpec> &gs, bool kfa, bool
     G.bc = g.bc;
     G.cr = g.cr;
     G.cc = g.cc;
-    L.total_tiles += ((g.M + L.tile - 1) / L.tile) * ((g.N + L.tile - 1) / L.tile);
+    const int tm = tile_rows(L.tile), tn = tile_cols(L.tile);
+    L.total_tiles += ((g.M + tm - 1) / tm) * ((g.N + tn - 1) / tn);
     L.flops += 2.0 * g.M * g.N * (double)g.K;
     L.bytes += 8.0 * ((double)g.M * g.K + (double)g.K * g.N + (double)g.M * g.N);
     tp.groups.push_back(G);

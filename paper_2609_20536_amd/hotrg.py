@@ -260,8 +260,8 @@ class Context:
         return [self._result(res[i], i) for i in range(len(pts))]
 
     def autotune(self, point, dcuts):
-        """Pick the faster projection tile per Dcut (see gxy_autotune);
-        returns {dcut: (tile, ms64, ms128)}."""
+        """Pick the fastest projection tile per Dcut (see gxy_autotune);
+        returns {dcut: (tile, ms64, ms128, ms256)}."""
         import numpy as np
         pt = point_from(point)
         d = np.ascontiguousarray(dcuts, dtype=np.int32)
@@ -273,13 +273,13 @@ class Context:
             copies.append(q)
         self.reserve(copies)
         tiles = np.empty(d.size, dtype=np.int32)
-        ms = np.empty(2 * d.size)
+        ms = np.empty(3 * d.size)
         self._check(self.lib.gxy_autotune(self.handle, C.byref(pt),
                                           d.ctypes.data_as(C.POINTER(C.c_int32)), d.size,
                                           tiles.ctypes.data_as(C.POINTER(C.c_int32)),
                                           ms.ctypes.data_as(C.POINTER(C.c_double))),
                     self.handle)
-        return {int(x): (int(t), float(ms[2 * i]), float(ms[2 * i + 1]))
+        return {int(x): (int(t), float(ms[3 * i]), float(ms[3 * i + 1]), float(ms[3 * i + 2]))
                 for i, (x, t) in enumerate(zip(d, tiles))}
 
     def step_log(self, run=0):

@@ -69,10 +69,10 @@ def test_autotune_picks_a_tile_and_keeps_results(ctx):
     pt = W.precision_point(dcut=24, impurities=0).with_(nsteps=8)
     before = ctx.run(pt)
     table = ctx.autotune(pt, [24, 32])
-    for d, (tile, ms64, ms128) in table.items():
-        assert tile in (64, 128)
-        assert ms64 > 0 and ms128 > 0
-        assert (tile == 64) == (ms64 <= ms128)
+    for d, (tile, ms64, ms128, ms256) in table.items():
+        assert tile in (64, 128, 256)
+        assert ms64 > 0 and ms128 > 0 and ms256 > 0
+        assert {64: ms64, 128: ms128, 256: ms256}[tile] == min(ms64, ms128, ms256)
     after = ctx.run(pt)
     assert after.lnz_per_site == before.lnz_per_site
 
@@ -90,3 +90,22 @@ def test_projection_chunks_do_not_change_results(ctx, chunk_mb, monkeypatch):
     for p, w in zip(pts, whole):
         r = ctx.run(p)
         assert _same(r, w), (p, r, w)
+
+
+@pytest.mark.parametrize("prec,k", [(W.PREC_FP64, 0), (W.PREC_FP32, 3), (W.PREC_BF16X3, 3)])
+def test_projection_tiles_give_the_same_bits(ctx, prec, k, monkeypatch):
+    """64 x 64, 128 x 128 and 256 x 128 projection tiles accumulate every
+    output element over the same k-slices in the same order, in each
+    arithmetic form."""
+    pts = [W.Point(beta=1.1, delta=0.6, nmax=6, dcut=32, nsteps=8, impurities=3, prec=prec,
+                   fp64_steps=k),
+           W.Point(beta=0.9, delta=0.4, nmax=5, dcut=24, nsteps=7, h1=0.05, impurities=3,
+                   prec=prec, fp64_steps=k)]
+    ref = None
+    for tile in ("64", "128", "256"):
+        monkeypatch.setenv("GXY_PROJ_TILE", tile)
+        res = [ctx.run(p) for p in pts]
+        if ref is None:
+            ref = res
+        for r, q in zip(res, ref):
+            assert _same(r, q), (tile, r, q)
