@@ -209,3 +209,32 @@ def test_golden_runs(ctx, path):
             if _tie_level(gd["cut_gap"]):
                 mtol = max(mtol, TIE_CUT_M_TOL)
             assert abs(got - ref) <= mtol
+
+
+def _cv_triplets():
+    """(beta, [minus, centre, plus] golden records) for every complete
+    zero-field C_v stencil stored from the oracle."""
+    out = []
+    for c in sorted(glob.glob(os.path.join(GOLDEN, "cv_b*_c_pure.json"))):
+        m, p = c.replace("_c_pure", "_m_pure"), c.replace("_c_pure", "_p_pure")
+        if os.path.exists(m) and os.path.exists(p):
+            recs = [json.load(open(f)) for f in (m, c, p)]
+            out.append((recs[1]["point"]["beta"], recs))
+    return out
+
+
+@pytest.mark.parametrize("beta,recs", _cv_triplets(), ids=lambda x: str(x) if isinstance(x, float) else "")
+def test_specific_heat_matches_stored_oracle_values(ctx, beta, recs):
+    """C_v = beta^2 d^2(ln Z/V)/d beta^2 by central differences (step 1e-3;
+    Ch. 3, the specific-heat equation), from GPU runs through the library's
+    observables kernel, against the same differences of the oracle's stored
+    ln Z/V. Each ln Z/V agrees to 1e-12, so C_v to 4 beta^2 1e-12 / 1e-6."""
+    from paper_2609_20536_amd import surrogate as S
+    pt = recs[1]["point"]
+    db = recs[2]["point"]["beta"] - beta
+    assert abs(db - 1e-3) < 1e-12
+    cv = S.cv_along_beta(ctx, pt["delta"], [beta], pt["dcut"], pt["nmax"], pt["nsteps"],
+                         workers=1, db=db)[0]
+    l = [r["lnz_per_site"] for r in recs]
+    cv_oracle = beta ** 2 * (l[0] - 2.0 * l[1] + l[2]) / db ** 2
+    assert abs(cv - cv_oracle) <= 4.0 * beta ** 2 * 1e-12 / db ** 2
