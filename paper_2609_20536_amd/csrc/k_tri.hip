@@ -17,8 +17,9 @@
 //     is kept in row j of A (right of the diagonal). Sectors of at least
 //     384 rows are shared by up to 8 workgroups of one cooperative launch
 //     (a barrier of the matrix's workgroups per column).
-//  2. tri_bisect: every eigenvalue of T by bisection on Sturm counts, one
-//     thread each (all of them enter the discarded weights).
+//  2. tri_bisect: every eigenvalue of T by bisection on Sturm counts, a
+//     group of 8 lanes each taking three halvings per round (all of them
+//     enter the discarded weights).
 //  3. tri_invit: the leading kq = min(n, Dcut) eigenvectors of T, one thread
 //     per vector, by inverse iteration on the pivoted LU factorisation of
 //     T - lambda I, then Gram-Schmidt across the workgroup (the textbook
@@ -442,12 +443,27 @@ __global__ void tri_counters_kernel(int nmat, const int32_t *npad, const int64_t
     *reinterpret_cast<int32_t *>(work + off[mi] + 4 * (int64_t)npad[mi]) = 0;
 }
 
-// Eigenvalues of T by bisection on Sturm counts, one thread per eigenvalue
-// (index k = k-th largest). The count of eigenvalues below x is the number of
-// negative pivots of the LDL^T factorisation of T - x I; pivots smaller than
-// pivmin are replaced by -pivmin. Bisection stops at relative width 2 eps or
-// after 128 halvings. The results are made non-increasing in k.
+// Eigenvalues of T by bisection on Sturm counts (index k = k-th largest).
+// The count of eigenvalues below x is the number of negative pivots of the
+// LDL^T factorisation of T - x I; pivots smaller than pivmin are replaced by
+// -pivmin. Bisection stops when the midpoint no longer lies strictly inside
+// the interval, at relative width 2 eps, or after 128 halvings. The results
+// are made non-increasing in k by tri_values_kernel.
+//
+// Each eigenvalue has a group of kBisLanes = 2^kBisLevels lanes. The
+// midpoints that the next kBisLevels halvings can visit form a binary tree of
+// kBisLanes - 1 points, each computed as 0.5 (a + b) from its two enclosing
+// points exactly as sequential halving computes it; lane g > 0 takes the
+// Sturm count at point g, and every lane of the group then replays the
+// halvings (tests included) on the shared counts. The result is the one of
+// plain one-point bisection, bit for bit, in a kBisLevels-th of the rounds:
+// the Sturm recurrence is a chain of dependent divisions, so the lanes run
+// side by side at the latency of one.
 constexpr int kBisThreads = 256;
+constexpr int kBisLevels = 3;
+constexpr int kBisLanes = 1 << kBisLevels;
+constexpr int kBisPerBlock = kBisThreads / kBisLanes;
+constexpr int kBisMaxHalvings = 128;
 
 __device__ int sturm_below(const double *d, const double *e2, int n, double x, double pivmin) {
   double q = d[0] - x;
@@ -467,47 +483,99 @@ __global__ __launch_bounds__(kBisThreads) void tri_bisect_kernel(int nmat, int n
                                                                  const int64_t *off,
                                                                  double *work) {
   __shared__ double ds[kTriMaxN], e2s[kTriMaxN];
-  __shared__ double gl_s, gu_s, piv_s;
+  __shared__ double red_s[3][kBisThreads / 64];
   const int mi = blockIdx.y;
   if (mi >= nmat) return;
   const int n = sec_n[mi % nsec];
+  if (blockIdx.x * kBisPerBlock >= n) return;   // uniform over the block
   const int np = npad[mi];
   double *dg = work + off[mi], *eg = dg + np, *lam = dg + 3 * np;
+  // Gershgorin interval and the largest squared off-diagonal (min and max
+  // are exact, so the reduction order does not matter)
+  double gl = DBL_MAX, gu = -DBL_MAX, emax2 = 0.0;
   for (int i = threadIdx.x; i < n; i += kBisThreads) {
-    ds[i] = dg[i];
-    e2s[i] = i < n - 1 ? eg[i] * eg[i] : 0.0;
+    const double di = dg[i];
+    const double el = i > 0 ? eg[i - 1] : 0.0, er = i < n - 1 ? eg[i] : 0.0;
+    const double r = fabs(el) + fabs(er);
+    ds[i] = di;
+    e2s[i] = er * er;
+    gl = fmin(gl, di - r);
+    gu = fmax(gu, di + r);
+    emax2 = fmax(emax2, er * er);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    gl = fmin(gl, __shfl_xor(gl, o, 64));
+    gu = fmax(gu, __shfl_xor(gu, o, 64));
+    emax2 = fmax(emax2, __shfl_xor(emax2, o, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red_s[0][threadIdx.x >> 6] = gl;
+    red_s[1][threadIdx.x >> 6] = gu;
+    red_s[2][threadIdx.x >> 6] = emax2;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    // Gershgorin interval and the pivot floor
-    double gl = DBL_MAX, gu = -DBL_MAX, emax2 = 0.0;
-    for (int i = 0; i < n; ++i) {
-      const double r = (i > 0 ? fabs(eg[i - 1]) : 0.0) + (i < n - 1 ? fabs(eg[i]) : 0.0);
-      gl = fmin(gl, ds[i] - r);
-      gu = fmax(gu, ds[i] + r);
-      emax2 = fmax(emax2, e2s[i]);
+  gl = red_s[0][0], gu = red_s[1][0], emax2 = red_s[2][0];
+  for (int w = 1; w < kBisThreads / 64; ++w) {
+    gl = fmin(gl, red_s[0][w]);
+    gu = fmax(gu, red_s[1][w]);
+    emax2 = fmax(emax2, red_s[2][w]);
+  }
+  const double wdt = fmax(gu - gl, DBL_MIN);
+  const double pivmin = DBL_MIN * fmax(1.0, emax2);
+  const int g = threadIdx.x % kBisLanes;
+  const int k = blockIdx.x * kBisPerBlock + threadIdx.x / kBisLanes;
+  if (k >= n) return;   // whole groups leave together
+  const int j = n - 1 - k;   // ascending index of the k-th largest eigenvalue
+  const int base = (threadIdx.x & 63) & ~(kBisLanes - 1);
+  double lo = gl - 2.0 * DBL_EPSILON * wdt - DBL_MIN;
+  double hi = gu + 2.0 * DBL_EPSILON * wdt + DBL_MIN;
+  int halvings = 0;
+  bool done = false;
+  while (!done) {
+    // this lane's tree point: descend from (lo, hi), halving towards index g
+    double x = lo;
+    {
+      double lv = lo, rv = hi;
+      int a = 0;
+#pragma unroll
+      for (int h = kBisLanes / 2; h >= 1; h >>= 1) {
+        const double mv = 0.5 * (lv + rv);
+        if (g == a + h) x = mv;
+        if (g < a + h) {
+          rv = mv;
+        } else {
+          lv = mv;
+          a += h;
+        }
+      }
     }
-    const double w = fmax(gu - gl, DBL_MIN);
-    gl_s = gl - 2.0 * DBL_EPSILON * w - DBL_MIN;
-    gu_s = gu + 2.0 * DBL_EPSILON * w + DBL_MIN;
-    piv_s = DBL_MIN * fmax(1.0, emax2);
-  }
-  __syncthreads();
-  const int k = blockIdx.x * kBisThreads + threadIdx.x;
-  if (k < n) {
-    const int j = n - 1 - k;   // ascending index of the k-th largest eigenvalue
-    double lo = gl_s, hi = gu_s;
-    for (int it = 0; it < 128; ++it) {
-      const double mid = 0.5 * (lo + hi);
-      if (mid <= lo || mid >= hi) break;
-      if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi))) break;
-      if (sturm_below(ds, e2s, n, mid, piv_s) > j)
+    const int c = g > 0 ? sturm_below(ds, e2s, n, x, pivmin) : 0;
+    // replay the halvings on the group's points and counts
+    int a = 0, z = kBisLanes;
+#pragma unroll
+    for (int lev = 0; lev < kBisLevels; ++lev) {
+      if (halvings == kBisMaxHalvings) {
+        done = true;
+        break;
+      }
+      const int m = (a + z) >> 1;
+      const double mid = __shfl(x, base + m, 64);
+      const int cm = __shfl(c, base + m, 64);
+      if (mid <= lo || mid >= hi || hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi))) {
+        done = true;
+        break;
+      }
+      if (cm > j) {
+        z = m;
         hi = mid;
-      else
+      } else {
+        a = m;
         lo = mid;
+      }
+      ++halvings;
     }
-    lam[k] = 0.5 * (lo + hi);
   }
+  if (g == 0) lam[k] = 0.5 * (lo + hi);
 }
 
 // Make the eigenvalues non-increasing and put them on diag(A) (padding -1),
@@ -893,7 +961,7 @@ void launch_tri_values(int nmat, int nsec, const int *h_sec_n, const int32_t *d_
                        d_sec_n, d_npad, d_off, A, work, Y, grouped ? 1 : 0);
     GXY_CHECK_LAUNCH();
   }
-  hipLaunchKernelGGL(tri_bisect_kernel, dim3(kTriMaxN / kBisThreads, nmat), dim3(kBisThreads),
+  hipLaunchKernelGGL(tri_bisect_kernel, dim3(kTriMaxN / kBisPerBlock, nmat), dim3(kBisThreads),
                      0, s, nmat, nsec, d_sec_n, d_npad, d_off, work);
   GXY_CHECK_LAUNCH();
   hipLaunchKernelGGL(tri_values_kernel, dim3(nmat), dim3(256), 0, s, nmat, nsec, d_sec_n,
