@@ -40,7 +40,12 @@ namespace gxy {
 
 namespace {
 
-constexpr int kRedThreads = 1024;
+// 512 threads: the reduction's registers (up to 256 per lane at 8 waves per
+// compute unit) then hold its working set without spilling; at 1024 threads
+// (128 registers) about 90 values per lane spilled to scratch, whose reloads
+// miss in the caches after every matrix-vector product has streamed A22
+// through them (bench: 31.5 -> 39.7 steps/s).
+constexpr int kRedThreads = 512;
 constexpr int kRedWaves = kRedThreads / 64;
 constexpr int kMvCols = kTriMaxN / 64;   // row segments of 64 per lane in A22 v
 
@@ -89,15 +94,19 @@ constexpr int kNb = 16;
 // Sharing pays only for large sectors: every column costs a barrier of the
 // matrix's workgroups, and they hold their compute units while they wait.
 // Bench workload (largest sectors near 540 rows): 29.0 steps/s with the
-// threshold at 512 rows, 29.9 at 384, 29.8 at 256, 28.9 at 768.
+// threshold at 512 rows, 29.9 at 384, 29.8 at 256, 28.9 at 768 (1024-thread
+// workgroups); 39.9 at 384 and 39.7 at 256 with 512 threads.
 constexpr int kMultiMinRows = 384;
 
 // Workgroups that share one matrix in the multi-workgroup reduction: about
-// 96 rows of A22 each, at most 8, and few enough that their private panels
-// (2 kNb n values each) fit in the matrix's npad^2 scratch slot.
+// 128 rows of A22 each, at most 8, and few enough that their private panels
+// (2 kNb n values each) fit in the matrix's npad^2 scratch slot. Bench
+// workload (largest sectors near 540 rows, 512-thread workgroups): 40.5
+// steps/s with 128 rows per workgroup, 39.9 with 96, 40.3 with 192, 38.3
+// with 64.
 __host__ __device__ inline int tri_groups(int n) {
   const int np = (n + 31) / 32 * 32;
-  int g = (n + 95) / 96;
+  int g = (n + 127) / 128;
   if (g > 8) g = 8;
   if (g > np / 32) g = np / 32;
   return g < 1 ? 1 : g;
@@ -248,8 +257,8 @@ __device__ void tri_reduce_body(int nmat, int nsec, const int32_t *sec_n, const 
         }
         __syncthreads();
         // q1 = W^T v, q2 = V^T v over the earlier panel columns
-        if (wave < t) {
-          const double *vs = Vg + (int64_t)wave * n + j + 1, *ws = Wg + (int64_t)wave * n + j + 1;
+        for (int sw = wave; sw < t; sw += kRedWaves) {
+          const double *vs = Vg + (int64_t)sw * n + j + 1, *ws = Wg + (int64_t)sw * n + j + 1;
           double a1 = 0.0, a2 = 0.0;
           for (int i = lane; i < m; i += 64) {
             a1 += ws[i] * v[i];
@@ -258,15 +267,15 @@ __device__ void tri_reduce_body(int nmat, int nsec, const int32_t *sec_n, const 
           a1 = wave_sum(a1);
           a2 = wave_sum(a2);
           if (lane == 0) {
-            q1[wave] = a1;
-            q2[wave] = a2;
+            q1[sw] = a1;
+            q2[sw] = a2;
           }
         }
         // A22 v, using the symmetry of A22: sum over k of v[k] times row k,
         // so that lanes run along rows (coalesced) with no cross-lane sums.
-        // The k range is split into G x 16 parts (G = tri_groups(n) in a
-        // launch whose largest sector has at least kMultiMinRows rows, else
-        // 1): group h's 16
+        // The k range is split into G x kRedWaves parts (G = tri_groups(n)
+        // in a launch whose largest sector has at least kMultiMinRows rows,
+        // else 1): group h's kRedWaves
         // parts (one per wave) are added in a fixed order through LDS, then
         // the group sums in order of h. With MULTI group h is workgroup h of
         // the matrix; one workgroup alone runs the groups one after another
