@@ -1228,9 +1228,10 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
       SL.pos = blk.pos;
       SL.vrank = blk.vrank;
       const QSet s0{0};
-      // launch kinds: pure X, Y, T'; impurity Y = X(T) T_X2, T' of it,
-      // X(T_X), Y = X(T_X) T2
-      enum { PX, PY, PT, IY, IT, IX2, IY2, NKIND };
+      // launch kinds: pure X, Y, T'; impurity Y = X(T) T_X2, X(T_X),
+      // Y += X(T_X) T2, T' of the summed Y (the projection is linear in Y, so
+      // the two placements share one T' product)
+      enum { PX, PY, PT, IY, IX2, IY2, IT, NKIND };
       struct Part {
         int a0 = 0, ac = 0, k = -1;  // k = -1: pure tensor; else impurity k
         ProjJob job[NKIND];
@@ -1250,7 +1251,7 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
         if (parts[i].k < 0)
           for (int kd : {PX, PY, PT}) order.push_back({i, kd});
         else
-          for (int kd : {IY, IT, IX2, IY2}) order.push_back({i, kd});
+          for (int kd : {IY, IX2, IY2, IT}) order.push_back({i, kd});
       }
       auto plan_job = [&SL, &s0, &imp_set, &parts, &arena](int i, int kd) {
         Part &pt = parts[i];
@@ -1302,7 +1303,7 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
       };
       size_t next = 0;
       auto take = [&](int i, int kd) -> ProjJob & {
-        // jobs are consumed in spawn order; an impurity T' is used twice
+        // jobs are consumed in spawn order
         while (next < order.size() && (order[next].first < i ||
                                        (order[next].first == i && order[next].second <= kd))) {
           spawn_upto(next + 1 + kPlanAhead);
@@ -1336,11 +1337,12 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
           // average 3.3 ms instead of 4.0)
           if (nimp > 0) imp_start();
         } else {
+          // (both Y products write the same blocks: those whose row and
+          // column charges differ by a charge of the impurity)
           go(take(i, IY), b.X, b.TX2[k], b.YI, 1.0, 0.0, true, si, sl + IY);
-          go(take(i, IT), b.YI, b.P, b.TXn[k], 0.5, 0.0, false, si, sl + IT);
           go(take(i, IX2), b.P, b.TX[k], b.XI, 1.0, 0.0, false, si, sl + IX2);
-          go(take(i, IY2), b.XI, b.T2, b.YI, 1.0, 0.0, true, si, sl + IY2);
-          go(take(i, IT), b.YI, b.P, b.TXn[k], 0.5, 1.0, false, si, sl + IT);
+          go(take(i, IY2), b.XI, b.T2, b.YI, 1.0, 1.0, true, si, sl + IY2);
+          go(take(i, IT), b.YI, b.P, b.TXn[k], 0.5, 0.0, false, si, sl + IT);
         }
       }
       if (si != s) record_on(si, 4 + par);
