@@ -216,8 +216,9 @@ __device__ unsigned long long tie_key(int label, int rank) {
 }
 
 // per side: writes side_res[side*8 + {0 eps, 1 trE, 2 lam1, 3 gap, 4 ties}],
-// side_pick_{sec,col,rank}[side*dcut + p]
-__global__ void select_side_kernel(SelectArgs a, double *side_res,
+// side_pick_{sec,col,rank}[side*dcut + p]. General form for any number of
+// candidates: they stay in global memory.
+__global__ void select_side_wide_kernel(SelectArgs a, double *side_res,
                                    int32_t *side_pick_sec, int32_t *side_pick_col,
                                    int32_t *side_pick_rank) {
   __shared__ double redd[kSelThreads];
@@ -317,6 +318,176 @@ __global__ void select_side_kernel(SelectArgs a, double *side_res,
   minkept = block_min(minkept, redd);
   maxdisc = block_max(maxdisc, redd);
   if (threadIdx.x == 0) {
+    side_res[side * 8 + 0] = eps;
+    side_res[side * 8 + 1] = tr;
+    side_res[side * 8 + 2] = lam1;
+    side_res[side * 8 + 3] = lam1 > 0.0 ? (minkept - maxdisc) / lam1 : 0.0;
+    side_res[side * 8 + 4] = (double)ties;
+  }
+}
+
+
+// The same selection with each thread's candidates (c = thread + k
+// kSelThreads) held in registers, for at most kSelThreads kSelPer candidates
+// per side: the greedy picks then touch no global memory, and their
+// reductions are one wave-level pass plus one barrier each. Maximum, minimum
+// and counts are exact in any order, and the discarded weight and trace are
+// summed in the order of the general form, so both give the same bits. A
+// sector whose eigenvalues arrive in non-increasing order (the tridiagonal
+// path's) has rank = column; any other sector is ranked by comparisons.
+constexpr int kSelPer = 12;
+constexpr int kSelWaves = kSelThreads / 64;
+
+__device__ __forceinline__ double sel_wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__global__ __launch_bounds__(kSelThreads) void select_side_kernel(
+    SelectArgs a, double *side_res, int32_t *side_pick_sec, int32_t *side_pick_col,
+    int32_t *side_pick_rank) {
+  __shared__ double redd[kSelThreads];
+  __shared__ double wmax[2][kSelWaves];
+  __shared__ unsigned long long wkey[kSelWaves];
+  __shared__ int wcnt[kSelWaves];
+  __shared__ int unsorted;
+  const int side = blockIdx.x;
+  const int nsec = a.nsec;
+  const int nc = a.ncand;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double *lam = a.d_lam + (int64_t)side * nc;
+  int32_t *csec = a.d_cand_sec + (int64_t)side * nc;
+  int32_t *crank = a.d_cand_rank + (int64_t)side * nc;
+  int32_t *ccol = a.d_cand_col + (int64_t)side * nc;
+  if (tid == 0) unsorted = 0;
+
+  // 1. candidates: eigenvalue = diagonal of the converged padded matrix
+  int base = 0;
+  for (int s = 0; s < nsec; ++s) {
+    const int n = a.d_sec_n[s];
+    const int mi = side * nsec + s;
+    const double *Am = a.A + a.d_mat_off[mi];
+    const int npad = a.d_mat_npad[mi];
+    for (int i = tid; i < n; i += kSelThreads) {
+      lam[base + i] = Am[(int64_t)i * npad + i];
+      csec[base + i] = s;
+      ccol[base + i] = i;
+      crank[base + i] = i;
+    }
+    base += n;
+  }
+  __syncthreads();
+  for (int c = tid; c + 1 < nc; c += kSelThreads)
+    if (csec[c] == csec[c + 1] && lam[c] < lam[c + 1]) unsorted = 1;
+  __syncthreads();
+  if (unsorted) {
+    // within-sector rank by decreasing eigenvalue (ties by column)
+    base = 0;
+    for (int s = 0; s < nsec; ++s) {
+      const int n = a.d_sec_n[s];
+      for (int i = tid; i < n; i += kSelThreads) {
+        const double li = lam[base + i];
+        int r = 0;
+        for (int j = 0; j < n; ++j) {
+          const double lj = lam[base + j];
+          r += (lj > li || (lj == li && j < i)) ? 1 : 0;
+        }
+        crank[base + i] = r;
+      }
+      base += n;
+    }
+    __syncthreads();
+  }
+  double rl[kSelPer];
+  unsigned long long rk[kSelPer];
+  unsigned out = 0;   // bit k: candidate k taken (or absent)
+#pragma unroll
+  for (int k = 0; k < kSelPer; ++k) {
+    const int c = tid + k * kSelThreads;
+    if (c < nc) {
+      rl[k] = lam[c];
+      rk[k] = tie_key(a.d_sec_label[csec[c]], crank[c]);
+    } else {
+      rl[k] = -DBL_MAX;
+      rk[k] = ~0ull;
+      out |= 1u << k;
+    }
+  }
+
+  // 2. greedy picks with the tie rule
+  double lam1 = -DBL_MAX;
+  int ties = 0;
+  for (int p = 0; p < a.dcut; ++p) {
+    double v = -DBL_MAX;
+#pragma unroll
+    for (int k = 0; k < kSelPer; ++k)
+      if (!((out >> k) & 1u)) v = fmax(v, rl[k]);
+    v = sel_wave_max(v);
+    if (lane == 0) wmax[p & 1][wave] = v;
+    __syncthreads();
+    double top = wmax[p & 1][0];
+    for (int w = 1; w < kSelWaves; ++w) top = fmax(top, wmax[p & 1][w]);
+    if (p == 0) lam1 = top;
+    const double tol = a.tie_rel * fabs(lam1);
+    unsigned long long kbest = ~0ull;
+    int cnt = 0;
+#pragma unroll
+    for (int k = 0; k < kSelPer; ++k)
+      if (!((out >> k) & 1u) && rl[k] >= top - tol) {
+        ++cnt;
+        if (rk[k] < kbest) kbest = rk[k];
+      }
+    for (int o = 32; o > 0; o >>= 1) {
+      const unsigned long long ko = __shfl_xor(kbest, o, 64);
+      if (ko < kbest) kbest = ko;
+      cnt += __shfl_xor(cnt, o, 64);
+    }
+    if (lane == 0) {
+      wkey[wave] = kbest;
+      wcnt[wave] = cnt;
+    }
+    __syncthreads();
+    kbest = wkey[0];
+    cnt = wcnt[0];
+    for (int w = 1; w < kSelWaves; ++w) {
+      if (wkey[w] < kbest) kbest = wkey[w];
+      cnt += wcnt[w];
+    }
+    if (cnt > 1) ++ties;
+    int kw = -1;   // the one candidate with the winning key, if this thread holds it
+#pragma unroll
+    for (int k = 0; k < kSelPer; ++k)
+      if (!((out >> k) & 1u) && rl[k] >= top - tol && rk[k] == kbest) kw = k;
+    if (kw >= 0) {
+      const int c = tid + kw * kSelThreads;
+      out |= 1u << kw;
+      side_pick_sec[side * a.dcut + p] = csec[c];
+      side_pick_col[side * a.dcut + p] = ccol[c];
+      side_pick_rank[side * a.dcut + p] = crank[c];
+    }
+    // (no barrier needed here: the next pick writes the other wmax buffer,
+    // and wkey only after its first barrier, which every thread reaches
+    // after reading this pick's wkey)
+  }
+
+  // 3. discarded weight, trace, cut gap (fixed-order reductions)
+  double eps = 0.0, tr = 0.0, minkept = DBL_MAX, maxdisc = -DBL_MAX;
+#pragma unroll
+  for (int k = 0; k < kSelPer; ++k) {
+    if (tid + k * kSelThreads >= nc) continue;
+    tr += rl[k];
+    if ((out >> k) & 1u) {
+      minkept = fmin(minkept, rl[k]);
+    } else {
+      eps += rl[k];
+      maxdisc = fmax(maxdisc, rl[k]);
+    }
+  }
+  eps = block_sum_d(eps, redd);
+  tr = block_sum_d(tr, redd);
+  minkept = block_min(minkept, redd);
+  maxdisc = block_max(maxdisc, redd);
+  if (tid == 0) {
     side_res[side * 8 + 0] = eps;
     side_res[side * 8 + 1] = tr;
     side_res[side * 8 + 2] = lam1;
@@ -477,8 +648,12 @@ void launch_select(const SelectArgs &a, hipStream_t s) {
   int32_t *sps = a.d_taken + 2 * (int64_t)a.ncand;  // 3 * 2 * dcut ints
   int32_t *spc = sps + 2 * a.dcut;
   int32_t *spr = spc + 2 * a.dcut;
-  hipLaunchKernelGGL(select_side_kernel, dim3(2), dim3(kSelThreads), 0, s, a, side_res,
-                     sps, spc, spr);
+  if (a.ncand <= kSelThreads * kSelPer)
+    hipLaunchKernelGGL(select_side_kernel, dim3(2), dim3(kSelThreads), 0, s, a, side_res,
+                       sps, spc, spr);
+  else
+    hipLaunchKernelGGL(select_side_wide_kernel, dim3(2), dim3(kSelThreads), 0, s, a,
+                       side_res, sps, spc, spr);
   GXY_CHECK_LAUNCH();
   hipLaunchKernelGGL(select_final_kernel, dim3(1), dim3(256), 0, s, a, side_res, sps,
                      spc, spr);
