@@ -456,8 +456,12 @@ __global__ void tri_counters_kernel(int nmat, const int32_t *npad, const int64_t
 // The count of eigenvalues below x is the number of negative pivots of the
 // LDL^T factorisation of T - x I; pivots smaller than pivmin are replaced by
 // -pivmin. Bisection stops when the midpoint no longer lies strictly inside
-// the interval, at relative width 2 eps, or after 128 halvings. The results
-// are made non-increasing in k by tri_values_kernel.
+// the interval, at width max(2 eps |lambda|, eps ||T||) (the absolute floor
+// is the usual one of bisection codes: the Householder reduction already
+// moves every eigenvalue by about eps ||A||, so halving further only
+// resolves rounding noise, at up to 128 halvings for eigenvalues near zero
+// instead of about 53), or after 128 halvings. The results are made
+// non-increasing in k by tri_values_kernel.
 //
 // Each eigenvalue has a group of kBisLanes = 2^kBisLevels lanes. The
 // midpoints that the next kBisLevels halvings can visit form a binary tree of
@@ -531,6 +535,9 @@ __global__ __launch_bounds__(kBisThreads) void tri_bisect_kernel(int nmat, int n
   }
   const double wdt = fmax(gu - gl, DBL_MIN);
   const double pivmin = DBL_MIN * fmax(1.0, emax2);
+  // absolute floor of the stopping width: eps ||T||, the accuracy to which
+  // the reduction itself fixes the eigenvalues
+  const double atol = DBL_EPSILON * fmax(fabs(gl), fabs(gu));
   const int g = threadIdx.x % kBisLanes;
   const int k = blockIdx.x * kBisPerBlock + threadIdx.x / kBisLanes;
   if (k >= n) return;   // whole groups leave together
@@ -570,7 +577,8 @@ __global__ __launch_bounds__(kBisThreads) void tri_bisect_kernel(int nmat, int n
       const int m = (a + z) >> 1;
       const double mid = __shfl(x, base + m, 64);
       const int cm = __shfl(c, base + m, 64);
-      if (mid <= lo || mid >= hi || hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi))) {
+      if (mid <= lo || mid >= hi ||
+          hi - lo <= fmax(2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)), atol)) {
         done = true;
         break;
       }
