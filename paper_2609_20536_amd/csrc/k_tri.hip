@@ -595,18 +595,49 @@ __global__ __launch_bounds__(kBisThreads) void tri_bisect_kernel(int nmat, int n
   if (g == 0) lam[k] = 0.5 * (lo + hi);
 }
 
+constexpr int kValThreads = 256;
+constexpr int kValPer = kTriMaxN / kValThreads;
+
 // Make the eigenvalues non-increasing and put them on diag(A) (padding -1),
 // where the selection reads them. The reflectors lie right of the diagonal.
-__global__ void tri_values_kernel(int nmat, int nsec, const int32_t *sec_n,
-                                  const int32_t *npad, const int64_t *off, double *work,
-                                  double *A) {
+__global__ __launch_bounds__(kValThreads) void tri_values_kernel(
+    int nmat, int nsec, const int32_t *sec_n, const int32_t *npad, const int64_t *off,
+    double *work, double *A) {
   const int mi = blockIdx.x;
   if (mi >= nmat) return;
   const int n = sec_n[mi % nsec];
   const int np = npad[mi];
   double *lam = work + off[mi] + 3 * np;
-  if (threadIdx.x == 0)
-    for (int k = 1; k < n; ++k) lam[k] = fmin(lam[k], lam[k - 1]);
+  // prefix minimum (exact, so any grouping gives the same values): each
+  // thread scans a run of kValPer, the runs' minima are scanned across the
+  // block, then applied. NaN is fmin's identity, so a NaN eigenvalue (a
+  // failed reduction) stays where a one-by-one scan would leave it.
+  __shared__ double wave_min[kValThreads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const double none = __builtin_nan("");
+  double x[kValPer];
+  double run = none;
+#pragma unroll
+  for (int u = 0; u < kValPer; ++u) {
+    const int c = tid * kValPer + u;
+    run = fmin(run, c < n ? lam[c] : none);
+    x[u] = run;
+  }
+  double incl = run;   // inclusive scan of the run minima over the wave
+  for (int o = 1; o < 64; o <<= 1) {
+    const double y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl = fmin(incl, y);
+  }
+  if (lane == 63) wave_min[wave] = incl;
+  __syncthreads();
+  double before = __shfl_up(incl, 1, 64);
+  if (lane == 0) before = none;
+  for (int w = 0; w < wave; ++w) before = fmin(before, wave_min[w]);
+#pragma unroll
+  for (int u = 0; u < kValPer; ++u) {
+    const int c = tid * kValPer + u;
+    if (c < n) lam[c] = fmin(x[u], before);
+  }
   __syncthreads();
   double *Am = A + off[mi];
   for (int c = threadIdx.x; c < np; c += blockDim.x)
@@ -981,7 +1012,7 @@ void launch_tri_values(int nmat, int nsec, const int *h_sec_n, const int32_t *d_
   hipLaunchKernelGGL(tri_bisect_kernel, dim3(kTriMaxN / kBisPerBlock, nmat), dim3(kBisThreads),
                      0, s, nmat, nsec, d_sec_n, d_npad, d_off, work);
   GXY_CHECK_LAUNCH();
-  hipLaunchKernelGGL(tri_values_kernel, dim3(nmat), dim3(256), 0, s, nmat, nsec, d_sec_n,
+  hipLaunchKernelGGL(tri_values_kernel, dim3(nmat), dim3(kValThreads), 0, s, nmat, nsec, d_sec_n,
                      d_npad, d_off, work, A);
   GXY_CHECK_LAUNCH();
 }
