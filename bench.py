@@ -52,8 +52,9 @@ def workload_point(dcut: int):
 
 def measured_traffic():
     """HBM bytes per launch of the D^7 GEMM from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary, if the kernel and planner sources are
-    unchanged since the counters were taken (else None)."""
+    FETCH_SIZE / WRITE_SIZE summary, if the sources it names (kernel, planner
+    and the engine that issues the launches) are unchanged since the counters
+    were taken (else None)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "ygemm_d64_chains_fp64_traffic.json")
     if not os.path.exists(path):

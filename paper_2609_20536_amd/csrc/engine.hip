@@ -1318,7 +1318,7 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
         const GGroup *dg = reinterpret_cast<const GGroup *>(b.proj_tab + j.off);
         const int64_t *dt = reinterpret_cast<const int64_t *>(b.proj_tab + j.off +
                                                               j.ngrp * (int64_t)sizeof(GGroup));
-        if (hot) hot_begin(ctx, st, j.L.flops, j.L.bytes);
+        if (hot) hot_begin(ctx, st, j.L.flops, j.L.bytes + (beta != 0.0 ? j.L.c_bytes : 0.0));
         run_launch(j.L, dg, dt, A, B, C, alpha, beta, st, sprec);
         if (hot) hot_end(ctx, st);
       };

@@ -37,6 +37,7 @@ struct Launch {
   bool kfast_a = false, nfast_b = false;
   double flops = 0.0;  // algorithmic 2 M N K summed over groups
   double bytes = 0.0;  // algorithmic FP64 bytes: A, B read once, C written once
+  double c_bytes = 0.0;  // 8 M N over the groups: C read once more when beta != 0
 };
 
 struct TablePlan {

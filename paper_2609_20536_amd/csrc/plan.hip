@@ -107,6 +107,7 @@ Launch finish_launch(TablePlan &tp, const std::vector<GSpec> &gs, bool kfa, bool
     L.total_tiles += ((g.M + tm - 1) / tm) * ((g.N + tn - 1) / tn);
     L.flops += 2.0 * g.M * g.N * (double)g.K;
     L.bytes += 8.0 * ((double)g.M * g.K + (double)g.K * g.N + (double)g.M * g.N);
+    L.c_bytes += 8.0 * (double)g.M * g.N;
     tp.groups.push_back(G);
     ++L.ngroups;
   }
