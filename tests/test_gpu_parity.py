@@ -215,9 +215,13 @@ def _cv_triplets():
     """(beta, [minus, centre, plus] golden records) for every complete
     zero-field C_v stencil stored from the oracle."""
     out = []
-    for c in sorted(glob.glob(os.path.join(GOLDEN, "cv_b*_c_pure.json"))):
-        m, p = c.replace("_c_pure", "_m_pure"), c.replace("_c_pure", "_p_pure")
-        if os.path.exists(m) and os.path.exists(p):
+    trip = [(c, c.replace("_c_pure", "_m_pure"), c.replace("_c_pure", "_p_pure"))
+            for c in sorted(glob.glob(os.path.join(GOLDEN, "cv_b*_c_pure.json")))]
+    # the bench point (beta = 1.2, Delta = 0.7) at Dcut = 64
+    c64 = os.path.join(GOLDEN, "prec_d64_pure.json")
+    trip.append((c64, c64[:-5] + "_m.json", c64[:-5] + "_p.json"))
+    for c, m, p in trip:
+        if os.path.exists(c) and os.path.exists(m) and os.path.exists(p):
             recs = [json.load(open(f)) for f in (m, c, p)]
             out.append((recs[1]["point"]["beta"], recs))
     return out
