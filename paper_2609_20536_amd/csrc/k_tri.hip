@@ -807,8 +807,16 @@ __global__ __launch_bounds__(kInvThreads) void tri_invit_kernel(int nmat, int ns
             for (int q = 0; q < kInvChunk; ++q)
               if (q < cnt) x[i1 - q] = bx[q];
           }
+          // (in chunks too: one element at a time, each load would wait)
           const double inv = xmax > 0.0 ? 1.0 / xmax : 1.0;
-          for (int i = 0; i < n; ++i) x[i] *= inv;
+          for (int i0 = 0; i0 < n; i0 += kInvChunk) {
+            double xs[kInvChunk];
+#pragma unroll
+            for (int q = 0; q < kInvChunk; ++q) xs[q] = x[min(i0 + q, n - 1)];
+#pragma unroll
+            for (int q = 0; q < kInvChunk; ++q)
+              if (i0 + q < n) x[i0 + q] = xs[q] * inv;
+          }
         }
       }
     }
@@ -843,6 +851,9 @@ __global__ __launch_bounds__(kCgsThreads) void tri_cgs_kernel(int nmat, int nsec
       for (int j = wave; j < c; j += kCgsThreads / 64) {
         const double *xj = Ym + (int64_t)j * np;
         double acc = 0.0;
+        // (unrolled: the loads of several rows are issued before the
+        // accumulation, which keeps its order)
+#pragma unroll 8
         for (int i = lane; i < n; i += 64) acc += xj[i] * xs[i];
         acc = wave_sum(acc);
         if (lane == 0) dot[j] = acc;
@@ -850,6 +861,7 @@ __global__ __launch_bounds__(kCgsThreads) void tri_cgs_kernel(int nmat, int nsec
       __syncthreads();
       for (int i = tid; i < n; i += kCgsThreads) {
         double v = xs[i];
+#pragma unroll 8
         for (int j = 0; j < c; ++j) v -= dot[j] * Ym[(int64_t)j * np + i];
         xs[i] = v;
       }
