@@ -102,6 +102,17 @@ def test_run_matches_oracle(ctx, pt):
     _compare(ctx.run(pt), o.run_point(**pt))
 
 
+@pytest.mark.parametrize("pt", [LIVE[0], LIVE[5], LIVE[7]],
+                         ids=lambda p: ",".join(f"{k}={v}" for k, v in p.items()))
+def test_run_with_block_jacobi_matches_oracle(ctx, pt, monkeypatch):
+    """Every sector through block Jacobi instead of the tridiagonal path. Its
+    eigenvalues reach the selection in no particular order, so the kept
+    states are ranked by comparisons there (the tridiagonal path's arrive
+    sorted and take rank = column)."""
+    monkeypatch.setenv("GXY_EIG", "jacobi")
+    _compare(ctx.run(pt), o.run_point(**pt))
+
+
 @pytest.mark.parametrize("nsteps,nmax", [(0, 3), (1, 3), (2, 3), (3, 1)])
 @pytest.mark.parametrize("h,h1", [(0.0, 0.0), (0.3, 0.2)])
 def test_untruncated_tiny_tori(ctx, nsteps, nmax, h, h1):
