@@ -8,15 +8,20 @@ import it.
 What it computes, and where the thesis defines it:
 
 * Character coefficients t_n of the bond weight
-  w(phi) = exp(beta [Delta cos phi + (1 - Delta) cos 2 phi]) (Ch. 3, Sec.
+  w(phi) = exp(beta [Delta cos phi + (1 - Delta) cos q phi]) (Ch. 3, Sec.
   "Tensor Formulation", eq. for a_n): t_n = (1/2pi) int w(phi) cos(n phi).
   The normative evaluation is the periodic trapezoid rule on nquad points;
-  the Bessel-product series of that equation is the cross-check.
-* Site tensor T_{n1 n2 n3 n4} = sqrt(prod a_nk) * sum_l I_{Q+2l}(beta h)
+  the Bessel-product series of that equation is the cross-check. The thesis
+  writes the Hamiltonian (Ch. 3, Sec. "The Generalized XY Model", eq.
+  gXY_ham) for a general harmonic q and studies q = 2, the default here;
+  q >= 3 is the extension its conclusions name.
+* Site tensor T_{n1 n2 n3 n4} = sqrt(prod a_nk) * sum_l I_{Q+ql}(beta h)
   I_l(beta h1), Q = n1 + n2 - n3 - n4, legs (top, right, bottom, left)
-  (Ch. 3, Sec. "Derivation of Tensors", final site-tensor equation), and the
-  impurity tensors for <cos theta> and <cos 2 theta> (Ch. 3, Sec. "Numerical
-  Results", the two impure-tensor equations).
+  (Ch. 3, Sec. "Derivation of Tensors", final site-tensor equation, written
+  there for q = 2), and the impurity tensors for <cos theta> and
+  <cos q theta> (Ch. 3, Sec. "Numerical Results", the two impure-tensor
+  equations). The field h1 couples to cos q theta (for q = 2 the thesis's
+  nematic field).
 * HOTRG coarse graining (Ch. 2, Sec. "Higher-Order Tensor Renormalization
   Group Method"): the fused two-site tensor M (eq. Mtensor), the mode
   unfoldings' Gram matrices whose eigenvectors are the HOSVD factors U, V
@@ -37,7 +42,8 @@ design notes):
   tensors ("y-step"); an x-step is the y-step applied to the transposed
   tensor T[u, d, l, r] and transposed back. The first step is a y-step.
 * The eigendecomposition is done per symmetry sector (U(1) charge at
-  h = h1 = 0, Z2 parity at h = 0 != h1, one dense block otherwise).
+  h = h1 = 0, Z_q label (charge mod q) at h = 0 != h1, one dense block
+  otherwise).
 * Truncation keeps Dcut states chosen greedily: repeatedly take, among the
   remaining eigenvalues within TIE_REL * lambda_max of the largest
   remaining one, the state with the smallest (|q|, q, rank in its sector).
@@ -67,7 +73,7 @@ IMP_COS2 = 2
 
 SYM_U1 = 0     # integer charges, fused by addition
 SYM_NONE = 1   # a single sector (all labels 0)
-SYM_Z2 = 2     # parities, fused by addition mod 2
+SYM_Z2 = 2     # Z_q labels (charge mod q; parities for q = 2), fused by addition mod q
 
 
 # --------------------------------------------------------------------------
@@ -101,24 +107,24 @@ def bessel_i(k: int, x: float) -> float:
 
 
 def char_coeffs(beta: float, delta: float, nmax: int,
-                nquad: int = 4096) -> np.ndarray:
+                nquad: int = 4096, q: int = 2) -> np.ndarray:
     """t_n for n = -nmax..nmax by the periodic trapezoid rule on nquad points.
 
     t_n = (1/Q) sum_{k<Q} w(phi_k) cos(n phi_k), phi_k = 2 pi k / Q,
-    w(phi) = exp(beta [Delta cos phi + (1-Delta) cos 2 phi]) (Ch. 3, the
+    w(phi) = exp(beta [Delta cos phi + (1-Delta) cos q phi]) (Ch. 3, the
     character-expansion coefficient a_n written as a Fourier integral).
     The negative orders are mirrored (t_{-n} = t_n holds exactly since w is
     even) and the values are clamped at 0 (the exact coefficients are
     non-negative; odd orders at Delta = 0 come out at rounding level).
 
     Pinned by: Bessel-product series, closed sums sum t_n = e^beta,
-    sum (-1)^n t_n = e^(beta(1-2 Delta)), Parseval sum t_n^2 = t_0(2 beta),
-    the Delta = 1 and Delta = 0 reductions, beta = 0.
+    sum (-1)^n t_n = e^(beta(-Delta + (1-Delta)(-1)^q)), Parseval
+    sum t_n^2 = t_0(2 beta), the Delta = 1 and Delta = 0 reductions, beta = 0.
     """
     if nquad <= 2 * nmax:
         raise ValueError("nquad must exceed 2*nmax")
     phi = 2.0 * np.pi * np.arange(nquad, dtype=np.float64) / nquad
-    w = np.exp(beta * (delta * np.cos(phi) + (1.0 - delta) * np.cos(2.0 * phi)))
+    w = np.exp(beta * (delta * np.cos(phi) + (1.0 - delta) * np.cos(q * phi)))
     half = np.array([np.sum(w * np.cos(n * phi)) / nquad
                      for n in range(nmax + 1)])
     half = np.maximum(half, 0.0)
@@ -126,32 +132,35 @@ def char_coeffs(beta: float, delta: float, nmax: int,
 
 
 def char_coeffs_bessel(beta: float, delta: float, nmax: int,
-                       mmax: int = 50) -> np.ndarray:
-    """a_n = sum_{|m|<=mmax} I_{n-2m}(beta Delta) I_m(beta (1-Delta)).
+                       mmax: int = 50, q: int = 2) -> np.ndarray:
+    """a_n = sum_{|m|<=mmax} I_{n-qm}(beta Delta) I_m(beta (1-Delta)).
 
-    The thesis's Bessel-product form (Ch. 3, eq. a_n), truncated at |m| <= mmax
-    as the thesis does. Used as an independent check of char_coeffs.
+    The thesis's Bessel-product form (Ch. 3, eq. a_n, there with q = 2),
+    truncated at |m| <= mmax as the thesis does. Used as an independent check
+    of char_coeffs.
     """
     out = []
     for n in range(-nmax, nmax + 1):
         s = 0.0
         for m in range(-mmax, mmax + 1):
-            s += bessel_i(n - 2 * m, beta * delta) * bessel_i(m, beta * (1.0 - delta))
+            s += bessel_i(n - q * m, beta * delta) * bessel_i(m, beta * (1.0 - delta))
         out.append(s)
     return np.array(out)
 
 
 def field_factors(beta: float, h: float, h1: float, qmax: int,
-                  lmax: int = 50) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+                  lmax: int = 50, q: int = 2) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
     """Field factors of the pure and the two impure site tensors.
 
     For Q in [-qmax, qmax] (array index Q + qmax):
-      F(Q)   = sum_l I_{Q+2l}(beta h) I_l(beta h1)
-      F_M(Q) = sum_l I_l(beta h1) [I_{Q+2l-1}(beta h) + I_{Q+2l+1}(beta h)]/2
-      F_M1(Q)= sum_l I_{Q+2l}(beta h) [I_{l+1}(beta h1) + I_{l-1}(beta h1)]/2
+      F(Q)   = sum_l I_{Q+ql}(beta h) I_l(beta h1)
+      F_M(Q) = sum_l I_l(beta h1) [I_{Q+ql-1}(beta h) + I_{Q+ql+1}(beta h)]/2
+      F_M1(Q)= sum_l I_{Q+ql}(beta h) [I_{l+1}(beta h1) + I_{l-1}(beta h1)]/2
     with |l| <= lmax (Ch. 3, final site-tensor equation and the two
-    impure-tensor equations). At h = h1 = 0 these are exactly
-    delta_{Q,0}, (delta_{Q,1} + delta_{Q,-1})/2, (delta_{Q,2} + delta_{Q,-2})/2.
+    impure-tensor equations, there with q = 2: the Fourier coefficients of
+    exp(beta h cos th + beta h1 cos q th) times 1, cos th, cos q th). At
+    h = h1 = 0 these are exactly delta_{Q,0}, (delta_{Q,1} + delta_{Q,-1})/2,
+    (delta_{Q,q} + delta_{Q,-q})/2.
     """
     qs = np.arange(-qmax, qmax + 1)
     F = np.zeros(len(qs))
@@ -160,23 +169,23 @@ def field_factors(beta: float, h: float, h1: float, qmax: int,
     if h == 0.0 and h1 == 0.0:
         F[qs == 0] = 1.0
         FM[np.abs(qs) == 1] = 0.5
-        FM1[np.abs(qs) == 2] = 0.5
+        FM1[np.abs(qs) == q] = 0.5
         return F, FM, FM1
     x, x1 = beta * h, beta * h1
     for a, Q in enumerate(qs):
         f = fm = fm1 = 0.0
         for l in range(-lmax, lmax + 1):
             il1 = bessel_i(l, x1)
-            iq = bessel_i(Q + 2 * l, x)
+            iq = bessel_i(Q + q * l, x)
             f += iq * il1
-            fm += il1 * 0.5 * (bessel_i(Q + 2 * l - 1, x) + bessel_i(Q + 2 * l + 1, x))
+            fm += il1 * 0.5 * (bessel_i(Q + q * l - 1, x) + bessel_i(Q + q * l + 1, x))
             fm1 += iq * 0.5 * (bessel_i(l + 1, x1) + bessel_i(l - 1, x1))
         F[a], FM[a], FM1[a] = f, fm, fm1
     return F, FM, FM1
 
 
 def symmetry_of(h: float, h1: float) -> int:
-    """Symmetry left by the fields: U(1) at h = h1 = 0, Z2 at h = 0, else none."""
+    """Symmetry left by the fields: U(1) at h = h1 = 0, Z_q at h = 0, else none."""
     if h == 0.0 and h1 == 0.0:
         return SYM_U1
     if h == 0.0:
@@ -184,20 +193,20 @@ def symmetry_of(h: float, h1: float) -> int:
     return SYM_NONE
 
 
-def leg_labels(nmax: int, sym: int) -> np.ndarray:
+def leg_labels(nmax: int, sym: int, q: int = 2) -> np.ndarray:
     n = np.arange(-nmax, nmax + 1)
     if sym == SYM_U1:
         return n.copy()
     if sym == SYM_Z2:
-        return np.mod(n, 2)
+        return np.mod(n, q)
     return np.zeros_like(n)
 
 
-def fuse_labels(qa: np.ndarray, qb: np.ndarray, sym: int) -> np.ndarray:
+def fuse_labels(qa: np.ndarray, qb: np.ndarray, sym: int, q: int = 2) -> np.ndarray:
     """Label of the fused index (a, b) -> a * len(qb) + b."""
     s = qa[:, None] + qb[None, :]
     if sym == SYM_Z2:
-        s = np.mod(s, 2)
+        s = np.mod(s, q)
     elif sym == SYM_NONE:
         s = np.zeros_like(s)
     return s.reshape(-1)
@@ -205,17 +214,17 @@ def fuse_labels(qa: np.ndarray, qb: np.ndarray, sym: int) -> np.ndarray:
 
 def initial_tensors(beta: float, delta: float, h: float, h1: float,
                     nmax: int, nquad: int = 4096,
-                    impurities: int = 0) -> Tuple[np.ndarray, Dict[int, np.ndarray]]:
+                    impurities: int = 0, q: int = 2) -> Tuple[np.ndarray, Dict[int, np.ndarray]]:
     """Site tensor T[l, r, u, d] and the requested impurity tensors.
 
     T[l,r,u,d] = sqrt(t_l t_r t_u t_d) F(n_u + n_r - n_d - n_l); the cos
-    impurity uses F_M and the cos 2 impurity F_M1 in place of F.
+    impurity uses F_M and the cos q impurity F_M1 in place of F.
     Pinned by: the 1x1-torus trace (sum t)^2, tiny-torus brute force and
     theta quadrature (pure and with fields).
     """
-    t = char_coeffs(beta, delta, nmax, nquad)
+    t = char_coeffs(beta, delta, nmax, nquad, q)
     n = np.arange(-nmax, nmax + 1)
-    F, FM, FM1 = field_factors(beta, h, h1, 4 * nmax)
+    F, FM, FM1 = field_factors(beta, h, h1, 4 * nmax, q=q)
     l, r, u, d = np.meshgrid(n, n, n, n, indexing="ij")
     Q = u + r - d - l
     amp = np.sqrt(t[l + nmax] * t[r + nmax] * t[u + nmax] * t[d + nmax])
@@ -432,7 +441,7 @@ def _norm(T: np.ndarray, kind: str) -> float:
 def hotrg_run(T: np.ndarray, imps: Dict[int, np.ndarray], lab_h: np.ndarray,
               lab_v: np.ndarray, sym: int, dcut: int, nsteps: int,
               first: str = "y", norm: str = "fro",
-              basis_seed: Optional[int] = None) -> RunResult:
+              basis_seed: Optional[int] = None, q: int = 2) -> RunResult:
     """Coarse-grain T (and impurity tensors) nsteps times; ln Z per site.
 
     ln Z / 2^N = ln c_0 + sum_n ln c_n / 2^n + ln Tr T_N / 2^N, where c_n is
@@ -461,7 +470,7 @@ def hotrg_run(T: np.ndarray, imps: Dict[int, np.ndarray], lab_h: np.ndarray,
             imps = {k: np.ascontiguousarray(v.transpose(2, 3, 0, 1)) for k, v in imps.items()}
             lab_h, lab_v = lab_v, lab_h
         Dh, Dv = T.shape[0], T.shape[2]
-        fused = fuse_labels(lab_h, lab_h, sym)
+        fused = fuse_labels(lab_h, lab_h, sym, q)
         if Dh * Dh <= dcut:
             P = np.eye(Dh * Dh)
             new_h = fused
@@ -503,13 +512,14 @@ def run_point(beta: float, delta: float, h: float = 0.0, h1: float = 0.0,
               nmax: int = 3, dcut: int = 12, nsteps: int = 30,
               nquad: int = 4096, impurities: int = IMP_COS1 | IMP_COS2,
               first: str = "y", norm: str = "fro", basis_seed: Optional[int] = None,
-              **_ignored) -> RunResult:
+              q: int = 2, **_ignored) -> RunResult:
     """One HOTRG run from the gXY parameters (the full problem statement)."""
+    q = 2 if q == 0 else int(q)
     sym = symmetry_of(h, h1)
-    T, imps = initial_tensors(beta, delta, h, h1, nmax, nquad, impurities)
-    lab = leg_labels(nmax, sym)
+    T, imps = initial_tensors(beta, delta, h, h1, nmax, nquad, impurities, q)
+    lab = leg_labels(nmax, sym, q)
     return hotrg_run(T, imps, lab, lab, sym, dcut, nsteps, first=first, norm=norm,
-                     basis_seed=basis_seed)
+                     basis_seed=basis_seed, q=q)
 
 
 def observables_from_runs(beta: float, lnz: Sequence[float], m_h: Sequence[float],
@@ -518,10 +528,10 @@ def observables_from_runs(beta: float, lnz: Sequence[float], m_h: Sequence[float
     """f, C_v, chi, chi_n from the seven runs of one (beta, Delta) point.
 
     lnz = ln Z/V at beta - db, beta, beta + db; m_h = <cos theta> at
-    h = hc -/+ dh; m_h1 = <cos 2 theta> at h1 = hc -/+ dh1.
+    h = hc -/+ dh; m_h1 = <cos q theta> at h1 = hc -/+ dh1.
     f = -lnZ/(beta V) (F = -T ln Z), C_v = beta^2 d^2(lnZ/V)/d beta^2 by the
     central difference (eq. spech), chi = d<cos theta>/dh and
-    chi_n = d<cos 2 theta>/dh1 by central differences (eqs. susc, mag).
+    chi_n = d<cos q theta>/dh1 by central differences (eqs. susc, mag).
     """
     f = -lnz[1] / beta
     cv = beta * beta * (lnz[2] - 2.0 * lnz[1] + lnz[0]) / (dbeta * dbeta)

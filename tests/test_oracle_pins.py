@@ -37,12 +37,15 @@ def torus_trace(site_tensors, Lx, Ly):
     return float(np.einsum(*ops, [], optimize="greedy"))
 
 
-def theta_integral_2x2(t, beta, h=0.0, h1=0.0, K=40, observable=None):
+def theta_integral_2x2(t, beta, h=0.0, h1=0.0, K=40, observable=None, q=2):
     """Z (or <obs(theta_A)> Z) on the 2x2 periodic torus by trapezoid rule.
 
     Bond weight w(phi) = sum_{|n|<=nmax} t_n e^{i n phi} (character-truncated),
-    site weight exp(beta h cos theta + beta h1 cos 2 theta). Every pair of
-    neighbouring sites on the 2x2 torus is joined by two bonds.
+    site weight exp(beta h cos theta + beta h1 cos q theta). Every pair of
+    neighbouring sites on the 2x2 torus is joined by two bonds:
+    Z = (1/K^4) sum_{A,B,C,D} s_A s_B s_C s_D w(A-B)^2 w(C-D)^2 w(A-C)^2 w(B-D)^2.
+    For fixed (A, D) the sums over B and over C are the same,
+    M(A, D) = sum_X s_X w(A-X)^2 w(X-D)^2, so Z = (1/K^4) sum s_A s_D M(A, D)^2.
     """
     nmax = (len(t) - 1) // 2
     th = 2 * np.pi * np.arange(K) / K
@@ -51,14 +54,11 @@ def theta_integral_2x2(t, beta, h=0.0, h1=0.0, K=40, observable=None):
     def w(phi):
         return np.tensordot(np.cos(np.multiply.outer(phi, ns)), t, axes=([-1], [0]))
 
-    s = np.exp(beta * h * np.cos(th) + beta * h1 * np.cos(2 * th))
-    A, B, C, D = np.meshgrid(th, th, th, th, indexing="ij")
-    W = (w(A - B) ** 2) * (w(C - D) ** 2) * (w(A - C) ** 2) * (w(B - D) ** 2)
-    sa = s[:, None, None, None] * s[None, :, None, None] * s[None, None, :, None] * s[None, None, None, :]
-    W = W * sa
-    if observable is not None:
-        W = W * observable(A)
-    return float(W.sum()) / K ** 4
+    s = np.exp(beta * h * np.cos(th) + beta * h1 * np.cos(q * th))
+    W2 = w(np.subtract.outer(th, th)) ** 2
+    M = W2 @ (s[:, None] * W2)
+    sa = s if observable is None else s * observable(th)
+    return float(sa @ (M * M) @ s) / K ** 4
 
 
 def untruncated(beta, delta, nmax, nsteps, h=0.0, h1=0.0, imps=0, first="y"):
@@ -170,6 +170,94 @@ def test_two_by_two_theta_quadrature(beta, delta, h, h1):
     m2 = theta_integral_2x2(t, beta, h, h1, observable=lambda a: np.cos(2 * a)) / Z
     assert r.m_cos1 == pytest.approx(m1, abs=1e-13)
     assert r.m_cos2 == pytest.approx(m2, abs=1e-13)
+
+
+# --------------------------------------------------------------------------
+# harmonic q >= 3 of the second coupling (eq. gXY_ham with general q)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("q", [3, 4, 5])
+@pytest.mark.parametrize("beta,delta", [(0.6, 0.3), (1.2, 0.7), (1.5, 0.0)])
+def test_harmonic_q_quadrature_equals_bessel_series(q, beta, delta):
+    tq = o.char_coeffs(beta, delta, 12, q=q)
+    tb = o.char_coeffs_bessel(beta, delta, 12, q=q)
+    assert np.max(np.abs(tq - tb)) <= 1e-14 * math.exp(beta)
+
+
+@pytest.mark.parametrize("q", [3, 4])
+@pytest.mark.parametrize("beta,delta", [(0.5, 0.25), (1.0, 0.5), (1.5, 0.8)])
+def test_harmonic_q_closed_sums(q, beta, delta):
+    """w(0) = e^beta and w(pi) = e^{beta(-Delta + (1-Delta)(-1)^q)}."""
+    t = o.char_coeffs(beta, delta, 40, q=q)
+    n = np.arange(-40, 41)
+    tol = 1e-13 * math.exp(beta)
+    assert abs(t.sum() - math.exp(beta)) <= tol
+    wpi = math.exp(beta * (-delta + (1.0 - delta) * (-1.0) ** q))
+    assert abs(((-1.0) ** n * t).sum() - wpi) <= tol
+
+
+@pytest.mark.parametrize("q", [3, 4])
+def test_harmonic_q_delta_zero_is_bessel_of_n_over_q(q):
+    """At Delta = 0, w = exp(beta cos q phi): t_n = I_{n/q}(beta) if q | n, else 0."""
+    beta = 1.3
+    t = o.char_coeffs(beta, 0.0, 12, q=q)
+    n = np.arange(-12, 13)
+    on = n % q == 0
+    assert np.allclose(t[on], iv(n[on] // q, beta), rtol=1e-13, atol=1e-15 * math.exp(beta))
+    assert np.max(np.abs(t[~on])) <= 1e-15 * math.exp(beta)
+
+
+def test_harmonic_q_field_factors():
+    """Zero field: cos q theta impurity at |Q| = q; with fields: Fourier
+    coefficients of exp(bh cos th + bh1 cos q th) times 1, cos th, cos q th."""
+    for q in (3, 4):
+        F, FM, FM1 = o.field_factors(1.1, 0.0, 0.0, 8, q=q)
+        Q = np.arange(-8, 9)
+        assert np.array_equal(FM1, 0.5 * (np.abs(Q) == q))
+        beta, h, h1 = 1.1, 0.3, 0.2
+        F, FM, FM1 = o.field_factors(beta, h, h1, 6, q=q)
+        K = 256
+        th = 2 * np.pi * np.arange(K) / K
+        s = np.exp(beta * h * np.cos(th) + beta * h1 * np.cos(q * th))
+        for a, Qa in enumerate(range(-6, 7)):
+            assert F[a] == pytest.approx(np.mean(s * np.cos(Qa * th)), abs=1e-15)
+            assert FM[a] == pytest.approx(np.mean(np.cos(th) * s * np.cos(Qa * th)), abs=1e-15)
+            assert FM1[a] == pytest.approx(np.mean(np.cos(q * th) * s * np.cos(Qa * th)),
+                                           abs=1e-15)
+
+
+@pytest.mark.parametrize("q", [3, 4])
+@pytest.mark.parametrize("beta,delta,h,h1", [(0.9, 0.4, 0.0, 0.0), (1.0, 0.3, 0.0, 0.3),
+                                             (0.8, 0.5, 0.2, 0.15)])
+def test_harmonic_q_two_by_two_theta_quadrature(q, beta, delta, h, h1):
+    """Untruncated HOTRG on the 2x2 torus (U(1), Z_q and no-symmetry
+    sectors) = direct lattice integral with the cos q couplings."""
+    nmax = 3
+    t = o.char_coeffs(beta, delta, nmax, q=q)
+    r = o.run_point(beta, delta, h=h, h1=h1, nmax=nmax, dcut=10 ** 9, nsteps=2,
+                    impurities=3, q=q)
+    # K = 60 nodes: the trapezoid rule is exact up to degree K - 1, and the
+    # site weight's cos q theta series aliases at degree 16 + q l >= K only
+    # for orders l whose I_l(beta h1) are below 1e-16
+    K = 60
+    Z = theta_integral_2x2(t, beta, h, h1, K=K, q=q)
+    assert 4 * r.lnz_per_site == pytest.approx(math.log(Z), rel=0, abs=1e-13)
+    m1 = theta_integral_2x2(t, beta, h, h1, K=K, observable=np.cos, q=q) / Z
+    mq = theta_integral_2x2(t, beta, h, h1, K=K, observable=lambda a: np.cos(q * a), q=q) / Z
+    assert r.m_cos1 == pytest.approx(m1, abs=1e-13)
+    assert r.m_cos2 == pytest.approx(mq, abs=1e-13)
+
+
+def test_harmonic_q_sectors_do_not_change_truncated_runs():
+    """Z_q sectors (h = 0 != h1) against one dense block: the symmetry only
+    splits the eigensolves, so a truncated run gives the same ln Z/V."""
+    pt = dict(beta=1.0, delta=0.4, h1=0.2, nmax=3, dcut=9, nsteps=4, impurities=0)
+    T, _ = o.initial_tensors(pt["beta"], pt["delta"], 0.0, pt["h1"], pt["nmax"], q=3)
+    lab = o.leg_labels(pt["nmax"], o.SYM_Z2, 3)
+    zq = o.hotrg_run(T, {}, lab, lab, o.SYM_Z2, pt["dcut"], pt["nsteps"], q=3)
+    zero = np.zeros_like(lab)
+    dense = o.hotrg_run(T, {}, zero, zero, o.SYM_NONE, pt["dcut"], pt["nsteps"], q=3)
+    assert zq.lnz_per_site == pytest.approx(dense.lnz_per_site, abs=1e-12)
 
 
 def test_two_by_two_full_characters_tail():
