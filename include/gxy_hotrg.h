@@ -93,7 +93,7 @@ typedef struct {
   double beta;          /* inverse temperature, >= 0                         */
   double delta;         /* deformation, 0 <= delta <= 1 (J = delta, J1 = 1-delta) */
   double h;             /* field coupling to cos theta                       */
-  double h1;            /* field coupling to cos 2 theta                     */
+  double h1;            /* field coupling to cos q theta                     */
   int32_t nmax;         /* charges |n| <= nmax, initial bond D0 = 2 nmax + 1; 0..64 */
   int32_t dcut;         /* truncation bond dimension, 1..128                 */
   int32_t nsteps;       /* coarse-graining steps, 0..62 (lattice 2^nsteps sites) */
@@ -103,12 +103,17 @@ typedef struct {
   int32_t fp64_steps;   /* precision schedule: steps 1..fp64_steps contract in
                            FP64, later steps in prec (>= 0; step n enters
                            ln Z / N with weight 2^-n)                         */
+  int32_t q;            /* harmonic of the second coupling, (1 - delta)
+                           cos(q (theta_j - theta_k)) (Ch. 3, eq. gXY_ham;
+                           the thesis studies q = 2), of the field h1 and of
+                           the second impurity; 0 means 2; 2..16. At h = 0 !=
+                           h1 the sectors are charge mod q                   */
 } gxy_point;
 
 typedef struct {
   double lnz_per_site;  /* ln Z / 2^nsteps                                   */
   double m_cos1;        /* <cos theta>   (NaN if not requested)              */
-  double m_cos2;        /* <cos 2 theta> (NaN if not requested)              */
+  double m_cos2;        /* <cos q theta> (NaN if not requested)              */
   double max_trunc_err; /* max over steps of eps_chosen / trace(E)          */
   double min_cut_gap;   /* min over steps of (lam_D - lam_{D+1}) / lam_1     */
   int32_t near_ties;    /* number of tie-rule activations                   */

@@ -481,7 +481,11 @@ static void validate(const gxy_point &p) {
   if (p.prec != GXY_PREC_FP64 && p.prec != GXY_PREC_FP32 && p.prec != GXY_PREC_BF16X3)
     fail(GXY_EINVAL, "unknown contraction precision");
   if (p.fp64_steps < 0) fail(GXY_EINVAL, "fp64_steps must be >= 0");
+  if (p.q != 0 && (p.q < 2 || p.q > 16)) fail(GXY_EINVAL, "q must be 0 (= 2) or lie in [2, 16]");
 }
+
+// harmonic of the second coupling (0 selects the thesis's q = 2)
+static int harmonic(const gxy_point &p) { return p.q == 0 ? 2 : p.q; }
 
 static int sym_of(const gxy_point &p) {
   if (p.h == 0.0 && p.h1 == 0.0) return SYM_U1;
@@ -489,9 +493,10 @@ static int sym_of(const gxy_point &p) {
   return SYM_NONE;
 }
 
-static int fuse(int a, int b, int sym) {
+// labels fuse by addition (U(1)), by addition mod q (Z_q), or not at all
+static int fuse(int a, int b, int sym, int q) {
   if (sym == SYM_U1) return a + b;
-  if (sym == SYM_Z2) return (((a + b) % 2) + 2) % 2;
+  if (sym == SYM_Z2) return (((a + b) % q) + q) % q;
   return 0;
 }
 
@@ -668,11 +673,11 @@ struct Sectors {
   std::vector<int32_t> label, start, n, idx;
 };
 
-static Sectors make_sectors(const std::vector<int> &lh, int sym) {
+static Sectors make_sectors(const std::vector<int> &lh, int sym, int q) {
   const int Dh = (int)lh.size();
   std::map<int, std::vector<int32_t>> by;
   for (int a = 0; a < Dh; ++a)
-    for (int b = 0; b < Dh; ++b) by[fuse(lh[a], lh[b], sym)].push_back(a * Dh + b);
+    for (int b = 0; b < Dh; ++b) by[fuse(lh[a], lh[b], sym, q)].push_back(a * Dh + b);
   Sectors s;
   for (auto &kv : by) {
     s.label.push_back(kv.first);
@@ -995,8 +1000,9 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
   double *FM1 = FM + (2 * qmax + 1);
 
   tm.begin();
-  launch_char_coeffs(p.beta, p.delta, nmax, p.nquad, t, s);
-  launch_field_factors(p.beta, p.h, p.h1, qmax, kLmax, sym == SYM_U1, F, FM, FM1, s);
+  const int qh = harmonic(p);
+  launch_char_coeffs(p.beta, p.delta, qh, nmax, p.nquad, t, s);
+  launch_field_factors(p.beta, p.h, p.h1, qh, qmax, kLmax, sym == SYM_U1, F, FM, FM1, s);
   launch_init_tensor(t, F, nmax, b.T, s);
   int imp_which[2] = {0, 0};
   {
@@ -1019,22 +1025,23 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
   stream_after(ctx, si, s, 0);
   tm.end(0);
 
-  const int mod = (sym == SYM_U1) ? 0 : (sym == SYM_Z2 ? 2 : 1);
-  // allowed Q = q_l + q_d - q_r - q_u of each impurity tensor
+  const int mod = (sym == SYM_U1) ? 0 : (sym == SYM_Z2 ? qh : 1);
+  // allowed Q = q_l + q_d - q_r - q_u of each impurity tensor (cos theta
+  // carries charge +-1, cos q theta +-q; with Z_q labels these are mod q)
   QSet imp_set[2];
   for (int k = 0; k < nimp; ++k) {
     const bool cos1 = imp_which[k] == 1;
     if (sym == SYM_U1)
-      imp_set[k] = cos1 ? QSet{-1, 1} : QSet{-2, 2};
+      imp_set[k] = cos1 ? QSet{-1, 1} : QSet{-qh, qh};
     else if (sym == SYM_Z2)
-      imp_set[k] = cos1 ? QSet{1} : QSet{0};
+      imp_set[k] = cos1 ? qset_sum(QSet{1, -1}, QSet{0}, qh) : QSet{0};
     else
       imp_set[k] = QSet{0};
   }
   std::vector<int> lh(D0), lv(D0);
   for (int i = 0; i < D0; ++i) {
-    const int q = i - nmax;
-    lh[i] = lv[i] = (sym == SYM_U1) ? q : (sym == SYM_Z2 ? (((q % 2) + 2) % 2) : 0);
+    const int c = i - nmax;
+    lh[i] = lv[i] = (sym == SYM_U1) ? c : (sym == SYM_Z2 ? (((c % qh) + qh) % qh) : 0);
   }
   log.steps.clear();
   res.near_ties = 0;
@@ -1078,7 +1085,7 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
       launch_identity(b.P, (int)nf, s);
       new_lh.resize(nf);
       for (int a = 0; a < Dh; ++a)
-        for (int c = 0; c < Dh; ++c) new_lh[a * Dh + c] = fuse(lh[a], lh[c], sym);
+        for (int c = 0; c < Dh; ++c) new_lh[a * Dh + c] = fuse(lh[a], lh[c], sym, qh);
       info.truncated = 0;
     } else {
       // ---- environments ----
@@ -1103,7 +1110,7 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
       tm.end(1);
       // ---- sectors and eigensolver tables ----
       tm.begin();
-      const Sectors sec = make_sectors(lh, sym);
+      const Sectors sec = make_sectors(lh, sym, qh);
       const int nsec = (int)sec.label.size();
       EigMem em{b.eigA, b.eigV, b.eigQ, b.eig_scale, b.eig_flags, b.ints, b.ints_cap,
                 b.eig_elems, b.eig_q, b.eigB1, b.eigB2, b.gtab, b.ggrp, b.gtab_cap,
@@ -1419,8 +1426,9 @@ static void initial_tensor_only(gxy_ctx *ctx, const gxy_point &p, int which, dou
   double *T = (double *)ctx->ws;
   double *t = T + n4;
   double *F = t + D0, *FM = F + (2 * qmax + 1), *FM1 = FM + (2 * qmax + 1);
-  launch_char_coeffs(p.beta, p.delta, p.nmax, p.nquad, t, s);
-  launch_field_factors(p.beta, p.h, p.h1, qmax, kLmax, sym_of(p) == SYM_U1, F, FM, FM1, s);
+  launch_char_coeffs(p.beta, p.delta, harmonic(p), p.nmax, p.nquad, t, s);
+  launch_field_factors(p.beta, p.h, p.h1, harmonic(p), qmax, kLmax, sym_of(p) == SYM_U1, F, FM,
+                       FM1, s);
   launch_init_tensor(t, which == 0 ? F : (which == 1 ? FM : FM1), p.nmax, T, s);
   GXY_HIP(hipMemcpyAsync(out, T, n4 * sizeof(double), hipMemcpyDeviceToHost, s));
   GXY_HIP(hipStreamSynchronize(s));
@@ -1527,7 +1535,7 @@ gxy_status gxy_char_coeffs(gxy_ctx *ctx, double beta, double delta, int32_t nmax
   GXY_HIP(hipSetDevice(ctx->device));
   gxy::ensure_workspace(ctx, sizeof(double) * (2 * nmax + 1) + 256);
   double *d = (double *)ctx->ws;
-  gxy::launch_char_coeffs(beta, delta, nmax, nquad, d, ctx->stream);
+  gxy::launch_char_coeffs(beta, delta, 2, nmax, nquad, d, ctx->stream);
   GXY_HIP(hipMemcpyAsync(t, d, sizeof(double) * (2 * nmax + 1), hipMemcpyDeviceToHost,
                          ctx->stream));
   GXY_HIP(hipStreamSynchronize(ctx->stream));

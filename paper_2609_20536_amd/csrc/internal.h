@@ -119,11 +119,12 @@ void launch_mfma_probe32(int kind, const float *a, const float *b, float *out,
 // coefficients and initial tensors (FP64)
 // --------------------------------------------------------------------------
 
-// t[0..2nmax] for n = -nmax..nmax.
-void launch_char_coeffs(double beta, double delta, int nmax, int nquad,
+// t[0..2nmax] for n = -nmax..nmax; q = harmonic of the second coupling.
+void launch_char_coeffs(double beta, double delta, int q, int nmax, int nquad,
                         double *t, hipStream_t s);
-// F, FM, FM1 for Q in [-qmax, qmax]; zero_field selects the exact deltas.
-void launch_field_factors(double beta, double h, double h1, int qmax,
+// F, FM, FM1 for Q in [-qmax, qmax] (h1 couples to cos q theta, FM1 is the
+// cos q theta impurity); zero_field selects the exact deltas.
+void launch_field_factors(double beta, double h, double h1, int q, int qmax,
                           int lmax, bool zero_field, double *F, double *FM,
                           double *FM1, hipStream_t s);
 // T[l][r][u][d] = sqrt(t_l t_r t_u t_d) * F(n_u + n_r - n_d - n_l).

@@ -1,14 +1,15 @@
 // Character coefficients, field factors and initial site tensors (FP64).
 //
 // t_n = (1/Q) sum_k w(phi_k) cos(n phi_k), phi_k = 2 pi k / Q, with
-// w(phi) = exp(beta [Delta cos phi + (1 - Delta) cos 2 phi]): the character
+// w(phi) = exp(beta [Delta cos phi + (1 - Delta) cos q phi]): the character
 // coefficient a_n(beta, Delta) of Ch. 3 (eq. a_n) written as the Fourier
 // integral of the bond weight and evaluated by the periodic trapezoid rule.
-// Site tensor (Ch. 3, final site-tensor equation):
+// The Hamiltonian (Ch. 3, eq. gXY_ham) has a general harmonic q; the thesis
+// takes q = 2. Site tensor (Ch. 3, final site-tensor equation):
 //   T[l][r][u][d] = sqrt(t_l t_r t_u t_d) * F(n_u + n_r - n_d - n_l),
-//   F(Q) = sum_l I_{Q+2l}(beta h) I_l(beta h1),
-// and the impurity tensors with F_M, F_M1 (Ch. 3, the two impure-tensor
-// equations).
+//   F(Q) = sum_l I_{Q+ql}(beta h) I_l(beta h1)   (h1 couples to cos q theta),
+// and the impurity tensors with F_M (cos theta), F_M1 (cos q theta) (Ch. 3,
+// the two impure-tensor equations).
 #include "internal.h"
 
 namespace gxy {
@@ -17,14 +18,14 @@ namespace {
 
 constexpr int kCoeffThreads = 256;
 
-__global__ void char_coeffs_kernel(double beta, double delta, int nmax,
+__global__ void char_coeffs_kernel(double beta, double delta, int q, int nmax,
                                    int nquad, double *t) {
   __shared__ double red[kCoeffThreads];
   const int n = blockIdx.x;  // 0..nmax
   double acc = 0.0;
   for (int k = threadIdx.x; k < nquad; k += kCoeffThreads) {
     double phi = 2.0 * M_PI * (double)k / (double)nquad;
-    double w = exp(beta * (delta * cos(phi) + (1.0 - delta) * cos(2.0 * phi)));
+    double w = exp(beta * (delta * cos(phi) + (1.0 - delta) * cos((double)q * phi)));
     acc += w * cos((double)n * phi);
   }
   red[threadIdx.x] = acc;
@@ -57,7 +58,7 @@ __device__ double bessel_i(int k, double x) {
   return total;
 }
 
-__global__ void field_factors_kernel(double beta, double h, double h1, int qmax,
+__global__ void field_factors_kernel(double beta, double h, double h1, int q, int qmax,
                                      int lmax, int zero_field, double *F,
                                      double *FM, double *FM1) {
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
@@ -66,16 +67,16 @@ __global__ void field_factors_kernel(double beta, double h, double h1, int qmax,
   if (zero_field) {
     F[a] = Q == 0 ? 1.0 : 0.0;
     FM[a] = (Q == 1 || Q == -1) ? 0.5 : 0.0;
-    FM1[a] = (Q == 2 || Q == -2) ? 0.5 : 0.0;
+    FM1[a] = (Q == q || Q == -q) ? 0.5 : 0.0;
     return;
   }
   const double x = beta * h, x1 = beta * h1;
   double f = 0.0, fm = 0.0, fm1 = 0.0;
   for (int l = -lmax; l <= lmax; ++l) {
     const double il1 = bessel_i(l, x1);
-    const double iq = bessel_i(Q + 2 * l, x);
+    const double iq = bessel_i(Q + q * l, x);
     f += iq * il1;
-    fm += il1 * 0.5 * (bessel_i(Q + 2 * l - 1, x) + bessel_i(Q + 2 * l + 1, x));
+    fm += il1 * 0.5 * (bessel_i(Q + q * l - 1, x) + bessel_i(Q + q * l + 1, x));
     fm1 += iq * 0.5 * (bessel_i(l + 1, x1) + bessel_i(l - 1, x1));
   }
   F[a] = f;
@@ -101,19 +102,19 @@ __global__ void init_tensor_kernel(const double *t, const double *F, int nmax,
 
 }  // namespace
 
-void launch_char_coeffs(double beta, double delta, int nmax, int nquad,
+void launch_char_coeffs(double beta, double delta, int q, int nmax, int nquad,
                         double *t, hipStream_t s) {
   hipLaunchKernelGGL(char_coeffs_kernel, dim3(nmax + 1), dim3(kCoeffThreads), 0,
-                     s, beta, delta, nmax, nquad, t);
+                     s, beta, delta, q, nmax, nquad, t);
   GXY_CHECK_LAUNCH();
 }
 
-void launch_field_factors(double beta, double h, double h1, int qmax, int lmax,
+void launch_field_factors(double beta, double h, double h1, int q, int qmax, int lmax,
                           bool zero_field, double *F, double *FM, double *FM1,
                           hipStream_t s) {
   const int n = 2 * qmax + 1;
   hipLaunchKernelGGL(field_factors_kernel, dim3((n + 63) / 64), dim3(64), 0, s,
-                     beta, h, h1, qmax, lmax, zero_field ? 1 : 0, F, FM, FM1);
+                     beta, h, h1, q, qmax, lmax, zero_field ? 1 : 0, F, FM, FM1);
   GXY_CHECK_LAUNCH();
 }
 

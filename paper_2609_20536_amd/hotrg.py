@@ -32,7 +32,7 @@ class Point(C.Structure):
                 ("h1", C.c_double), ("nmax", C.c_int32), ("dcut", C.c_int32),
                 ("nsteps", C.c_int32), ("nquad", C.c_int32),
                 ("impurities", C.c_uint32), ("prec", C.c_int32),
-                ("fp64_steps", C.c_int32)]
+                ("fp64_steps", C.c_int32), ("q", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -131,9 +131,10 @@ def load_library(path: str = LIB_PATH):
 
 
 def make_point(beta, delta, h=0.0, h1=0.0, nmax=3, dcut=12, nsteps=30, nquad=4096,
-               impurities=3, prec=0, fp64_steps=0, **_ignored) -> Point:
+               impurities=3, prec=0, fp64_steps=0, q=2, **_ignored) -> Point:
     return Point(float(beta), float(delta), float(h), float(h1), int(nmax), int(dcut),
-                 int(nsteps), int(nquad), int(impurities), int(prec), int(fp64_steps))
+                 int(nsteps), int(nquad), int(impurities), int(prec), int(fp64_steps),
+                 int(q))
 
 
 def point_from(obj) -> Point:

@@ -50,6 +50,7 @@ class Point:
     impurities: int = IMP_COS1 | IMP_COS2
     prec: int = PREC_FP64
     fp64_steps: int = 0
+    q: int = 2
 
     def as_dict(self):
         return asdict(self)

@@ -285,3 +285,17 @@ def test_initial_tensors_match_oracle(ctx, h, h1, which):
     assert np.max(np.abs(Tg - ref)) <= 1e-15 * max(1.0, np.max(np.abs(ref)))
     if h == 0.0 and h1 == 0.0:
         assert np.array_equal(Tg == 0.0, ref == 0.0)   # exact charge structure
+
+
+@pytest.mark.parametrize("q", [3, 5])
+@pytest.mark.parametrize("h,h1", [(0.0, 0.0), (0.0, 0.3), (0.3, 0.2)])
+@pytest.mark.parametrize("which", [0, 1, 2])
+def test_initial_tensors_harmonic_q_match_oracle(ctx, q, h, h1, which):
+    nmax = 4
+    Tg = ctx.initial_tensor(dict(beta=1.1, delta=0.6, h=h, h1=h1, nmax=nmax, dcut=8,
+                                 nsteps=0, q=q), which)
+    T, imps = o.initial_tensors(1.1, 0.6, h, h1, nmax, impurities=3, q=q)
+    ref = T if which == 0 else imps[which]
+    assert np.max(np.abs(Tg - ref)) <= 1e-15 * max(1.0, np.max(np.abs(ref)))
+    if h == 0.0 and h1 == 0.0:
+        assert np.array_equal(Tg == 0.0, ref == 0.0)

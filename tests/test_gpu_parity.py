@@ -113,6 +113,33 @@ def test_run_with_block_jacobi_matches_oracle(ctx, pt, monkeypatch):
     _compare(ctx.run(pt), o.run_point(**pt))
 
 
+# harmonic q of the second coupling (Ch. 3, eq. gXY_ham with q >= 3): U(1)
+# sectors at zero field, Z_q sectors at h = 0 != h1, one block with h != 0.
+# The points avoid cuts through near-degenerate pairs (no cut gap between
+# 1e-13 and 1e-8 in the oracle's runs), where the kept direction, and so
+# ln Z/V to about 1e-9, is fixed only by eigensolver rounding.
+HARMONIC = [
+    dict(beta=1.1, delta=0.4, nmax=4, dcut=14, nsteps=10, impurities=3, q=3),
+    dict(beta=1.0, delta=0.3, nmax=3, dcut=12, nsteps=8, h1=0.2, impurities=3, q=3),
+    dict(beta=1.2, delta=0.6, nmax=5, dcut=16, nsteps=12, impurities=3, q=4),
+    dict(beta=0.8, delta=0.3, nmax=3, dcut=13, nsteps=8, h1=0.3, impurities=3, q=4),
+    dict(beta=0.8, delta=0.6, nmax=3, dcut=13, nsteps=8, h=0.1, h1=0.2, impurities=3, q=3),
+    dict(beta=1.3, delta=0.1, nmax=6, dcut=18, nsteps=10, impurities=3, q=6),
+]
+
+
+@pytest.mark.parametrize("pt", HARMONIC, ids=lambda p: ",".join(f"{k}={v}" for k, v in p.items()))
+def test_harmonic_q_runs_match_oracle(ctx, pt):
+    _compare(ctx.run(pt), o.run_point(**pt))
+
+
+def test_harmonic_q_two_is_the_default(ctx):
+    """q = 0 selects q = 2, bit for bit."""
+    p = dict(beta=1.0, delta=0.45, nmax=4, dcut=13, nsteps=10, h1=0.1, impurities=3)
+    a, b = ctx.run(dict(p, q=0)), ctx.run(dict(p, q=2))
+    assert a.lnz_per_site == b.lnz_per_site and a.m_cos2 == b.m_cos2
+
+
 @pytest.mark.parametrize("nsteps,nmax", [(0, 3), (1, 3), (2, 3), (3, 1)])
 @pytest.mark.parametrize("h,h1", [(0.0, 0.0), (0.3, 0.2)])
 def test_untruncated_tiny_tori(ctx, nsteps, nmax, h, h1):
@@ -153,7 +180,8 @@ def test_invalid_arguments_are_rejected(ctx):
     from paper_2609_20536_amd import hotrg as H
     for bad in (dict(beta=-1.0, delta=0.5), dict(beta=1.0, delta=1.5),
                 dict(beta=1.0, delta=0.5, dcut=0), dict(beta=1.0, delta=0.5, nquad=4, nmax=3),
-                dict(beta=1.0, delta=0.5, nsteps=-1)):
+                dict(beta=1.0, delta=0.5, nsteps=-1), dict(beta=1.0, delta=0.5, q=1),
+        dict(beta=1.0, delta=0.5, q=17)):
         with pytest.raises(H.GxyError) as e:
             ctx.run(bad)
         assert e.value.status == 1

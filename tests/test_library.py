@@ -57,3 +57,31 @@ def test_binding_fails_loudly_without_library(tmp_path):
         hotrg._lib = None
         hotrg.load_library(str(tmp_path / "missing.so"))
     hotrg._lib = None
+
+
+@pytest.mark.skipif(__import__("shutil").which("gcc") is None, reason="gcc not available")
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Size and every field offset of gxy_point, gxy_result and
+    gxy_step_info as a C compiler lays them out from the header, against the
+    ctypes structures of the binding."""
+    import subprocess
+    from paper_2609_20536_amd import hotrg as H
+    structs = {"gxy_point": H.Point, "gxy_result": H.Result, "gxy_step_info": H.StepInfo}
+    src = ["#include <stdio.h>", "#include <stddef.h>", '#include "gxy_hotrg.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        src.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            src.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    src += ["  return 0;", "}"]
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src) + "\n")
+    exe = tmp_path / "layout"
+    r = subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(c), "-o",
+                        str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-3000:]
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {tuple(line.split()[:2]): int(line.split()[2]) for line in out if line}
+    for cname, cls in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
