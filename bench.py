@@ -94,6 +94,22 @@ def precision_leg(ctx, pt, r64):
     return out
 
 
+def harmonic_leg(ctx, pt):
+    """The bench workload with the second coupling's harmonic q = 3 and 4
+    (cos q phi, h1 and the second impurity on cos q theta): steps/s of one
+    FP64 run each, with ln Z/V and <cos theta> for reference."""
+    out = {}
+    for q in (3, 4):
+        p = pt.with_(q=q)
+        ctx.run(p)
+        t0 = time.perf_counter()
+        r = ctx.run(p)
+        el = time.perf_counter() - t0
+        out[f"q{q}"] = {"steps_per_s": p.nsteps / el, "lnz_per_site": r.lnz_per_site,
+                        "max_trunc_err": r.max_trunc_err}
+    return out
+
+
 def batched_leg(ctx, note):
     """Points/s of f and C_v over a stratified grid subset, one batch."""
     from paper_2609_20536_amd import workloads as W
@@ -197,6 +213,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-harmonic", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="one plain 1 GiB device copy first (known HBM bytes for counter scaling)")
     ap.add_argument("--phases", action="store_true", help="one extra untimed run with phase timers")
@@ -299,6 +316,9 @@ def main():
     if not args.no_precision:
         line["precision"] = precision_leg(ctx, pt, r)
         note("bench: precision leg done")
+    if not args.no_harmonic:
+        line["harmonic"] = harmonic_leg(ctx, pt)
+        note("bench: harmonic-q leg done")
     if not args.no_batched:
         line["batched"] = batched_leg(ctx, note)
     if not args.no_cpu_baseline:
