@@ -38,10 +38,10 @@ def _small_pins():
     ]
 
 
-def _wrong_orientation(beta, delta, h, h1, nmax, nquad=4096, impurities=0):
-    t = o.char_coeffs(beta, delta, nmax, nquad)
+def _wrong_orientation(beta, delta, h, h1, nmax, nquad=4096, impurities=0, q=2):
+    t = o.char_coeffs(beta, delta, nmax, nquad, q)
     n = np.arange(-nmax, nmax + 1)
-    F, FM, FM1 = o.field_factors(beta, h, h1, 4 * nmax)
+    F, FM, FM1 = o.field_factors(beta, h, h1, 4 * nmax, q=q)
     l, r, u, d = np.meshgrid(n, n, n, n, indexing="ij")
     Q = u + d - r - l                      # mistake: l + r = u + d
     amp = np.sqrt(t[l + nmax] * t[r + nmax] * t[u + nmax] * t[d + nmax])
@@ -53,8 +53,8 @@ def _wrong_orientation(beta, delta, h, h1, nmax, nquad=4096, impurities=0):
     return amp * F[Q + 4 * nmax], imps
 
 
-def _no_sqrt(beta, delta, h, h1, nmax, nquad=4096, impurities=0):
-    T, imps = _orig_initial(beta, delta, h, h1, nmax, nquad, impurities)
+def _no_sqrt(beta, delta, h, h1, nmax, nquad=4096, impurities=0, q=2):
+    T, imps = _orig_initial(beta, delta, h, h1, nmax, nquad, impurities, q)
     return T * T, {k: v * v for k, v in imps.items()}   # mistake: prod t, not sqrt
 
 
@@ -120,3 +120,39 @@ def test_impurity_half_factor_is_caught(monkeypatch):
         lambda: pins.test_two_by_two_theta_quadrature(0.9, 0.6, 0.25, 0.0),
         lambda: pins.test_four_by_two_brute_force("y", 0.3, 0.2),
     ])
+
+
+_orig_cc = o.char_coeffs
+_orig_ff = o.field_factors
+_orig_ll = o.leg_labels
+_orig_fl = o.fuse_labels
+
+HARMONIC_MUTATIONS = {
+    # mistake: the second coupling stays cos 2 phi whatever q is
+    "coupling_harmonic_fixed": ("char_coeffs",
+                                lambda beta, delta, nmax, nquad=4096, q=2:
+                                _orig_cc(beta, delta, nmax, nquad, 2)),
+    # mistake: h1 and the second impurity stay on cos 2 theta
+    "field_harmonic_fixed": ("field_factors",
+                             lambda beta, h, h1, qmax, lmax=50, q=2:
+                             _orig_ff(beta, h, h1, qmax, lmax, 2)),
+    # mistake: Z2 parities instead of charge mod q
+    "sector_labels_mod_2": ("leg_labels", lambda nmax, sym, q=2: _orig_ll(nmax, sym, 2)),
+}
+
+
+def _harmonic_pins():
+    return [
+        lambda: pins.test_harmonic_q_quadrature_equals_bessel_series(3, 1.2, 0.7),
+        lambda: pins.test_harmonic_q_closed_sums(3, 1.0, 0.5),
+        pins.test_harmonic_q_field_factors,
+        lambda: pins.test_harmonic_q_two_by_two_theta_quadrature(3, 1.0, 0.3, 0.0, 0.3),
+        pins.test_harmonic_q_sectors_do_not_change_truncated_runs,
+    ]
+
+
+@pytest.mark.parametrize("name", sorted(HARMONIC_MUTATIONS))
+def test_harmonic_mutation_is_caught(name, monkeypatch):
+    attr, fn = HARMONIC_MUTATIONS[name]
+    monkeypatch.setattr(o, attr, fn)
+    _expect_some_pin_fails(_harmonic_pins())
