@@ -110,6 +110,23 @@ def harmonic_leg(ctx, pt):
     return out
 
 
+def transition_leg(ctx):
+    """The zero-field extrapolation of the transition temperature at
+    Delta = 0.32 (field h1): susceptibility scans at four central fields
+    and the C_v scan, Dcut = 24, |n| <= 10, 40 steps, in batches of 16."""
+    from paper_2609_20536_amd import transition as T
+    temps = [0.62 + 0.03 * i for i in range(13)]
+    hbars = [0.001, 0.002, 0.004, 0.008]
+    t0 = time.perf_counter()
+    tr = T.transition_temperature(ctx, 0.32, temps, hbars, dcut=24, nmax=10, nsteps=40,
+                                  workers=16)
+    el = time.perf_counter() - t0
+    runs = len(temps) * (2 * len(hbars) + 3)
+    return {"delta": 0.32, "dcut": 24, "field": tr.field, "runs": runs, "seconds": el,
+            "runs_per_s": runs / el, "hbars": hbars, "tpeaks": tr.tpeaks,
+            "fit": {"a": tr.a, "b": tr.b, "c": tr.c, "rms": tr.rms}, "t_cv": tr.t_cv}
+
+
 def batched_leg(ctx, note):
     """Points/s of f and C_v over a stratified grid subset, one batch."""
     from paper_2609_20536_amd import workloads as W
@@ -214,6 +231,7 @@ def main():
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-harmonic", action="store_true")
+    ap.add_argument("--no-transition", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="one plain 1 GiB device copy first (known HBM bytes for counter scaling)")
     ap.add_argument("--phases", action="store_true", help="one extra untimed run with phase timers")
@@ -319,6 +337,9 @@ def main():
     if not args.no_harmonic:
         line["harmonic"] = harmonic_leg(ctx, pt)
         note("bench: harmonic-q leg done")
+    if not args.no_transition:
+        line["transition"] = transition_leg(ctx)
+        note("bench: transition leg done")
     if not args.no_batched:
         line["batched"] = batched_leg(ctx, note)
     if not args.no_cpu_baseline:
