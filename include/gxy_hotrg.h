@@ -69,7 +69,7 @@ typedef enum {
   GXY_EDEVICE = 3,       /* a HIP runtime call failed                       */
   GXY_ENUMERIC = 4,      /* non-finite or non-positive trace, no eigen
                             convergence                                      */
-  GXY_EUNSUPPORTED = 5,  /* valid request this build does not implement     */
+  GXY_EUNSUPPORTED = 5,  /* valid request the library does not implement    */
   GXY_EPARTIAL = 6       /* batch: at least one run failed (see per-run)    */
 } gxy_status;
 
