@@ -35,6 +35,8 @@ def _mixed_points():
         base.with_(dcut=20, nmax=10, nsteps=6, prec=W.PREC_BF16X3, fp64_steps=2),
         base.with_(dcut=1, nsteps=5),
         base.with_(beta=0.7, dcut=12, nsteps=20, impurities=0),
+        base.with_(dcut=14, nmax=4, nsteps=10, q=3),
+        base.with_(dcut=12, h1=0.2, nsteps=8, q=4),
     ]
 
 

@@ -133,6 +133,16 @@ def test_harmonic_q_runs_match_oracle(ctx, pt):
     _compare(ctx.run(pt), o.run_point(**pt))
 
 
+def test_harmonic_q_bench_size_is_deterministic(ctx):
+    """The bench workload (Dcut = 64, |n| <= 10, 40 steps, both chains) at
+    q = 3: finite, truncation error in range, the same bits twice."""
+    p = W.precision_point(64).with_(q=3)
+    a, b = ctx.run(p), ctx.run(p)
+    assert a.status == 0 and math.isfinite(a.lnz_per_site) and 0.0 <= a.max_trunc_err < 1.0
+    assert a.lnz_per_site == b.lnz_per_site and a.m_cos1 == b.m_cos1 and a.m_cos2 == b.m_cos2
+    assert a.m_cos1 == 0.0 and a.m_cos2 == 0.0      # zero field: exact by symmetry
+
+
 def test_harmonic_q_two_is_the_default(ctx):
     """q = 0 selects q = 2, bit for bit."""
     p = dict(beta=1.0, delta=0.45, nmax=4, dcut=13, nsteps=10, h1=0.1, impurities=3)
