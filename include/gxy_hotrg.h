@@ -152,7 +152,9 @@ gxy_status gxy_set_workspace(gxy_ctx *ctx, void *dev_ptr, size_t bytes);
 
 /* Character coefficients t_n, n = -nmax..nmax (Ch. 3, eq. a_n as the
  * Fourier integral of the bond weight), computed on the device by the
- * nquad-point trapezoid rule; t is a host array of 2 nmax + 1 doubles. */
+ * nquad-point trapezoid rule; t is a host array of 2 nmax + 1 doubles. This
+ * entry point takes the thesis's q = 2; runs with another harmonic compute
+ * theirs from gxy_point.q (gxy_initial_tensor shows the resulting tensor). */
 gxy_status gxy_char_coeffs(gxy_ctx *ctx, double beta, double delta,
                            int32_t nmax, int32_t nquad, double *t);
 
