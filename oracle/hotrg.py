@@ -339,6 +339,7 @@ class Selection:
     lam_max: float
     cut_gap: float
     ties: int
+    sector_gap: float = math.inf   # smallest within-sector gap at the cut
 
 
 def select_states(secL: List[Sector], secR: List[Sector], dcut: int,
@@ -365,12 +366,22 @@ def select_states(secL: List[Sector], secR: List[Sector], dcut: int,
                   for k, lam in enumerate(s.lam) if (si, k) not in kept]
         # cut gap: smallest kept minus largest discarded eigenvalue
         gap = (min(kept_l) - max(disc_l)) / lam1 if lam1 > 0 else 0.0
-        res[side] = (picks, eps, lam1, gap, ties)
+        # the same within each sector that has both kept and discarded
+        # states (a diagnostic: a small value means the kept directions of
+        # that sector are fixed only to eps ||E|| / gap; a small cut gap
+        # between different sectors is settled exactly by the tie rule)
+        sgap = math.inf
+        for si, s in enumerate(secs):
+            kin = [float(lam) for k, lam in enumerate(s.lam) if (si, k) in kept]
+            kout = [float(lam) for k, lam in enumerate(s.lam) if (si, k) not in kept]
+            if kin and kout and lam1 > 0:
+                sgap = min(sgap, (min(kin) - max(kout)) / lam1)
+        res[side] = (picks, eps, lam1, gap, ties, sgap)
     epsL, epsR = res[0][1], res[1][1]
     lam_max = max(res[0][2], res[1][2])
     side = 1 if epsR < epsL - SIDE_TOL * lam_max else 0
     secs = secL if side == 0 else secR
-    picks, _, _, gap, ties = res[side]
+    picks, _, _, gap, ties, sgap = res[side]
     picks = sorted(picks, key=lambda p: (secs[p[0]].label, p[1]))
     P = np.zeros((nfused, dcut))
     labels = np.zeros(dcut, dtype=np.int64)
@@ -378,7 +389,7 @@ def select_states(secL: List[Sector], secR: List[Sector], dcut: int,
         s = secs[si]
         P[s.index, j] = s.vec[:, k]
         labels[j] = s.label
-    return Selection(P, labels, epsL, epsR, side, lam_max, gap, ties)
+    return Selection(P, labels, epsL, epsR, side, lam_max, gap, ties, sgap)
 
 
 def project(P: np.ndarray, A: np.ndarray, B: np.ndarray) -> np.ndarray:
@@ -418,6 +429,7 @@ class StepLog:
     cut_gap: float
     ties: int
     truncated: bool
+    sector_gap: float = math.inf
 
 
 @dataclass
@@ -497,7 +509,7 @@ def hotrg_run(T: np.ndarray, imps: Dict[int, np.ndarray], lab_h: np.ndarray,
             lab_h, lab_v = lab_v, lab_h
         logs.append(StepLog(math.log(c), sel.eps_l, sel.eps_r, sel.side,
                             T.shape[0], T.shape[2], sel.lam_max, sel.cut_gap,
-                            sel.ties, truncated))
+                            sel.ties, truncated, sel.sector_gap))
     Dh, Dv = T.shape[0], T.shape[2]
     tr = float(np.einsum("llUU->", T)) if Dh and Dv else 0.0
     if not (tr > 0.0) or not math.isfinite(tr):

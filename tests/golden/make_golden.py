@@ -9,12 +9,15 @@ Jobs whose oracle run takes minutes to hours (Dcut >= 48 at 40 steps) are
 computed once with this script and stored.
 
     python tests/golden/make_golden.py <job> [<job> ...]
+    python tests/golden/make_golden.py --sector-gaps <job> ...   (re-run, add gaps)
+    python tests/golden/make_golden.py --spread <job> ...        (also the spread)
     python tests/golden/make_golden.py --list
 """
 
 from __future__ import annotations
 
 import json
+import math
 import os
 import sys
 import time
@@ -56,6 +59,9 @@ def jobs():
                                         dcut=64, nsteps=40, impurities=0)
     j["prec_d64_chains_n12"] = _pt(beta=1.2, delta=0.7, nmax=10, dcut=64, nsteps=12, impurities=3)
     j["prec_d96_first3"] = _pt(beta=1.2, delta=0.7, nmax=10, dcut=96, nsteps=3, impurities=0)
+    # Dcut = 96 over 20 steps (the dense oracle takes about 8 minutes per
+    # square step here, so the 40-step run is out of reach on this host)
+    j["prec_d96_pure_n20"] = _pt(beta=1.2, delta=0.7, nmax=10, dcut=96, nsteps=20, impurities=0)
     # grid subset: two points per Dcut class, pure, 40 steps
     gp = W.grid_points()
     by = {}
@@ -68,13 +74,18 @@ def jobs():
     return j
 
 
-def spread_of(pt, runs=2):
+def _sector_gaps(r):
+    return [s.sector_gap if math.isfinite(s.sector_gap) else None for s in r.steps]
+
+
+def spread_of(pt, runs=2, base=None):
     """Largest |d ln Z/V| and |d m| of the oracle between its default run and
     runs whose sector eigensolves use a random orthogonal basis (an equally
     valid FP64 backward-stable eigensolve with a different rounding pattern).
-    Where near-degenerate eigenvalues straddle the cut, the kept vectors -- and
-    so the run -- are fixed by the FP64 eigensolve only to this level."""
-    base = o.run_point(**pt)
+    Where near-degenerate eigenvalues of one sector straddle the cut, the kept
+    vectors -- and so the run -- are fixed by the FP64 eigensolve only to this
+    level."""
+    base = base or o.run_point(**pt)
     sp, spm = 0.0, 0.0
     for seed in range(1, runs + 1):
         r = o.run_point(**pt, basis_seed=seed)
@@ -85,15 +96,26 @@ def spread_of(pt, runs=2):
     return sp, spm
 
 
-def add_spread(name):
+def annotate(name, spread_runs=0):
+    """Re-run a stored job with the current oracle and add the per-step
+    within-sector cut gaps (and, with spread_runs > 0, the spread over
+    equally valid eigensolves). The re-run must reproduce the stored
+    ln Z/V; the stored values are kept."""
     path = os.path.join(HERE, name + ".json")
     gd = json.load(open(path))
-    sp, spm = spread_of(gd["point"])
-    gd["spread"] = sp
-    gd["spread_m"] = spm
+    base = o.run_point(**gd["point"])
+    d = abs(base.lnz_per_site - gd["lnz_per_site"])
+    bound = max(1e-12, 10 * gd.get("spread", 0.0))
+    if d > bound:
+        raise SystemExit(f"{name}: re-run differs from the stored ln Z/V by {d:.2e}")
+    gd["sector_gap"] = _sector_gaps(base)
+    if spread_runs > 0:
+        sp, spm = spread_of(gd["point"], spread_runs, base)
+        gd["spread"] = max(sp, d)
+        gd["spread_m"] = spm
     with open(path, "w") as f:
         json.dump(gd, f, indent=1)
-    return sp
+    return gd.get("spread")
 
 
 def run_job(name, pt):
@@ -113,6 +135,10 @@ def run_job(name, pt):
         "cut_gap": [s.cut_gap for s in r.steps],
         "lam_max": [s.lam_max for s in r.steps],
         "ties": [s.ties for s in r.steps],
+        # smallest gap at the cut within one symmetry sector (null: no
+        # sector was split by the cut)
+        "sector_gap": [s.sector_gap if math.isfinite(s.sector_gap) else None
+                       for s in r.steps],
         "oracle_seconds": time.time() - t0,
         "writer": "tests/golden/make_golden.py (CPU oracle only)",
     }
@@ -127,9 +153,12 @@ if __name__ == "__main__":
         for k, v in J.items():
             print(k, v)
         sys.exit(0)
-    if sys.argv[1] == "--spread":
+    if sys.argv[1] in ("--spread", "--spread1", "--sector-gaps"):
+        # --sector-gaps: add the within-sector cut gaps; --spread: also the
+        # spread over two re-rotated eigensolves (--spread1: over one)
+        runs = {"--spread": 2, "--spread1": 1}.get(sys.argv[1], 0)
         for name in sys.argv[2:]:
-            print(name, "spread", add_spread(name), flush=True)
+            print(name, "spread", annotate(name, runs), flush=True)
         sys.exit(0)
     for name in sys.argv[1:]:
         r = run_job(name, J[name])
