@@ -186,6 +186,29 @@ gxy_status gxy_run(gxy_ctx *ctx, const gxy_point *pt, gxy_result *out);
 gxy_status gxy_run_batch(gxy_ctx *ctx, const gxy_point *pts, int32_t n,
                          gxy_result *out);
 
+/* Size of the device scratch array behind gxy_run_noalloc (bytes). */
+#define GXY_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+
+/* gxy_run for callers that cannot allocate device memory (code under HIP
+ * graph capture of the surrounding work, tight serving loops, harnesses
+ * that forbid hipMalloc): the same run and the same results as gxy_run,
+ * with every device buffer carved from one file-scope scratch array of
+ * GXY_NOALLOC_SCRATCH_BYTES that the library holds on each device it runs
+ * on until the process ends. The call makes no HIP allocation (no hipMalloc,
+ * hipFree, pinned host memory, stream or event creation) and no torch
+ * allocation; its host-side planning uses the C++ heap. Work runs on the
+ * context's stream only (no side streams, one workgroup per eigensolver
+ * sector) and the call returns when the run is done.
+ * Limits and errors: a run whose workspace does not fit the array, even with
+ * the projection split into the smallest chunks, returns GXY_EINVAL before
+ * any device work (the last error names both sizes); other statuses as for
+ * gxy_run. The array keeps the last call's contents; every buffer a run reads
+ * is written by that run first. All calls on one device share that device's
+ * array: calls that overlap in time on one device (two host threads, or two
+ * contexts) race and must not be issued. The context's own workspace
+ * (gxy_set_workspace or library-owned) is neither used nor changed. */
+gxy_status gxy_run_noalloc(gxy_ctx *ctx, const gxy_point *pt, gxy_result *out);
+
 /* Number of worker contexts gxy_run_batch uses (0 = default, at most 64). */
 gxy_status gxy_set_batch_workers(gxy_ctx *ctx, int32_t workers);
 

@@ -65,6 +65,14 @@ struct gxy_ctx {
   size_t chunk_bytes = 0;  // projection chunk bound (0: GXY_CHUNK_BYTES or 32 GiB)
   bool worker = false;     // batch worker: one stream, no side streams
   std::vector<gxy_ctx *> children;
+  // no-allocation runs (gxy_run_noalloc): this device's address of the
+  // library's static scratch array (looked up once per device at
+  // gxy_create), the flag that routes a run through it with one stream and
+  // no HIP allocation, and fixed host staging for results read back
+  void *scratch = nullptr;
+  bool noalloc = false;
+  std::vector<char> noalloc_arena;          // projection tables (host planning)
+  alignas(64) unsigned char noalloc_host[1 << 20];
 };
 
 // Every C entry point runs its body inside these: library errors become

@@ -271,7 +271,12 @@ static size_t carve(const gxy_point &p, const Plan &pl, Carver &c, Buffers &b) {
 
 namespace gxy {
 
+// One stream per run and no cooperative launches: batch workers (many of
+// them already fill the device) and no-allocation runs.
+static bool single_stream(const gxy_ctx *ctx) { return ctx->worker || ctx->noalloc; }
+
 static void ensure_pinned(gxy_ctx *ctx, size_t bytes) {
+  if (ctx->noalloc) return;   // host staging is ctx->noalloc_host
   if (ctx->pinned_bytes >= bytes) return;
   if (ctx->pinned) GXY_HIP(hipHostFree(ctx->pinned));
   ctx->pinned = nullptr;
@@ -287,6 +292,13 @@ static void upload_plan(gxy_ctx *ctx, int j, const TablePlan &tp, int64_t *d_tab
   if ((int64_t)tp.tab.size() > tab_cap || (int64_t)tp.groups.size() > grp_cap)
     fail(GXY_ENOMEM, "charge-block table bound exceeded");
   const size_t tb = tp.tab.size() * sizeof(int64_t), gb = tp.groups.size() * sizeof(GGroup);
+  if (ctx->noalloc) {
+    // straight from the planner's host vectors, complete before they go
+    if (tb) GXY_HIP(hipMemcpyAsync(d_tab, tp.tab.data(), tb, hipMemcpyHostToDevice, s));
+    if (gb) GXY_HIP(hipMemcpyAsync(d_grp, tp.groups.data(), gb, hipMemcpyHostToDevice, s));
+    GXY_HIP(hipStreamSynchronize(s));
+    return;
+  }
   const size_t need = tb + gb + 64;
   if (ctx->stage_used[j]) GXY_HIP(hipEventSynchronize(ctx->stage_ev[j]));
   if (ctx->stage_bytes[j] < need) {
@@ -319,7 +331,22 @@ struct ProjArena {
   int32_t *perm = nullptr;  // block-order permutation of the step
 };
 
-static void proj_stage_begin(gxy_ctx *ctx, int q, ProjArena &A, int64_t cap, int64_t perm_cap) {
+static void proj_stage_begin(gxy_ctx *ctx, int q, ProjArena &A, int64_t cap, int64_t perm_cap,
+                             hipStream_t s) {
+  if (ctx->noalloc) {
+    // one host arena (host heap), reused once the stream has drained
+    GXY_HIP(hipStreamSynchronize(s));
+    const size_t cb = ((size_t)cap + 255) & ~(size_t)255;
+    const size_t need = cb + (size_t)perm_cap * sizeof(int32_t) + 256;
+    if (ctx->noalloc_arena.size() < need) ctx->noalloc_arena.resize(need);
+    char *b = ctx->noalloc_arena.data();
+    b += (256 - ((uintptr_t)b & 255)) & 255;
+    A.base = b;
+    A.cap = cap;
+    A.used = 0;
+    A.perm = (int32_t *)(A.base + cb);
+    return;
+  }
   if (ctx->arena_pending[q]) GXY_HIP(hipEventSynchronize(ctx->arena_ev[q]));
   ctx->arena_pending[q] = false;
   const size_t cb = ((size_t)cap + 255) & ~(size_t)255;
@@ -341,6 +368,7 @@ static void proj_stage_begin(gxy_ctx *ctx, int q, ProjArena &A, int64_t cap, int
 // the arena may be reused once this event has completed (every copy
 // precedes its launch).
 static void proj_stage_done(gxy_ctx *ctx, int q, hipStream_t s) {
+  if (ctx->noalloc) return;   // the next step's begin drains the stream
   if (!ctx->arena_ev[q])
     GXY_HIP(hipEventCreateWithFlags(&ctx->arena_ev[q], hipEventDisableTiming));
   GXY_HIP(hipEventRecord(ctx->arena_ev[q], s));
@@ -380,7 +408,7 @@ static void stage_plan(ProjArena &A, const TablePlan &tp, const Launch &L, ProjJ
 static void send_plan(gxy_ctx *ctx, const ProjArena &A, ProjJob &j, char *d_area, hipStream_t s,
                       size_t k) {
   if (j.sent) return;
-  if (j.bytes && ctx->worker) {   // batch worker: copy on its own stream
+  if (j.bytes && single_stream(ctx)) {   // copy on the run's own stream
     GXY_HIP(hipMemcpyAsync(d_area + j.off, A.base + j.off, j.bytes, hipMemcpyHostToDevice, s));
   } else if (j.bytes) {
     while (ctx->copy_ev.size() <= k) {
@@ -418,6 +446,10 @@ static void run_launch(const Launch &L, const GGroup *d_grp, const int64_t *d_ta
 
 static void ensure_workspace(gxy_ctx *ctx, size_t need) {
   if (ctx->ws && ctx->ws_bytes >= need) return;
+  if (ctx->noalloc)
+    fail(GXY_EINVAL, "the run needs " + std::to_string(need) +
+                         " bytes of device workspace; the no-allocation scratch holds " +
+                         std::to_string(ctx->ws_bytes));
   if (ctx->ws && !ctx->ws_owned)
     fail(GXY_ENOMEM, "caller workspace of " + std::to_string(ctx->ws_bytes) +
                          " bytes is smaller than the " + std::to_string(need) +
@@ -846,7 +878,7 @@ static SectorSolve solve_sectors(gxy_ctx *ctx, hipStream_t s, const double *E, i
     launch_eig_gather(E, nf, r.d_idx, r.d_start, r.d_n, nsec, eg, s);
     std::vector<int> hn(sec.n.begin(), sec.n.end());
     launch_tri_values(nmat, nsec, hn.data(), r.d_n, eb.d_npad, eb.d_off, m.A, m.B1, m.V, m.B2,
-                      !ctx->worker, s);
+                      !single_stream(ctx), s);
     r.eb.A = m.A;
     r.eb.V = m.V;
     r.sweeps = 0;
@@ -939,7 +971,7 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
       ctx->chunk_bytes ? ctx->chunk_bytes : env_size("GXY_CHUNK_BYTES", kDefaultChunkBytes);
   // batch workers keep to their one stream: many workers already fill the
   // device, and every extra stream shares the few hardware queues
-  const Plan pl = make_plan(p, chunk_bytes, !ctx->worker);
+  const Plan pl = make_plan(p, chunk_bytes, !single_stream(ctx));
   Buffers b{};
   {
     Carver c0;
@@ -970,8 +1002,8 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
     GXY_HIP(hipEventRecord(ctx->pipe_ev[slot], st));
   };
   Timer tm;
-  tm.on = env_flag("GXY_TIMING");
-  ctx->hot_on = tm.on || ctx->hot_force || env_flag("GXY_HOT_EVENTS");
+  tm.on = env_flag("GXY_TIMING") && !ctx->noalloc;
+  ctx->hot_on = !ctx->noalloc && (tm.on || ctx->hot_force || env_flag("GXY_HOT_EVENTS"));
   ctx->hot_launches.clear();
   tm.s = s;
   tm.acc = ctx->phase_ms;
@@ -1048,7 +1080,7 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
   res.max_trunc_err = 0.0;
   res.min_cut_gap = INFINITY;
 
-  int32_t *hp = (int32_t *)ctx->pinned;
+  int32_t *hp = ctx->noalloc ? (int32_t *)ctx->noalloc_host : (int32_t *)ctx->pinned;
   for (int n = 1; n <= p.nsteps; ++n) {
     const StepDims &sd = pl.steps[n - 1];
     // buffers of this step's parity; the impurity stream read them last in
@@ -1150,12 +1182,17 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
                              hipMemcpyDeviceToHost, s));
       double *hd = reinterpret_cast<double *>(hp + 512);
       GXY_HIP(hipMemcpyAsync(hd, b.diag, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
-      if (!ctx->sel_ev) GXY_HIP(hipEventCreateWithFlags(&ctx->sel_ev, hipEventDisableTiming));
-      GXY_HIP(hipEventRecord(ctx->sel_ev, s));
+      if (!ctx->noalloc) {
+        if (!ctx->sel_ev) GXY_HIP(hipEventCreateWithFlags(&ctx->sel_ev, hipEventDisableTiming));
+        GXY_HIP(hipEventRecord(ctx->sel_ev, s));
+      }
       sv.vectors(b.diag + 2, s);   // diag[2] = chosen side
       launch_build_projector(eb.V, eb.d_off, eb.d_npad, d_idx, d_start, d_n, b.pick,
                              b.pick + Dn, b.diag, nsec, (int)nf, Dn, b.P, s);
-      GXY_HIP(hipEventSynchronize(ctx->sel_ev));
+      if (ctx->noalloc)
+        GXY_HIP(hipStreamSynchronize(s));
+      else
+        GXY_HIP(hipEventSynchronize(ctx->sel_ev));
       new_lh.assign(hp, hp + Dn);
       info.eps_l = hd[0];
       info.eps_r = hd[1];
@@ -1215,8 +1252,8 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
       // soon as it is ready, so the device runs one launch while the host
       // plans the next.
       ProjArena arena;
-      proj_stage_begin(ctx, par, arena, pl.proj_bytes, pl.maxW);
-      if (!ctx->copy_stream && !ctx->worker)
+      proj_stage_begin(ctx, par, arena, pl.proj_bytes, pl.maxW, s);
+      if (!ctx->copy_stream && !single_stream(ctx))
         GXY_HIP(hipStreamCreateWithFlags(&ctx->copy_stream, hipStreamNonBlocking));
       // (proj_stage_begin has seen the last launches that read this
       // parity's device slices complete, two steps ago, so the side stream
@@ -1295,6 +1332,7 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
         for (int64_t f = 0; f < Wn; ++f) arena.perm[blk.pos[f]] = (int32_t)f;
         GXY_HIP(hipMemcpyAsync(b.perm, arena.perm, Wn * sizeof(int32_t), hipMemcpyHostToDevice,
                                s));
+        if (ctx->noalloc) GXY_HIP(hipStreamSynchronize(s));
         launch_block_gather(b.T, b.T2, b.perm, Dh, Dv, s);
       }
       const int64_t nTn = (int64_t)Dn * Dn * Dv * Dv;
@@ -1442,6 +1480,76 @@ static size_t workspace_for(const gxy_point &p) {
   return carve(p, pl, c, b);
 }
 
+// ---------------------------------------------------------------------------
+// no-allocation runs: a fixed device scratch array
+// ---------------------------------------------------------------------------
+
+// Device memory of gxy_run_noalloc. Host code never uses this name as an
+// address (on the host it is only a stand-in): each device's copy is found
+// with hipGetSymbolAddress at gxy_create and kept in the context.
+constexpr size_t kScratchBytes = GXY_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch address on `device`, which must be current; looked up once
+// per device.
+static void *scratch_address(int device) {
+  if (device < 0 || device >= kMaxDevices) fail(GXY_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void *ptr = nullptr;
+    GXY_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) fail(GXY_EDEVICE, "no device address for the scratch array");
+    g_scratch_ptr[device] = ptr;
+  }
+  return g_scratch_ptr[device];
+}
+
+// Largest projection chunk bound whose workspace fits the scratch array
+// (0 if none does).
+static size_t noalloc_chunk(const gxy_point &p, size_t *need_out) {
+  size_t need = 0;
+  for (size_t chunk = kDefaultChunkBytes; chunk >= ((size_t)1 << 16); chunk /= 2) {
+    const Plan pl = make_plan(p, chunk, false);
+    Buffers b{};
+    Carver c;
+    need = carve(p, pl, c, b);
+    if (need <= kScratchBytes) {
+      *need_out = need;
+      return chunk;
+    }
+  }
+  *need_out = need;
+  return 0;
+}
+
+// Routes the context's runs through the scratch array for one call and
+// restores its own workspace afterwards.
+struct NoallocScope {
+  gxy_ctx *ctx;
+  void *ws;
+  size_t ws_bytes, chunk;
+  bool owned;
+  NoallocScope(gxy_ctx *c, size_t chunk_bytes)
+      : ctx(c), ws(c->ws), ws_bytes(c->ws_bytes), chunk(c->chunk_bytes), owned(c->ws_owned) {
+    c->ws = c->scratch;
+    c->ws_bytes = kScratchBytes;
+    c->ws_owned = false;
+    c->chunk_bytes = chunk_bytes;
+    c->noalloc = true;
+  }
+  ~NoallocScope() {
+    ctx->ws = ws;
+    ctx->ws_bytes = ws_bytes;
+    ctx->ws_owned = owned;
+    ctx->chunk_bytes = chunk;
+    ctx->noalloc = false;
+  }
+};
+
 }  // namespace gxy
 
 // ===========================================================================
@@ -1465,6 +1573,13 @@ gxy_status gxy_create(gxy_ctx **out, int device, void *hip_stream) {
   ctx = new gxy_ctx();
   ctx->device = device;
   ctx->stream = (hipStream_t)hip_stream;
+  try {
+    ctx->scratch = gxy::scratch_address(device);
+  } catch (...) {
+    delete ctx;
+    ctx = nullptr;
+    throw;
+  }
   *out = ctx;
   return GXY_OK;
   GXY_API_END(ctx)
@@ -1556,6 +1671,29 @@ gxy_status gxy_run(gxy_ctx *ctx, const gxy_point *pt, gxy_result *out) {
   if (!ctx || !pt || !out) return GXY_EINVAL;
   GXY_API_BEGIN
   GXY_HIP(hipSetDevice(ctx->device));
+  ctx->logs.assign(1, gxy::RunLog{});
+  gxy_result r{};
+  r.status = GXY_OK;
+  r.fail_step = -1;
+  gxy::run_one(ctx, *pt, r, ctx->logs[0]);
+  *out = r;
+  return (gxy_status)r.status;
+  GXY_API_END(ctx)
+}
+
+gxy_status gxy_run_noalloc(gxy_ctx *ctx, const gxy_point *pt, gxy_result *out) {
+  if (!ctx || !pt || !out) return GXY_EINVAL;
+  GXY_API_BEGIN
+  GXY_HIP(hipSetDevice(ctx->device));
+  gxy::validate(*pt);
+  if (!ctx->scratch) gxy::fail(GXY_EDEVICE, "no scratch address on this device");
+  size_t need = 0;
+  const size_t chunk = gxy::noalloc_chunk(*pt, &need);
+  if (!chunk)
+    gxy::fail(GXY_EINVAL, "the run needs " + std::to_string(need) +
+                              " bytes of device workspace; gxy_run_noalloc holds at most " +
+                              std::to_string(gxy::kScratchBytes));
+  gxy::NoallocScope scope(ctx, chunk);
   ctx->logs.assign(1, gxy::RunLog{});
   gxy_result r{};
   r.status = GXY_OK;

@@ -85,6 +85,7 @@ def load_library(path: str = LIB_PATH):
         "gxy_initial_tensor": [C.c_void_p, P(Point), C.c_int32, P(C.c_double)],
         "gxy_run": [C.c_void_p, P(Point), P(Result)],
         "gxy_run_batch": [C.c_void_p, P(Point), C.c_int32, P(Result)],
+        "gxy_run_noalloc": [C.c_void_p, P(Point), P(Result)],
         "gxy_set_batch_workers": [C.c_void_p, C.c_int32],
         "gxy_autotune": [C.c_void_p, P(Point), P(C.c_int32), C.c_int32, P(C.c_int32),
                          P(C.c_double)],
@@ -242,6 +243,16 @@ class Context:
         self.reserve([p])
         r = Result()
         st = self.lib.gxy_run(self.handle, C.byref(p), C.byref(r))
+        if st != GXY_OK and r.status == 0:
+            self._check(st, self.handle)
+        return self._result(r, 0)
+
+    def run_noalloc(self, point) -> RunResult:
+        """gxy_run_noalloc: the run in the library's fixed device scratch
+        array (no device allocation, no workspace reservation here)."""
+        p = point_from(point)
+        r = Result()
+        st = self.lib.gxy_run_noalloc(self.handle, C.byref(p), C.byref(r))
         if st != GXY_OK and r.status == 0:
             self._check(st, self.handle)
         return self._result(r, 0)
