@@ -15,6 +15,8 @@ from .hotrg import (  # noqa: F401
     char_coeffs,
     char_coeffs_bessel,
     field_factors,
+    square_factors,
+    second_moment_update,
     initial_tensors,
     environments,
     sector_eigh,

@@ -32,6 +32,12 @@ What it computes, and where the thesis defines it:
   running log-norm, the final tensor trace on the periodic 1x1 torus, the
   impurity ratio M = P/Z, and finite-difference observables C_v, chi
   (Ch. 3, eqs. spech, susc, mag).
+* Zero-field susceptibility from summed insertions (a variant of the
+  impurity method of Ch. 3 that the thesis does not use): besides the
+  one-insertion tensor, the tensor with two insertions averaged over ordered
+  pairs of sites is carried through the steps, so <m^2> = Tr T2 / Tr T for
+  the site average m, and chi = beta V (<m^2> - <m>^2) (eq. susc by the
+  fluctuation relation) from one zero-field run.
 
 Readings where the thesis is silent or garbled (each is restated in the
 design notes):
@@ -70,6 +76,10 @@ SIDE_TOL = 1e-10
 
 IMP_COS1 = 1
 IMP_COS2 = 2
+# second moments of the site-averaged insertions (zero-field susceptibilities)
+IMP_COS1_SQ = 4
+IMP_COS2_SQ = 8
+SECOND_OF = {IMP_COS1_SQ: IMP_COS1, IMP_COS2_SQ: IMP_COS2}
 
 SYM_U1 = 0     # integer charges, fused by addition
 SYM_NONE = 1   # a single sector (all labels 0)
@@ -184,6 +194,24 @@ def field_factors(beta: float, h: float, h1: float, qmax: int,
     return F, FM, FM1
 
 
+def square_factors(qmax: int, q: int = 2) -> Tuple[np.ndarray, np.ndarray]:
+    """Zero-field factors of the site tensors with cos^2 theta and cos^2 q theta
+    inserted: the Fourier coefficients (1/2pi) int cos^2(k th) e^{-i Q th} dth
+    = delta_{Q,0}/2 + (delta_{Q,2k} + delta_{Q,-2k})/4 for k = 1 and k = q
+    (index Q + qmax), the same integral over the site angle that gives the
+    impure tensors of Ch. 3 (Sec. Numerical Results) with cos^2 in place of
+    cos. Pinned by: beta = 0 (<m^2> V = 1/2 exactly) and the 2x2 / 4x2 tori.
+    """
+    qs = np.arange(-qmax, qmax + 1)
+    out = []
+    for k in (1, q):
+        f = np.zeros(len(qs))
+        f[qs == 0] += 0.5
+        f[np.abs(qs) == 2 * k] += 0.25
+        out.append(f)
+    return out[0], out[1]
+
+
 def symmetry_of(h: float, h1: float) -> int:
     """Symmetry left by the fields: U(1) at h = h1 = 0, Z_q at h = 0, else none."""
     if h == 0.0 and h1 == 0.0:
@@ -234,6 +262,14 @@ def initial_tensors(beta: float, delta: float, h: float, h1: float,
         imps[IMP_COS1] = amp * FM[Q + 4 * nmax]
     if impurities & IMP_COS2:
         imps[IMP_COS2] = amp * FM1[Q + 4 * nmax]
+    if impurities & (IMP_COS1_SQ | IMP_COS2_SQ):
+        if h != 0.0 or h1 != 0.0:
+            raise ValueError("second-moment insertions are defined at zero field only")
+        F2, F2q = square_factors(4 * nmax, q)
+        if impurities & IMP_COS1_SQ:
+            imps[IMP_COS1_SQ] = amp * F2[Q + 4 * nmax]
+        if impurities & IMP_COS2_SQ:
+            imps[IMP_COS2_SQ] = amp * F2q[Q + 4 * nmax]
     return T, imps
 
 
@@ -413,6 +449,15 @@ def project(P: np.ndarray, A: np.ndarray, B: np.ndarray) -> np.ndarray:
     return out
 
 
+def second_moment_update(P: np.ndarray, x2: np.ndarray, T: np.ndarray,
+                         x1: np.ndarray) -> np.ndarray:
+    """Two insertions averaged over the ordered pairs of sites of the merged
+    block: pairs inside the upper or the lower half, and the pairs split
+    between the halves (both orders): (X2 (x) T + T (x) X2 + 2 X1 (x) X1) / 4,
+    with X1 the one-insertion tensor of the step's input."""
+    return 0.25 * (project(P, x2, T) + project(P, T, x2) + 2.0 * project(P, x1, x1))
+
+
 # --------------------------------------------------------------------------
 # Full run
 # --------------------------------------------------------------------------
@@ -440,6 +485,10 @@ class RunResult:
     steps: List[StepLog] = field(default_factory=list)
     lnc0: float = 0.0
     trace: float = 0.0
+    msq_cos1: float = float("nan")   # <m^2>, m = (1/V) sum_i cos theta_i
+    msq_cos2: float = float("nan")   # the same for cos q theta
+    chi0: float = float("nan")       # beta V (<m^2> - <m>^2), cos theta
+    chi0_n: float = float("nan")     # the same for cos q theta
 
 
 def _norm(T: np.ndarray, kind: str) -> float:
@@ -496,7 +545,16 @@ def hotrg_run(T: np.ndarray, imps: Dict[int, np.ndarray], lab_h: np.ndarray,
             new_h = sel.labels
             truncated = True
         Tn = project(P, T, T)
-        new_imps = {k: 0.5 * (project(P, v, T) + project(P, T, v)) for k, v in imps.items()}
+        # one insertion averaged over the sites of the doubled block:
+        # (X (x) T + T (x) X) / 2; two insertions averaged over ordered pairs
+        # of sites: (X2 (x) T + T (x) X2 + 2 X (x) X) / 4, with the step's
+        # input X (the pairs split between the two halves count twice)
+        new_imps = {}
+        for k, v in imps.items():
+            if k in SECOND_OF:
+                new_imps[k] = second_moment_update(P, v, T, imps[SECOND_OF[k]])
+            else:
+                new_imps[k] = 0.5 * (project(P, v, T) + project(P, T, v))
         c = _norm(Tn, norm)
         Tn /= c
         for k in new_imps:
@@ -516,8 +574,9 @@ def hotrg_run(T: np.ndarray, imps: Dict[int, np.ndarray], lab_h: np.ndarray,
         raise FloatingPointError("non-positive or non-finite final trace")
     lnz = acc + math.log(tr) / 2.0 ** nsteps
     m = {k: float(np.einsum("llUU->", v)) / tr for k, v in imps.items()}
-    return RunResult(lnz, m.get(IMP_COS1, float("nan")), m.get(IMP_COS2, float("nan")),
-                     logs, math.log(c0), tr)
+    nan = float("nan")
+    return RunResult(lnz, m.get(IMP_COS1, nan), m.get(IMP_COS2, nan),
+                     logs, math.log(c0), tr, m.get(IMP_COS1_SQ, nan), m.get(IMP_COS2_SQ, nan))
 
 
 def run_point(beta: float, delta: float, h: float = 0.0, h1: float = 0.0,
@@ -528,10 +587,23 @@ def run_point(beta: float, delta: float, h: float = 0.0, h1: float = 0.0,
     """One HOTRG run from the gXY parameters (the full problem statement)."""
     q = 2 if q == 0 else int(q)
     sym = symmetry_of(h, h1)
+    # a second moment carries its first moment along
+    if impurities & IMP_COS1_SQ:
+        impurities |= IMP_COS1
+    if impurities & IMP_COS2_SQ:
+        impurities |= IMP_COS2
     T, imps = initial_tensors(beta, delta, h, h1, nmax, nquad, impurities, q)
     lab = leg_labels(nmax, sym, q)
-    return hotrg_run(T, imps, lab, lab, sym, dcut, nsteps, first=first, norm=norm,
-                     basis_seed=basis_seed, q=q)
+    r = hotrg_run(T, imps, lab, lab, sym, dcut, nsteps, first=first, norm=norm,
+                  basis_seed=basis_seed, q=q)
+    # susceptibility from the fluctuation of the site average (Ch. 3, eq. susc
+    # as beta V (<m^2> - <m>^2) at the field of the run), V = 2^nsteps
+    V = 2.0 ** nsteps
+    if impurities & IMP_COS1_SQ:
+        r.chi0 = beta * V * (r.msq_cos1 - r.m_cos1 ** 2)
+    if impurities & IMP_COS2_SQ:
+        r.chi0_n = beta * V * (r.msq_cos2 - r.m_cos2 ** 2)
+    return r
 
 
 def observables_from_runs(beta: float, lnz: Sequence[float], m_h: Sequence[float],
