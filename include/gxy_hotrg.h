@@ -86,7 +86,13 @@ typedef enum {
                             MFMA with FP32 accumulation                     */
 } gxy_precision;
 
-enum { GXY_IMP_COS1 = 1u, GXY_IMP_COS2 = 2u };
+/* Impurity chains. COS1 / COS2: one cos theta / cos q theta insertion
+ * averaged over the sites (Ch. 3, the impure-tensor method). COS1_SQ /
+ * COS2_SQ (zero field only): also two insertions averaged over ordered
+ * pairs of sites, giving <m^2> and the susceptibility
+ * beta V (<m^2> - <m>^2) of Ch. 3, eq. susc, from one run (a variant of the
+ * impurity method the thesis does not use); each implies its first moment. */
+enum { GXY_IMP_COS1 = 1u, GXY_IMP_COS2 = 2u, GXY_IMP_COS1_SQ = 4u, GXY_IMP_COS2_SQ = 8u };
 
 /* One HOTRG run (one point of the (beta, Delta, h, h1) parameter space). */
 typedef struct {
@@ -120,6 +126,12 @@ typedef struct {
   int32_t status;       /* gxy_status of this run                            */
   int32_t fail_step;    /* step at which it failed, -1 if none               */
   int32_t nsteps_done;
+  double msq_cos1;      /* <m^2>, m = (1/V) sum_i cos theta_i (GXY_IMP_COS1_SQ;
+                           else NaN); V = 2^nsteps                          */
+  double msq_cos2;      /* the same for cos q theta (GXY_IMP_COS2_SQ)        */
+  double chi0;          /* beta V (<m^2> - <m>^2) for cos theta: the
+                           susceptibility at this (zero) field               */
+  double chi0_n;        /* the same for cos q theta                          */
 } gxy_result;
 
 /* Per-step diagnostics of the last run (or of run `run` of the last batch). */

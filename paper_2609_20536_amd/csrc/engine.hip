@@ -99,11 +99,34 @@ struct Plan {
 
 static int sym_of(const gxy_point &p);
 
+// Impurity chains of a run: the one-insertion chains (cos theta, cos q theta)
+// first, then the second-moment chains, each with the index of the
+// one-insertion chain it is built from. A second moment carries its first
+// moment along.
+struct Chains {
+  int n = 0;
+  int which[4] = {0, 0, 0, 0};   // GXY_IMP_* of chain k
+  int first[4] = {-1, -1, -1, -1};  // second-moment chains: their first moment
+};
+
+static Chains chains_of(const gxy_point &p) {
+  Chains c;
+  uint32_t m = p.impurities;
+  if (m & GXY_IMP_COS1_SQ) m |= GXY_IMP_COS1;
+  if (m & GXY_IMP_COS2_SQ) m |= GXY_IMP_COS2;
+  int at1 = -1, at2 = -1;
+  if (m & GXY_IMP_COS1) { at1 = c.n; c.which[c.n++] = GXY_IMP_COS1; }
+  if (m & GXY_IMP_COS2) { at2 = c.n; c.which[c.n++] = GXY_IMP_COS2; }
+  if (m & GXY_IMP_COS1_SQ) { c.first[c.n] = at1; c.which[c.n++] = GXY_IMP_COS1_SQ; }
+  if (m & GXY_IMP_COS2_SQ) { c.first[c.n] = at2; c.which[c.n++] = GXY_IMP_COS2_SQ; }
+  return c;
+}
+
 static Plan make_plan(const gxy_point &p, size_t chunk_bytes, bool allow_overlap = true) {
   Plan pl;
   pl.d0 = 2 * p.nmax + 1;
   int Dh = pl.d0, Dv = pl.d0;
-  pl.nimp = ((p.impurities & GXY_IMP_COS1) ? 1 : 0) + ((p.impurities & GXY_IMP_COS2) ? 1 : 0);
+  pl.nimp = chains_of(p).n;
   pl.maxT = (int64_t)Dh * Dh * Dv * Dv;
   int64_t per_a_max = 1;
   for (int n = 1; n <= p.nsteps; ++n) {
@@ -138,7 +161,9 @@ static Plan make_plan(const gxy_point &p, size_t chunk_bytes, bool allow_overlap
                !getenv("GXY_NO_OVERLAP");
   // bounds of the charge-block tables of one step (see plan.hip): every row,
   // reduction and column index appears in at most |S| <= 2 groups per table
-  const int64_t nvar = 1 + 2 * pl.nimp;
+  // table variants per chunk (one X, Y and T' plan each): the pure tensor
+  // one, a one-insertion chain two, a second-moment chain three
+  const int64_t nvar = 1 + 3 * pl.nimp;
   for (const StepDims &sd : pl.steps) {
     const int64_t Dh = sd.dh, Dv = sd.dv, Dn = sd.dn, MN = Dh * Dv;
     const int64_t nch = (Dn + ac - 1) / ac;
@@ -152,7 +177,7 @@ static Plan make_plan(const gxy_point &p, size_t chunk_bytes, bool allow_overlap
     pl.grp_env = std::max(pl.grp_env, 2 * (2 * MN + Dh * Dh) + 16);
     pl.grp_proj = std::max(pl.grp_proj, nch * nvar * (Dn * Dh + 2 * MN + Dn + 16));
     // one slice per launch (groups, then tables), each rounded up to 64 bytes
-    const int64_t nlaunch = nch * (3 + 4 * pl.nimp);
+    const int64_t nlaunch = nch * (3 + 6 * pl.nimp);
     pl.proj_bytes = std::max(pl.proj_bytes, 8 * pl.tab_proj +
                                                 (int64_t)sizeof(GGroup) * pl.grp_proj +
                                                 64 * nlaunch);
@@ -162,7 +187,7 @@ static Plan make_plan(const gxy_point &p, size_t chunk_bytes, bool allow_overlap
 
 struct Buffers {
   double *T, *Tn, *T2;             // site tensor, next, bottom-operand copy
-  double *TX[2], *TXn[2], *TX2[2]; // impurity tensors
+  double *TX[4], *TXn[4], *TX2[4]; // impurity tensors
   double *envA, *envB, *E;         // environments
   double *P;                       // projector of the current step
   double *X, *XI, *Y, *YI;         // projection chunks (YI: impurity stream)
@@ -202,7 +227,7 @@ static size_t carve(const gxy_point &p, const Plan &pl, Carver &c, Buffers &b) {
   b.T2b[0] = c.take<double>(T);
   b.T2b[1] = pl.overlap ? c.take<double>(T) : b.T2b[0];
   b.T2 = b.T2b[0];
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < 4; ++k) {
     const bool on = k < pl.nimp;
     b.TX[k] = on ? c.take<double>(T) : nullptr;
     b.TXn[k] = on ? c.take<double>(T) : nullptr;
@@ -253,7 +278,7 @@ static size_t carve(const gxy_point &p, const Plan &pl, Carver &c, Buffers &b) {
   b.partial = c.take<double>(1024);
   b.nrm = c.take<double>(3 * (int64_t)(p.nsteps + 1));
   const int qmax = 4 * p.nmax;
-  b.coef = c.take<double>(pl.d0 + 3 * (2 * qmax + 1));
+  b.coef = c.take<double>(pl.d0 + 5 * (2 * qmax + 1));
   b.scal = c.take<double>(16);
   b.tab_env = c.take<int64_t>(pl.tab_env);
   for (int q = 0; q < 2; ++q) {
@@ -441,6 +466,7 @@ static void run_launch(const Launch &L, const GGroup *d_grp, const int64_t *d_ta
   g.beta = beta;
   g.kfast_a = L.kfast_a;
   g.nfast_b = L.nfast_b;
+  g.contig = L.contig;
   grouped_gemm(g, s);
 }
 
@@ -509,7 +535,9 @@ static void validate(const gxy_point &p) {
   if (p.dcut < 1 || p.dcut > 128) fail(GXY_EINVAL, "dcut must lie in [1, 128]");
   if (p.nsteps < 0 || p.nsteps > 62) fail(GXY_EINVAL, "nsteps must lie in [0, 62]");
   if (p.nquad <= 2 * p.nmax) fail(GXY_EINVAL, "nquad must exceed 2*nmax");
-  if (p.impurities & ~3u) fail(GXY_EINVAL, "unknown impurity bits");
+  if (p.impurities & ~15u) fail(GXY_EINVAL, "unknown impurity bits");
+  if ((p.impurities & (GXY_IMP_COS1_SQ | GXY_IMP_COS2_SQ)) && (p.h != 0.0 || p.h1 != 0.0))
+    fail(GXY_EUNSUPPORTED, "second-moment insertions are built at zero field only");
   if (p.prec != GXY_PREC_FP64 && p.prec != GXY_PREC_FP32 && p.prec != GXY_PREC_BF16X3)
     fail(GXY_EINVAL, "unknown contraction precision");
   if (p.fp64_steps < 0) fail(GXY_EINVAL, "fp64_steps must be >= 0");
@@ -1030,23 +1058,22 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
   double *F = t + D0;
   double *FM = F + (2 * qmax + 1);
   double *FM1 = FM + (2 * qmax + 1);
+  double *FS1 = FM1 + (2 * qmax + 1);   // cos^2 theta
+  double *FS2 = FS1 + (2 * qmax + 1);   // cos^2 q theta
 
   tm.begin();
   const int qh = harmonic(p);
   launch_char_coeffs(p.beta, p.delta, qh, nmax, p.nquad, t, s);
   launch_field_factors(p.beta, p.h, p.h1, qh, qmax, kLmax, sym == SYM_U1, F, FM, FM1, s);
   launch_init_tensor(t, F, nmax, b.T, s);
-  int imp_which[2] = {0, 0};
-  {
-    int k = 0;
-    if (p.impurities & GXY_IMP_COS1) {
-      launch_init_tensor(t, FM, nmax, b.TX[k], s);
-      imp_which[k++] = 1;
-    }
-    if (p.impurities & GXY_IMP_COS2) {
-      launch_init_tensor(t, FM1, nmax, b.TX[k], s);
-      imp_which[k++] = 2;
-    }
+  const Chains ch = chains_of(p);
+  if (p.impurities & (GXY_IMP_COS1_SQ | GXY_IMP_COS2_SQ))
+    launch_square_factors(qh, qmax, FS1, FS2, s);
+  for (int k = 0; k < ch.n; ++k) {
+    const int w = ch.which[k];
+    const double *Fk = w == GXY_IMP_COS1 ? FM : w == GXY_IMP_COS2 ? FM1
+                       : w == GXY_IMP_COS1_SQ ? FS1 : FS2;
+    launch_init_tensor(t, Fk, nmax, b.TX[k], s);
   }
   const int nimp = pl.nimp;
   int Dh = D0, Dv = D0;
@@ -1060,10 +1087,15 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
   const int mod = (sym == SYM_U1) ? 0 : (sym == SYM_Z2 ? qh : 1);
   // allowed Q = q_l + q_d - q_r - q_u of each impurity tensor (cos theta
   // carries charge +-1, cos q theta +-q; with Z_q labels these are mod q)
-  QSet imp_set[2];
+  QSet imp_set[4];
   for (int k = 0; k < nimp; ++k) {
-    const bool cos1 = imp_which[k] == 1;
-    if (sym == SYM_U1)
+    const int w = ch.which[k];
+    const bool cos1 = w == GXY_IMP_COS1;
+    if (w == GXY_IMP_COS1_SQ)          // zero field only: cos^2 carries 0, +-2
+      imp_set[k] = QSet{-2, 0, 2};
+    else if (w == GXY_IMP_COS2_SQ)     // cos^2 q: 0, +-2q
+      imp_set[k] = QSet{-2 * qh, 0, 2 * qh};
+    else if (sym == SYM_U1)
       imp_set[k] = cos1 ? QSet{-1, 1} : QSet{-qh, qh};
     else if (sym == SYM_Z2)
       imp_set[k] = cos1 ? qset_sum(QSet{1, -1}, QSet{0}, qh) : QSet{0};
@@ -1275,7 +1307,9 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
       // launch kinds: pure X, Y, T'; impurity Y = X(T) T_X2, X(T_X),
       // Y += X(T_X) T2, T' of the summed Y (the projection is linear in Y, so
       // the two placements share one T' product)
-      enum { PX, PY, PT, IY, IX2, IY2, IT, NKIND };
+      // second-moment chains also Y += 2 X(T1) T1 (the pairs split between
+      // the halves), with X(T1) formed again: IX3, IY3
+      enum { PX, PY, PT, IY, IX2, IY2, IX3, IY3A, IY3B, IT, NKIND };
       struct Part {
         int a0 = 0, ac = 0, k = -1;  // k = -1: pure tensor; else impurity k
         ProjJob job[NKIND];
@@ -1294,13 +1328,16 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
       for (int i = 0; i < (int)parts.size(); ++i) {
         if (parts[i].k < 0)
           for (int kd : {PX, PY, PT}) order.push_back({i, kd});
-        else
+        else if (ch.first[parts[i].k] < 0)
           for (int kd : {IY, IX2, IY2, IT}) order.push_back({i, kd});
+        else
+          for (int kd : {IY, IX2, IY2, IX3, IY3A, IY3B, IT}) order.push_back({i, kd});
       }
-      auto plan_job = [&SL, &s0, &imp_set, &parts, &arena](int i, int kd) {
+      auto plan_job = [&SL, &s0, &imp_set, &parts, &arena, &ch](int i, int kd) {
         Part &pt = parts[i];
         const int a0 = pt.a0, a1 = pt.a0 + pt.ac;
         const QSet &sk = pt.k < 0 ? s0 : imp_set[pt.k];
+        const QSet &s1 = (pt.k < 0 || ch.first[pt.k] < 0) ? s0 : imp_set[ch.first[pt.k]];
         TablePlan tp;
         Launch L;
         switch (kd) {
@@ -1310,6 +1347,10 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
           case IY: L = plan_proj_y(SL, a0, a1, s0, sk, tp); break;
           case IT: L = plan_proj_t(SL, a0, a1, sk, tp); break;
           case IX2: L = plan_proj_x(SL, a0, a1, sk, tp); break;
+          case IX3: L = plan_proj_x(SL, a0, a1, s1, tp); break;
+          // X(T1) T1 by the charge of the upper factor (U(1): {-c, +c})
+          case IY3A: L = plan_proj_y(SL, a0, a1, QSet{s1.front()}, s1, tp); break;
+          case IY3B: L = plan_proj_y(SL, a0, a1, QSet{s1.back()}, s1, tp); break;
           default: L = plan_proj_y(SL, a0, a1, sk, s0, tp); break;
         }
         stage_plan(arena, tp, L, pt.job[kd]);
@@ -1387,7 +1428,15 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
           go(take(i, IY), b.X, b.TX2[k], b.YI, 1.0, 0.0, true, si, sl + IY);
           go(take(i, IX2), b.P, b.TX[k], b.XI, 1.0, 0.0, false, si, sl + IX2);
           go(take(i, IY2), b.XI, b.T2, b.YI, 1.0, 1.0, true, si, sl + IY2);
-          go(take(i, IT), b.YI, b.P, b.TXn[k], 0.5, 0.0, false, si, sl + IT);
+          const int k1 = ch.first[k];
+          if (k1 >= 0) {
+            // second moment: (T2 (x) T + T (x) T2 + 2 T1 (x) T1) / 4 with the
+            // step's input T1 (its chain wrote only TXn[k1] so far)
+            go(take(i, IX3), b.P, b.TX[k1], b.XI, 1.0, 0.0, false, si, sl + IX3);
+            go(take(i, IY3A), b.XI, b.TX2[k1], b.YI, 2.0, 1.0, true, si, sl + IY3A);
+            go(take(i, IY3B), b.XI, b.TX2[k1], b.YI, 2.0, 1.0, true, si, sl + IY3B);
+          }
+          go(take(i, IT), b.YI, b.P, b.TXn[k], k1 >= 0 ? 0.25 : 0.5, 0.0, false, si, sl + IT);
         }
       }
       if (si != s) record_on(si, 4 + par);
@@ -1426,19 +1475,21 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
   }
   // ---- trace and result ----
   stream_after(ctx, s, si, 3);
-  double *tr = b.scal, *tr1 = b.scal + 1, *tr2 = b.scal + 2, *rr = b.scal + 4;
+  // traces at scal[0] (pure) and scal[1 + k] (chain k); results at scal[8..15]
+  double *tr = b.scal, *tr1 = b.scal + 1, *rr = b.scal + 8;
   launch_trace(b.T, Dh, Dv, tr, s);
-  const double *trk[2] = {nullptr, nullptr};
+  const double *trk[4] = {nullptr, nullptr, nullptr, nullptr};
   for (int k = 0; k < nimp; ++k) {
     launch_trace(b.TX[k], Dh, Dv, tr1 + k, s);
-    trk[imp_which[k] - 1] = tr1 + k;
+    const int w = ch.which[k];
+    trk[w == GXY_IMP_COS1 ? 0 : w == GXY_IMP_COS2 ? 1 : w == GXY_IMP_COS1_SQ ? 2 : 3] = tr1 + k;
   }
   // lnc[n] lives at nrm[3n + 1]; gather them contiguously into the partial buffer
   GXY_HIP(hipMemcpy2DAsync(b.partial, sizeof(double), b.nrm + 1, 3 * sizeof(double),
                            sizeof(double), p.nsteps + 1, hipMemcpyDeviceToDevice, s));
-  launch_finish(b.partial, p.nsteps, tr, trk[0], trk[1], rr, s);
+  launch_finish(b.partial, p.nsteps, p.beta, tr, trk, rr, s);
   double *hd = reinterpret_cast<double *>(hp);
-  GXY_HIP(hipMemcpyAsync(hd, rr, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+  GXY_HIP(hipMemcpyAsync(hd, rr, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
   GXY_HIP(hipMemcpyAsync(hd + 8, b.partial, (p.nsteps + 1) * sizeof(double),
                          hipMemcpyDeviceToHost, s));
   GXY_HIP(hipStreamSynchronize(s));
@@ -1447,11 +1498,14 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
   res.m_cos1 = hd[1];
   res.m_cos2 = hd[2];
   res.status = (int32_t)hd[3];
+  res.msq_cos1 = hd[4];
+  res.msq_cos2 = hd[5];
+  res.chi0 = hd[6];
+  res.chi0_n = hd[7];
   res.fail_step = res.status ? p.nsteps : -1;
   res.nsteps_done = p.nsteps;
   if (!isfinite(res.min_cut_gap)) res.min_cut_gap = 0.0;
   for (int n = 1; n <= p.nsteps; ++n) log.steps[n - 1].lnc = hd[8 + n];
-  (void)tr2;
 }
 
 static void initial_tensor_only(gxy_ctx *ctx, const gxy_point &p, int which, double *out) {
@@ -1733,12 +1787,14 @@ gxy_status gxy_run_batch(gxy_ctx *ctx, const gxy_point *pts, int32_t n, gxy_resu
     } catch (const Error &e) {
       r.status = e.status;
       r.lnz_per_site = r.m_cos1 = r.m_cos2 = NAN;
+      r.msq_cos1 = r.msq_cos2 = r.chi0 = r.chi0_n = NAN;
       std::lock_guard<std::mutex> g(err_mu);
       last = e.msg;
       if (e.status == GXY_EDEVICE) dead = true;
     } catch (...) {
       r.status = GXY_EDEVICE;
       r.lnz_per_site = r.m_cos1 = r.m_cos2 = NAN;
+      r.msq_cos1 = r.msq_cos2 = r.chi0 = r.chi0_n = NAN;
       std::lock_guard<std::mutex> g(err_mu);
       last = "unexpected host exception";
       dead = true;
@@ -1779,7 +1835,7 @@ gxy_status gxy_run_batch(gxy_ctx *ctx, const gxy_point *pts, int32_t n, gxy_resu
     std::vector<double> cost(n);
     for (int i = 0; i < n; ++i) {
       const gxy_point &p = pts[i];
-      const int nimp = ((p.impurities & 1) ? 1 : 0) + ((p.impurities & 2) ? 1 : 0);
+      const int nimp = gxy::chains_of(p).n;
       const double D = std::max(1, std::min(p.dcut, 128));
       cost[i] = std::pow(D, 7.0) * std::max(p.nsteps, 1) * (1 + 2 * nimp) *
                 ((p.h != 0.0) ? 16.0 : (p.h1 != 0.0 ? 2.0 : 1.0));
@@ -1808,6 +1864,7 @@ gxy_status gxy_run_batch(gxy_ctx *ctx, const gxy_point *pts, int32_t n, gxy_resu
     if (dead && out[i].status == GXY_OK && out[i].nsteps_done == 0 && pts[i].nsteps > 0) {
       out[i].status = GXY_EDEVICE;
       out[i].lnz_per_site = out[i].m_cos1 = out[i].m_cos2 = NAN;
+      out[i].msq_cos1 = out[i].msq_cos2 = out[i].chi0 = out[i].chi0_n = NAN;
     }
     any_fail |= out[i].status != GXY_OK;
   }

@@ -106,6 +106,12 @@ struct GroupedGemm {
   double *C;
   double alpha, beta;
   bool kfast_a, nfast_b;
+  // contig: every group's reduction and column indices are contiguous
+  // ranges; its fields then read ar = row table (A and C rows), ac = A
+  // column base, br = B base, bc = B row stride, cc = C column base, and
+  // A(m, k) = A[tab[ar + m] + ac + k], B(k, n) = B[br + k bc + n],
+  // C(m, n) = C[tab[ar + m] + cc + n]
+  bool contig;
 };
 
 void grouped_gemm(const GroupedGemm &g, hipStream_t s);
@@ -127,6 +133,9 @@ void launch_char_coeffs(double beta, double delta, int q, int nmax, int nquad,
 void launch_field_factors(double beta, double h, double h1, int q, int qmax,
                           int lmax, bool zero_field, double *F, double *FM,
                           double *FM1, hipStream_t s);
+// Zero-field factors of cos^2 theta and cos^2 q theta insertions, Q in
+// [-qmax, qmax]: delta_{Q,0} / 2 + (delta_{Q,2k} + delta_{Q,-2k}) / 4.
+void launch_square_factors(int q, int qmax, double *F2, double *F2q, hipStream_t s);
 // T[l][r][u][d] = sqrt(t_l t_r t_u t_d) * F(n_u + n_r - n_d - n_l).
 void launch_init_tensor(const double *t, const double *F, int nmax, double *T,
                         hipStream_t s);
@@ -257,10 +266,11 @@ void launch_build_projector(const double *V, const int64_t *d_mat_off,
                             const double *d_diag, int nsec, int nfused,
                             int dcut, double *P, hipStream_t s);
 
-// final: res[0] = lnz, res[1] = m1, res[2] = m2 (NaN if absent), res[3] = status
-void launch_finish(const double *lnc, int nsteps, const double *tr,
-                   const double *tr1, const double *tr2, double *res,
-                   hipStream_t s);
+// final: res[0] = lnz, res[1] = <cos>, res[2] = <cos q>, res[3] = status,
+// res[4..5] = <m^2> of both, res[6..7] = beta V (<m^2> - <m>^2) (NaN where a
+// chain is absent); trk = traces of the cos, cos q, cos^2, cos^2 q chains
+void launch_finish(const double *lnc, int nsteps, double beta, const double *tr,
+                   const double *const trk[4], double *res, hipStream_t s);
 void launch_observables(int npts, const double *beta, const double *lnz,
                         const double *mh, const double *mh1, double dbeta,
                         double dh, double dh1, double *out, hipStream_t s);

@@ -118,6 +118,24 @@ void launch_field_factors(double beta, double h, double h1, int q, int qmax, int
   GXY_CHECK_LAUNCH();
 }
 
+// The site angle's integral of cos^2(k theta) e^{-i Q theta} / 2 pi, the
+// factor of a site tensor with that insertion at zero field, k = 1 and q.
+__global__ void square_factors_kernel(int q, int qmax, double *F2, double *F2q) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > 2 * qmax) return;
+  const int Q = i - qmax;
+  const int aq = Q < 0 ? -Q : Q;
+  F2[i] = (Q == 0 ? 0.5 : 0.0) + (aq == 2 ? 0.25 : 0.0);
+  F2q[i] = (Q == 0 ? 0.5 : 0.0) + (aq == 2 * q ? 0.25 : 0.0);
+}
+
+void launch_square_factors(int q, int qmax, double *F2, double *F2q, hipStream_t s) {
+  const int n = 2 * qmax + 1;
+  hipLaunchKernelGGL(square_factors_kernel, dim3((n + 63) / 64), dim3(64), 0, s, q, qmax, F2,
+                     F2q);
+  GXY_CHECK_LAUNCH();
+}
+
 void launch_init_tensor(const double *t, const double *F, int nmax, double *T,
                         hipStream_t s) {
   const int D = 2 * nmax + 1;

@@ -552,17 +552,28 @@ __global__ void build_projector_kernel(const double *V, const int64_t *mat_off,
     P[(int64_t)sec_idx[st + i] * dcut + j] = Vm[(int64_t)i * npad + col];
 }
 
-__global__ void finish_kernel(const double *lnc, int nsteps, const double *tr,
-                              const double *tr1, const double *tr2, double *res) {
+struct TraceSet {
+  const double *t[4];   // cos, cos q, cos^2, cos^2 q (null if not carried)
+};
+
+__global__ void finish_kernel(const double *lnc, int nsteps, double beta, const double *tr,
+                              TraceSet tk, double *res) {
   if (threadIdx.x != 0) return;
   double acc = lnc[0];
   for (int n = 1; n <= nsteps; ++n) acc += lnc[n] / ldexp(1.0, n);
   const double t = tr[0];
   const bool ok = (t > 0.0) && isfinite(t) && isfinite(acc);
   res[0] = ok ? acc + log(t) / ldexp(1.0, nsteps) : NAN;
-  res[1] = tr1 ? tr1[0] / t : NAN;
-  res[2] = tr2 ? tr2[0] / t : NAN;
+  res[1] = tk.t[0] ? tk.t[0][0] / t : NAN;
+  res[2] = tk.t[1] ? tk.t[1][0] / t : NAN;
   res[3] = ok ? 0.0 : (double)GXY_ENUMERIC;
+  // second moments of the site averages and beta V (<m^2> - <m>^2)
+  const double V = ldexp(1.0, nsteps);
+  for (int j = 0; j < 2; ++j) {
+    const double msq = tk.t[2 + j] ? tk.t[2 + j][0] / t : NAN;
+    res[4 + j] = msq;
+    res[6 + j] = beta * V * (msq - res[1 + j] * res[1 + j]);
+  }
 }
 
 __global__ void observables_kernel(int npts, const double *beta, const double *lnz,
@@ -673,11 +684,10 @@ void launch_build_projector(const double *V, const int64_t *d_mat_off,
   GXY_CHECK_LAUNCH();
 }
 
-void launch_finish(const double *lnc, int nsteps, const double *tr,
-                   const double *tr1, const double *tr2, double *res,
-                   hipStream_t s) {
-  hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(64), 0, s, lnc, nsteps, tr, tr1, tr2,
-                     res);
+void launch_finish(const double *lnc, int nsteps, double beta, const double *tr,
+                   const double *const trk[4], double *res, hipStream_t s) {
+  TraceSet tk{{trk[0], trk[1], trk[2], trk[3]}};
+  hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(64), 0, s, lnc, nsteps, beta, tr, tk, res);
   GXY_CHECK_LAUNCH();
 }
 

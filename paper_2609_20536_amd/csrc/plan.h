@@ -35,6 +35,7 @@ QSet qset_sum(const QSet &a, const QSet &b, int mod);
 struct Launch {
   int32_t first_group = 0, ngroups = 0, total_tiles = 0, tile = 64;
   bool kfast_a = false, nfast_b = false;
+  bool contig = false;  // groups of contiguous ranges (GroupedGemm::contig)
   double flops = 0.0;  // algorithmic 2 M N K summed over groups
   double bytes = 0.0;  // algorithmic FP64 bytes: A, B read once, C written once
   double c_bytes = 0.0;  // 8 M N over the groups: C read once more when beta != 0
@@ -77,6 +78,9 @@ void plan_env(const StepLegs &L, bool right, TablePlan &tp, Launch out[3]);
 //  T'[a][b][u][d]     += alpha sum_(r1,r2) Y[a-a0][r1][u][pos(r2,d)] P[(r1,r2),b]
 // with B2[pos(l2,i)][pos(r2,d)] = B[l2][r2][i][d] (B in sB). Every charge
 // block of the D^7 product Y = X B2 then reads and writes contiguous rows.
+// plan_proj_y takes at most one of sA, sB with several charges (each output
+// block then has one reduction block); a product of two charged factors is
+// planned once per charge of A and accumulated.
 Launch plan_proj_x(const StepLegs &L, int a0, int a1, const QSet &sA, TablePlan &tp);
 Launch plan_proj_y(const StepLegs &L, int a0, int a1, const QSet &sA, const QSet &sB,
                    TablePlan &tp);

@@ -84,11 +84,12 @@ int choose_tile(const std::vector<GSpec> &gs) {
 }
 
 Launch finish_launch(TablePlan &tp, const std::vector<GSpec> &gs, bool kfa, bool nfb,
-                     int force_tile = 0) {
+                     int force_tile = 0, bool contig = false) {
   Launch L;
   L.first_group = (int32_t)tp.groups.size();
   L.kfast_a = kfa;
   L.nfast_b = nfb;
+  L.contig = contig;
   L.tile = force_tile ? force_tile : choose_tile(gs);
   for (const auto &g : gs) {
     if (g.M <= 0 || g.N <= 0) continue;
@@ -342,6 +343,11 @@ Launch plan_proj_x(const StepLegs &S, int a0, int a1, const QSet &sA, TablePlan 
 
 Launch plan_proj_y(const StepLegs &S, int a0, int a1, const QSet &sA, const QSet &sB,
                    TablePlan &tp) {
+  // every output block must take its whole reduction from one group: with
+  // several charges on both operands a block (rho, nu) would sum over
+  // several kappa (the caller splits such a product by the charge of A)
+  if (sA.size() > 1 && sB.size() > 1)
+    fail(GXY_EUNSUPPORTED, "projection product with several charges on both operands");
   const int Dh = S.Dh, Dv = S.Dv, mod = S.mod;
   const int64_t W = (int64_t)Dh * Dv;
   // rho = q_a - q_r1 - q_u per row (a, r1, u); kappa = q_l2 - q_i per reduction
@@ -379,36 +385,49 @@ Launch plan_proj_y(const StepLegs &S, int a0, int a1, const QSet &sA, const QSet
       for (int s : sA) kappas.push_back(qnorm(lo + k - s, mod));
   std::sort(kappas.begin(), kappas.end());
   kappas.erase(std::unique(kappas.begin(), kappas.end()), kappas.end());
+  // first position and length of a block-order range that must be contiguous
+  auto range_of = [](const std::vector<int64_t> &v, int64_t &first) {
+    first = v.empty() ? 0 : v.front();
+    for (size_t i = 0; i < v.size(); ++i)
+      if (v[i] != first + (int64_t)i) fail(GXY_EDEVICE, "block order range is not contiguous");
+    return (int32_t)v.size();
+  };
+  // One group per (kappa, nu): rows through the table, the reduction range
+  // of kappa and the column range of nu as bases (contiguous groups).
   std::vector<GSpec> gs;
   for (int kappa : kappas) {
-    std::vector<int64_t> rows, cols, ac, br;
+    std::vector<int64_t> rows;
     for (int k = 0; k < rows_by_rho.nk; ++k) {
       const auto &v = rows_by_rho.first[k];
       if (!v.empty() && in_set(qnorm(lo + k - kappa, mod), sA))
         rows.insert(rows.end(), v.begin(), v.end());
     }
-    for (const auto &kv : cols_by_nu)
-      if (in_set(qnorm(kappa - kv.first, mod), sB))
-        cols.insert(cols.end(), kv.second.begin(), kv.second.end());
-    if (rows.empty() || cols.empty()) continue;
+    if (rows.empty()) continue;
+    int64_t k0 = 0;
+    int32_t K = 0;
     auto ik = ks_by_kappa.find(kappa);
-    if (ik != ks_by_kappa.end()) {
-      ac = ik->second;
-      for (int64_t k : ik->second) br.push_back(k * W);
+    if (ik != ks_by_kappa.end()) K = range_of(ik->second, k0);
+    int64_t rows_at = -1;
+    for (const auto &kv : cols_by_nu) {
+      if (!in_set(qnorm(kappa - kv.first, mod), sB)) continue;
+      int64_t c0 = 0;
+      const int32_t N = range_of(kv.second, c0);
+      if (N == 0) continue;
+      if (rows_at < 0) rows_at = put(tp, rows);
+      GSpec g;
+      g.M = (int32_t)rows.size();
+      g.N = N;
+      g.K = K;
+      g.ar = rows_at;
+      g.cr = rows_at;
+      g.ac = k0;
+      g.br = k0 * W + c0;
+      g.bc = W;
+      g.cc = c0;
+      gs.push_back(g);
     }
-    GSpec g;
-    g.M = (int32_t)rows.size();
-    g.N = (int32_t)cols.size();
-    g.K = (int32_t)ac.size();
-    g.ar = put(tp, rows);
-    g.cr = g.ar;
-    g.ac = put(tp, ac);
-    g.br = put(tp, br);
-    g.bc = put(tp, cols);
-    g.cc = g.bc;
-    gs.push_back(g);
   }
-  return finish_launch(tp, gs, true, true, S.tile);
+  return finish_launch(tp, gs, true, true, S.tile, true);
 }
 
 Launch plan_proj_t(const StepLegs &S, int a0, int a1, const QSet &sY, TablePlan &tp) {

@@ -40,7 +40,8 @@ class Result(C.Structure):
                 ("m_cos2", C.c_double), ("max_trunc_err", C.c_double),
                 ("min_cut_gap", C.c_double), ("near_ties", C.c_int32),
                 ("status", C.c_int32), ("fail_step", C.c_int32),
-                ("nsteps_done", C.c_int32)]
+                ("nsteps_done", C.c_int32), ("msq_cos1", C.c_double),
+                ("msq_cos2", C.c_double), ("chi0", C.c_double), ("chi0_n", C.c_double)]
 
 
 class StepInfo(C.Structure):
@@ -156,6 +157,11 @@ class RunResult:
     near_ties: int
     status: int
     steps: list
+    msq_cos1: float = float("nan")
+    msq_cos2: float = float("nan")
+    chi0: float = float("nan")
+    chi0_n: float = float("nan")
+    fail_step: int = -1
 
 
 class Context:
@@ -306,7 +312,8 @@ class Context:
     def _result(self, r: Result, run: int) -> RunResult:
         steps = self.step_log(run) if r.status == 0 else []
         return RunResult(r.lnz_per_site, r.m_cos1, r.m_cos2, r.max_trunc_err,
-                         r.min_cut_gap, r.near_ties, r.status, steps)
+                         r.min_cut_gap, r.near_ties, r.status, steps, r.msq_cos1,
+                         r.msq_cos2, r.chi0, r.chi0_n, r.fail_step)
 
     def observables(self, beta, lnz, m_h, m_h1, dbeta, dh, dh1):
         import numpy as np

@@ -24,6 +24,8 @@ from typing import List
 
 IMP_COS1 = 1
 IMP_COS2 = 2
+IMP_COS1_SQ = 4
+IMP_COS2_SQ = 8
 
 PREC_FP64 = 0
 PREC_FP32 = 1

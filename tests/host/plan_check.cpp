@@ -20,15 +20,19 @@ void emulate(const TablePlan &tp, const Launch &L, const std::vector<double> &A,
   for (int gi = 0; gi < L.ngroups; ++gi) {
     const GGroup &g = tp.groups[L.first_group + gi];
     auto T = [&](int64_t base, int i) { int64_t idx = base + i; CHECK(idx >= 0 && idx < (int64_t)tp.tab.size(), "tab idx"); return tp.tab[idx]; };
+    // contiguous groups: rows through the table, k and n as ranges (GroupedGemm::contig)
+    auto offA = [&](int m, int k) { return L.contig ? T(g.ar, m) + g.ac + k : T(g.ar, m) + T(g.ac, k); };
+    auto offB = [&](int k, int n) { return L.contig ? g.br + (int64_t)k * g.bc + n : T(g.br, k) + T(g.bc, n); };
+    auto offC = [&](int m, int n) { return L.contig ? T(g.ar, m) + g.cc + n : T(g.cr, m) + T(g.cc, n); };
     for (int m = 0; m < g.M; ++m) for (int n = 0; n < g.N; ++n) {
       double acc = 0;
       for (int k = 0; k < g.K; ++k) {
-        int64_t ia = T(g.ar, m) + T(g.ac, k), ib = T(g.br, k) + T(g.bc, n);
+        int64_t ia = offA(m, k), ib = offB(k, n);
         CHECK(ia >= 0 && ia < (int64_t)A.size(), "A off %lld", (long long)ia);
         CHECK(ib >= 0 && ib < (int64_t)B.size(), "B off %lld", (long long)ib);
         if (ia >= 0 && ia < (int64_t)A.size() && ib >= 0 && ib < (int64_t)B.size()) acc += A[ia] * B[ib];
       }
-      int64_t ic = T(g.cr, m) + T(g.cc, n);
+      int64_t ic = offC(m, n);
       CHECK(ic >= 0 && ic < (int64_t)C.size(), "C off");
       if (ic >= 0 && ic < (int64_t)C.size()) {
         C[ic] = alpha * acc + (beta == 0.0 ? 0.0 : beta * C[ic]);
@@ -106,18 +110,33 @@ void run_case(int Dh, int Dv, int Dn, int mod, int seed, const QSet &SX) {
     for (int l2 = 0; l2 < Dh; ++l2) for (int r2 = 0; r2 < Dh; ++r2) for (int i = 0; i < Dv; ++i) for (int d = 0; d < Dv; ++d)
       o[(size_t)SL.pos[(size_t)l2*Dv + i]*W + SL.pos[(size_t)r2*Dv + d]] = B[(((size_t)l2*Dh + r2)*Dv + i)*Dv + d]; return o; };
   for (int chunk : {Dn, (Dn + 1)/2, 1}) {
-    for (int variant = 0; variant < 3; ++variant) {
-      const std::vector<double> &A = (variant == 2) ? TX : T;
-      const std::vector<double> &B = (variant == 1) ? TX : T;
-      QSet sA = (variant == 2) ? SX : s0, sB = (variant == 1) ? SX : s0, sY = qset_sum(sA, sB, mod);
+    for (int variant = 0; variant < 4; ++variant) {
+      // 0: T T, 1: T TX, 2: TX T, 3: TX TX (split by the charge of A)
+      const std::vector<double> &A = (variant >= 2) ? TX : T;
+      const std::vector<double> &B = (variant == 1 || variant == 3) ? TX : T;
+      QSet sA = (variant >= 2) ? SX : s0, sB = (variant == 1 || variant == 3) ? SX : s0, sY = qset_sum(sA, sB, mod);
       auto B2 = swap_mid(B);
       std::vector<double> Tn((size_t)Dn*Dn*Dv*Dv, 0.0);
       for (int a0 = 0; a0 < Dn; a0 += chunk) {
         int a1 = std::min(Dn, a0 + chunk);
         TablePlan tp;
-        Launch lx = plan_proj_x(SL, a0, a1, sA, tp), ly = plan_proj_y(SL, a0, a1, sA, sB, tp), lt = plan_proj_t(SL, a0, a1, sY, tp);
+        Launch lx = plan_proj_x(SL, a0, a1, sA, tp), lt = plan_proj_t(SL, a0, a1, sY, tp);
         std::vector<double> X((size_t)(a1-a0)*W*W, NAN), Y((size_t)(a1-a0)*W*W, NAN);
-        emulate(tp, lx, P, A, X, 1, 0); emulate(tp, ly, X, B2, Y, 1, 0); emulate(tp, lt, Y, P, Tn, 1, 0);
+        emulate(tp, lx, P, A, X, 1, 0);
+        if (variant == 3 && sA.size() > 1 && sB.size() > 1) {
+          // the blocks are first cleared by a product that writes every one
+          // of them (as the engine's first Y launch of a chain does), then
+          // each charge of A adds its part
+          std::fill(Y.begin(), Y.end(), 0.0);
+          for (int c : sA) {
+            Launch ly = plan_proj_y(SL, a0, a1, QSet{c}, sB, tp);
+            emulate(tp, ly, X, B2, Y, 1, 1);
+          }
+        } else {
+          Launch ly = plan_proj_y(SL, a0, a1, sA, sB, tp);
+          emulate(tp, ly, X, B2, Y, 1, 0);
+        }
+        emulate(tp, lt, Y, P, Tn, 1, 0);
       }
       auto R = proj_ref(A, B);
       double maxerr = 0; for (size_t e = 0; e < R.size(); ++e) maxerr = std::max(maxerr, std::fabs(R[e] - Tn[e]));
