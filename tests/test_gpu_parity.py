@@ -10,15 +10,15 @@ does not fix what the method keeps:
 * the cut passes between two nearly degenerate states of ONE symmetry
   sector (within-sector gap < 1e-10 lambda_1): which directions of that
   pair are kept is fixed only to eps ||E|| / gap by any FP64 eigensolver;
-* the gap between the last kept and the first dropped state lies between
-  1e-14 and 1e-10 lambda_1, where the tie rule's grouping (1e-12) is itself
-  decided by rounding.
+* the gap between the last kept and the first dropped state lies within a
+  decade of the tie rule's grouping width (1e-12 lambda_1), where that
+  grouping is itself decided by rounding.
 An exact tie across sectors (|gap| < 1e-14: at zero field the charge-
 conjugate sectors q and -q have equal spectra) is settled exactly by the tie
-rule and is not ambiguous. The oracle reports the within-sector gap per step
-(stored runs written before it did: at zero field the exact ties are the
-charge-conjugate pairs, in different sectors; with fields any |gap| < 1e-10
-counts). Per-step values are compared up to the first ambiguous step; runs
+rule and is not ambiguous. The oracle reports the within-sector gap per step.
+Stored runs written before it did count any |gap| in [1e-14, 1e-10) as
+ambiguous at zero field (the pair could share a sector) and any
+|gap| < 1e-10 with fields. Per-step values are compared up to the first ambiguous step; runs
 with one compare ln Z/V and m at ten times the oracle's own spread over
 equally valid eigensolves (stored per golden as "spread"). The single-point
 workload has its own bound (its flow amplifies 1-ulp changes of the input).
@@ -50,12 +50,13 @@ def ctx():
 
 AMBIG_GAP = 1e-10
 EXACT_TIE = 1e-14
+TIE_BAND = (1e-13, 1e-11)   # a decade around the tie rule's grouping width
 
 
 def _ambiguous(cut_gap, sector_gap, u1, known):
     if known:
         return (sector_gap is not None and sector_gap < AMBIG_GAP) or \
-            EXACT_TIE <= abs(cut_gap) < AMBIG_GAP
+            TIE_BAND[0] <= abs(cut_gap) <= TIE_BAND[1]
     if u1:
         return EXACT_TIE <= abs(cut_gap) < AMBIG_GAP
     return abs(cut_gap) < AMBIG_GAP
