@@ -11,16 +11,23 @@ covers every step of the path.
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
 Prints one JSON line. value = coarse-graining steps per second (40 per run).
-Two more legs ride on the same line (both skippable):
+More legs ride on the same line (each skippable):
 * "precision": the same workload with the projection contractions in FP32
-  and in split-BF16x3 (FP64 for the first 12 / 16 steps), steps/s and
-  |d ln Z/V| against the FP64 run;
+  and in split-BF16x3, with every step reduced and with the first 12 / 16
+  steps in FP64: steps/s, |d ln Z/V| and |d C_v| against the FP64 GPU runs
+  and against the stored oracle values, |d <cos 2 theta>| at h1 = 1.1e-3;
+* "susceptibility": the workload with the second-moment chains (zero-field
+  chi and chi_n from one run);
+* "harmonic", "transition": the harmonic q = 3, 4 and the transition-
+  temperature procedure;
 * "batched": a stratified 16-point subset of the 16 x 16 (beta, Delta) grid
-  (4 points per Dcut in {24, 32, 48, 64}), three runs per point (beta - db,
-  beta, beta + db; f and C_v): points/s of the plain FP64 path (runs one
-  after another), and, after the per-Dcut tile autotuner, of one batch on 16
-  worker streams (16 hardware queues for the process) in FP64 and with
-  BF16x3 + schedule; max |d f| of the latter against FP64.
+  (4 points per Dcut in {24, 32, 48, 64}) by the zero-field route, three
+  runs per point (beta -+ db for C_v, beta with the second-moment chains for
+  chi, chi_n): points/s of the plain FP64 path (runs one after another) and,
+  after the per-Dcut tile autotuner, of one batch on 16 worker streams (16
+  hardware queues for the process) in FP64, FP32 and BF16x3 with schedules;
+  max |d f| and relative d chi against FP64; the same for the Dcut = 64
+  points alone.
 """
 
 from __future__ import annotations
@@ -68,30 +75,75 @@ def measured_traffic():
     return rec["hbm_bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
 
 
+def stored_oracle(name):
+    """ln Z/V (and the point) of a stored oracle run (tests/golden, written by
+    the oracle's golden script), or None."""
+    path = os.path.join(ROOT, "tests", "golden", name + ".json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
 def precision_leg(ctx, pt, r64):
-    """Reduced-precision contraction forms on the bench workload: steps/s and
-    |d ln Z/V| against the FP64 run, and d C_v from zero-field runs at
-    beta +- 1e-3 (C_v = beta^2 d^2(ln Z/V)/d beta^2, central differences)."""
+    """Reduced-precision contraction forms on the bench workload (Dcut = 64):
+    steps/s, and the errors of ln Z/V and C_v (central differences at
+    beta +- 1e-3) against the FP64 GPU runs and against the stored oracle
+    values, for every step reduced (fp64_steps = 0) and with the first
+    steps kept in FP64; <cos 2 theta> at h1 = 1.1e-3 (Dcut = 48) against its
+    stored oracle value."""
     from paper_2609_20536_amd import workloads as W
     out = {}
     db = W.BETA_FD_STEP
+    gold = [stored_oracle(n) for n in ("prec_d64_pure_m", "prec_d64_pure", "prec_d64_pure_p")]
+    l_or = [g["lnz_per_site"] for g in gold] if all(gold) else None
 
-    def cv(prec, k):
+    def lnz3(prec, k):
         base = pt.with_(impurities=0, prec=prec, fp64_steps=k)
-        l = [ctx.run(base.with_(beta=pt.beta + s)).lnz_per_site for s in (-db, 0.0, db)]
+        return [ctx.run(base.with_(beta=pt.beta + s)).lnz_per_site for s in (-db, 0.0, db)]
+
+    def cv(l):
         return pt.beta ** 2 * (l[0] - 2.0 * l[1] + l[2]) / db ** 2
-    cv64 = cv(W.PREC_FP64, 0)
-    out["cv_fp64"] = cv64
-    for name, prec, k in (("fp32", W.PREC_FP32, 12), ("bf16x3", W.PREC_BF16X3, 16)):
-        q = pt.with_(prec=prec, fp64_steps=k)
-        ctx.run(q)
-        t0 = time.perf_counter()
-        r = ctx.run(q)
-        el = time.perf_counter() - t0
-        out[name] = {"fp64_steps": k, "steps_per_s": q.nsteps / el,
-                     "abs_dlnz_per_site": abs(r.lnz_per_site - r64.lnz_per_site),
-                     "abs_dcv": abs(cv(prec, k) - cv64)}
+    l64 = lnz3(W.PREC_FP64, 0)
+    out["cv_fp64"] = cv(l64)
+    if l_or:
+        out["fp64_vs_oracle"] = {"abs_dlnz_per_site": abs(l64[1] - l_or[1]),
+                                 "abs_dcv": abs(cv(l64) - cv(l_or))}
+    gm = stored_oracle("cv_b1.0_h1p")
+    for name, prec, sched in (("fp32", W.PREC_FP32, (0, 12)), ("bf16x3", W.PREC_BF16X3, (0, 16))):
+        rows = {}
+        for k in sched:
+            q = pt.with_(prec=prec, fp64_steps=k)
+            ctx.run(q)
+            t0 = time.perf_counter()
+            r = ctx.run(q)
+            el = time.perf_counter() - t0
+            l = lnz3(prec, k)
+            row = {"fp64_steps": k, "steps_per_s": q.nsteps / el,
+                   "abs_dlnz_vs_fp64_gpu": abs(r.lnz_per_site - r64.lnz_per_site),
+                   "abs_dcv_vs_fp64_gpu": abs(cv(l) - cv(l64))}
+            if l_or:
+                row["abs_dlnz_vs_oracle"] = abs(l[1] - l_or[1])
+                row["abs_dcv_vs_oracle"] = abs(cv(l) - cv(l_or))
+            if gm:
+                g = ctx.run(W.Point(**{**gm["point"], "prec": prec, "fp64_steps": k}))
+                row["abs_dm_cos2_h1_vs_oracle"] = abs(g.m_cos2 - gm["m_cos2"])
+            rows[f"k{k}"] = row
+        out[name] = rows
     return out
+
+
+def susceptibility_leg(ctx, pt):
+    """The bench workload with both second-moment chains (zero-field chi and
+    chi_n from one run): steps/s and the values."""
+    from paper_2609_20536_amd import workloads as W
+    p = pt.with_(impurities=W.IMP_COS1_SQ | W.IMP_COS2_SQ)
+    ctx.run(p)
+    t0 = time.perf_counter()
+    r = ctx.run(p)
+    el = time.perf_counter() - t0
+    return {"steps_per_s": p.nsteps / el, "chi": r.chi0, "chi_n": r.chi0_n,
+            "msq_cos1": r.msq_cos1, "lnz_per_site": r.lnz_per_site}
 
 
 def harmonic_leg(ctx, pt):
@@ -128,47 +180,49 @@ def transition_leg(ctx):
 
 
 def batched_leg(ctx, note):
-    """Points/s of f and C_v over a stratified grid subset, one batch."""
+    """Points/s of (f, C_v, chi, chi_n) over a stratified grid subset by the
+    zero-field route (three runs per point: beta -+ 1e-3, and beta with the
+    second-moment chains), as one batch; plain FP64 one run after another
+    against batched FP64 and batched reduced precision; also the Dcut = 64
+    points alone."""
+    from paper_2609_20536_amd import surrogate as S
     from paper_2609_20536_amd import workloads as W
     gp = W.grid_points()
     sub = []
     for d in W.GRID_DCUTS:
         sub += [g for g in gp if g.dcut == d][:4]
-    db = W.BETA_FD_STEP
-
-    def runs(prec, k):
-        return [W.Point(beta=g.beta + s, delta=g.delta, nmax=10, dcut=g.dcut, nsteps=40,
-                        impurities=0, prec=prec, fp64_steps=k)
-                for g in sub for s in (-db, 0.0, db)]
     tiles = ctx.autotune(W.Point(beta=1.0, delta=0.5, nmax=10, dcut=24, nsteps=10,
                                  impurities=0), list(W.GRID_DCUTS))
     note("bench: tile autotuner done")
-    out = {"points": len(sub), "runs_per_point": 3, "workers": BATCH_WORKERS,
+    out = {"points": len(sub), "runs_per_point": 3,
+           "route": "zero field: beta -+ 1e-3 for C_v, second-moment chains for chi, chi_n",
+           "workers": BATCH_WORKERS,
            "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
            "plain": "the same runs one after another on one stream (FP64)",
            "tiles": {str(k): v[0] for k, v in tiles.items()}}
-    res = {}
-    for name, prec, k, workers in (("plain_fp64", W.PREC_FP64, 0, 1),
-                                   ("fp64", W.PREC_FP64, 0, BATCH_WORKERS),
-                                   ("bf16x3", W.PREC_BF16X3, 16, BATCH_WORKERS)):
-        pts = runs(prec, k)
-        ctx.run_batch(pts[:3], workers=workers)
-        t0 = time.perf_counter()
-        rr = ctx.run_batch(pts, workers=workers)
-        el = time.perf_counter() - t0
-        if any(r.status != 0 for r in rr):
-            raise SystemExit(f"batched {name}: a run failed")
-        res[name] = rr
-        out[name + "_points_per_s"] = len(sub) / el
-        note(f"bench: {name} ({workers} worker(s)) done in {el:.1f}s")
-    out["speedup_bf16x3_batched_vs_plain_fp64"] = (out["bf16x3_points_per_s"] /
-                                                   out["plain_fp64_points_per_s"])
-    # f = -(1/beta) ln Z/V at the centre runs
-    df = 0.0
-    for i, g in enumerate(sub):
-        a, b = res["fp64"][3 * i + 1], res["bf16x3"][3 * i + 1]
-        df = max(df, abs(a.lnz_per_site - b.lnz_per_site) / g.beta)
-    out["max_abs_df_bf16x3_vs_fp64"] = df
+    for label, pts in (("stratified", sub), ("d64", [g for g in sub if g.dcut == 64])):
+        res = {}
+        row = {"points": len(pts)}
+        for name, prec, k, workers in (("plain_fp64", W.PREC_FP64, 0, 1),
+                                       ("fp64", W.PREC_FP64, 0, BATCH_WORKERS),
+                                       ("fp32", W.PREC_FP32, 12, BATCH_WORKERS),
+                                       ("bf16x3", W.PREC_BF16X3, 16, BATCH_WORKERS)):
+            S.grid_observables_zero_field(ctx, pts[:1], workers=workers, prec=prec,
+                                          fp64_steps=k)
+            t0 = time.perf_counter()
+            obs, _ = S.grid_observables_zero_field(ctx, pts, workers=workers, prec=prec,
+                                                   fp64_steps=k)
+            el = time.perf_counter() - t0
+            res[name] = obs
+            row[name + "_points_per_s"] = len(pts) / el
+            note(f"bench: {label} {name} ({workers} worker(s)) done in {el:.1f}s")
+        for name in ("fp32", "bf16x3"):
+            row[f"speedup_{name}_batched_vs_plain_fp64"] = (row[name + "_points_per_s"] /
+                                                            row["plain_fp64_points_per_s"])
+            row[f"max_abs_df_{name}_vs_fp64"] = float(abs(res[name][:, 0] - res["fp64"][:, 0]).max())
+            row[f"max_rel_dchi_{name}_vs_fp64"] = float(
+                (abs(res[name][:, 2] - res["fp64"][:, 2]) / res["fp64"][:, 2]).max())
+        out[label] = row
     return out
 
 
@@ -188,6 +242,15 @@ def cpu_baseline(dcut: int, nimp: int, frac_cols: int = 8):
         cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:  # pragma: no cover
         cores = os.cpu_count() or 1
+    cpu_model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:  # pragma: no cover
+        pass
     rng = np.random.default_rng(20536)
     D = dcut
     mult = np.maximum(1, np.round(np.exp(-0.5 * (np.arange(-7, 8) / 3.0) ** 2) * 8)).astype(int)
@@ -213,6 +276,7 @@ def cpu_baseline(dcut: int, nimp: int, frac_cols: int = 8):
         "value": 1.0 / per_step,
         "unit": "HOTRG steps/s",
         "cores": int(cores),
+        "cpu": cpu_model,
         "kind": "oracle",
         "sample": (f"one y-step at Dcut={D} on a synthetic charge-conserving tensor: "
                    f"environments {t_env:.2f}s + sector eigensolves {t_eig:.2f}s + "
@@ -232,6 +296,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-harmonic", action="store_true")
     ap.add_argument("--no-transition", action="store_true")
+    ap.add_argument("--no-susceptibility", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="one plain 1 GiB device copy first (known HBM bytes for counter scaling)")
     ap.add_argument("--phases", action="store_true", help="one extra untimed run with phase timers")
@@ -334,6 +399,9 @@ def main():
     if not args.no_precision:
         line["precision"] = precision_leg(ctx, pt, r)
         note("bench: precision leg done")
+    if not args.no_susceptibility:
+        line["susceptibility"] = susceptibility_leg(ctx, pt)
+        note("bench: susceptibility leg done")
     if not args.no_harmonic:
         line["harmonic"] = harmonic_leg(ctx, pt)
         note("bench: harmonic-q leg done")

@@ -53,6 +53,31 @@ def grid_observables(ctx: Context, points: Sequence[Tuple[float, float]], dcut: 
     return ctx.observables(beta, lnz, mh, mh1, db, W.FIELD_FD_STEP, W.FIELD_FD_STEP)
 
 
+def grid_observables_zero_field(ctx: Context, grid: Sequence, workers: int = 16,
+                                prec: int = W.PREC_FP64, fp64_steps: int = 0,
+                                nmax: int = 10, nsteps: int = 40,
+                                db: float = W.BETA_FD_STEP) -> Tuple[np.ndarray, list]:
+    """(f, C_v, chi, chi_n) for grid points with their own Dcut (objects with
+    beta, delta, dcut), three runs per point (W.zero_field_runs): C_v by the
+    library's central difference, chi and chi_n at zero field from the
+    second-moment chains. Returns the (n, 4) array and the run results."""
+    runs = []
+    for g in grid:
+        runs += W.zero_field_runs(g.beta, g.delta, g.dcut, nmax, nsteps, prec, fp64_steps, db)
+    res = ctx.run_batch(runs, workers=workers)
+    bad = [i for i, r in enumerate(res) if r.status != 0]
+    if bad:
+        raise RuntimeError(f"{len(bad)} HOTRG runs failed (first: {runs[bad[0]]})")
+    n = len(grid)
+    lnz = np.array([[res[3 * k + j].lnz_per_site for j in range(3)] for k in range(n)])
+    zero = np.zeros((n, 2))
+    beta = np.array([g.beta for g in grid], dtype=np.float64)
+    obs = ctx.observables(beta, lnz, zero, zero, db, 1.0, 1.0)
+    obs[:, 2] = [res[3 * k + 1].chi0 for k in range(n)]
+    obs[:, 3] = [res[3 * k + 1].chi0_n for k in range(n)]
+    return obs, res
+
+
 def cv_along_beta(ctx: Context, delta: float, betas: Sequence[float], dcut: int,
                   nmax: int, nsteps: int, workers: int = 8,
                   db: float = W.BETA_FD_STEP) -> np.ndarray:

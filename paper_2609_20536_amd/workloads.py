@@ -152,6 +152,24 @@ def observable_runs(beta: float, delta: float, dcut: int, nmax: int = 10,
     ]
 
 
+def zero_field_runs(beta: float, delta: float, dcut: int, nmax: int = 10,
+                    nsteps: int = 40, prec: int = PREC_FP64,
+                    fp64_steps: int = 0, db: float = BETA_FD_STEP) -> List[Point]:
+    """The three runs behind (f, C_v, chi, chi_n) at one (beta, Delta) by the
+    zero-field route: beta-db and beta+db without chains, and beta with the
+    second-moment chains of cos theta and cos 2 theta (chi, chi_n at h = 0).
+
+    Order: beta-db, beta (chains), beta+db.
+    """
+    base = Point(beta=beta, delta=delta, nmax=nmax, dcut=dcut, nsteps=nsteps,
+                 impurities=0, prec=prec, fp64_steps=fp64_steps)
+    return [
+        base.with_(beta=beta - db),
+        base.with_(impurities=IMP_COS1_SQ | IMP_COS2_SQ),
+        base.with_(beta=beta + db),
+    ]
+
+
 # ---------------------------------------------------------------------------
 # Learned surrogate: seeded initial weights and train/validation split.
 # ---------------------------------------------------------------------------
