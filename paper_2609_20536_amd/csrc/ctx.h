@@ -44,6 +44,8 @@ struct gxy_ctx {
   // pinned arenas for the projection tables of a step, by step parity
   void *arena[2] = {nullptr, nullptr};
   size_t arena_bytes[2] = {0, 0};
+  bool arena_pageable[2] = {false, false};  // arena[q] lives in arena_host[q]
+  std::vector<char> arena_host[2];
   hipEvent_t arena_ev[2] = {nullptr, nullptr};
   bool arena_pending[2] = {false, false};
   // second stream for the impurity projections, and the events that order

@@ -159,19 +159,29 @@ static Plan make_plan(const gxy_point &p, size_t chunk_bytes, bool allow_overlap
   pl.chunk_elems = ac * per_a_max;
   pl.overlap = allow_overlap && sym_of(p) != SYM_NONE && pl.nimp > 0 && ac >= pl.maxDn &&
                !getenv("GXY_NO_OVERLAP");
-  // bounds of the charge-block tables of one step (see plan.hip): every row,
-  // reduction and column index appears in at most |S| <= 2 groups per table
-  // table variants per chunk (one X, Y and T' plan each): the pure tensor
-  // one, a one-insertion chain two, a second-moment chain three
+  // Bounds of the charge-block tables of one step (see plan.hip), per launch
+  // with s the number of charges of its charged factor (a column of X, a row
+  // of Y or T' appears in at most s groups; a label slot repeats the row and
+  // reduction lists at most Dv times): X 2 ac Dh Dv + 2 Dh Dv + 2 s Dh Dv^2,
+  // Y (rows only) s ac Dh Dv, T' 2 Dh^2 Dv + 2 Dn Dv + 2 s ac Dv^2.
+  // Launches per chunk: pure X, Y, T'; a one-insertion chain (charges s1)
+  // Y(1) X(s1) Y(s1) T'(s1); a second-moment chain (charges 3, first moment
+  // 2) Y(1) X(3) Y(3) X(2) Y(1) Y(1) T'(3).
+  const Chains chn = chains_of(p);
   const int64_t nvar = 1 + 3 * pl.nimp;
   for (const StepDims &sd : pl.steps) {
     const int64_t Dh = sd.dh, Dv = sd.dv, Dn = sd.dn, MN = Dh * Dv;
     const int64_t nch = (Dn + ac - 1) / ac;
     const int64_t env = 2 * (8 * MN + 4 * Dh * Dh + Dv * Dv) + 64;
-    const int64_t proj = nch * nvar *
-                             (2 * (2 * Dn * Dh + 2 * Dh + 4 * Dh * Dv * Dv) +
-                              2 * (Dn * Dh * Dv + 2 * MN + MN) +
-                              2 * (2 * Dn * Dv * Dv + 2 * Dh * Dh + 2 * Dn)) + 64;
+    const int64_t acn = std::min<int64_t>(ac, Dn);
+    auto bx = [&](int64_t sc) { return 2 * acn * Dh * Dv + 2 * Dh * Dv + 2 * sc * Dh * Dv * Dv + 64; };
+    auto by = [&](int64_t sc) { return sc * acn * Dh * Dv + 64; };
+    auto bt = [&](int64_t sc) { return 2 * Dh * Dh * Dv + 2 * Dn * Dv + 2 * sc * acn * Dv * Dv + 64; };
+    int64_t per_chunk = bx(1) + by(1) + bt(1);
+    for (int k = 0; k < chn.n; ++k)
+      per_chunk += chn.first[k] < 0 ? by(1) + bx(2) + by(2) + bt(2)
+                                    : by(1) + bx(3) + by(3) + bx(2) + 2 * by(1) + bt(3);
+    const int64_t proj = nch * per_chunk + 64;
     pl.tab_env = std::max(pl.tab_env, env);
     pl.tab_proj = std::max(pl.tab_proj, proj);
     pl.grp_env = std::max(pl.grp_env, 2 * (2 * MN + Dh * Dh) + 16);
@@ -377,10 +387,19 @@ static void proj_stage_begin(gxy_ctx *ctx, int q, ProjArena &A, int64_t cap, int
   const size_t cb = ((size_t)cap + 255) & ~(size_t)255;
   const size_t need = cb + (size_t)perm_cap * sizeof(int32_t);
   if (ctx->arena_bytes[q] < need) {
-    if (ctx->arena[q]) GXY_HIP(hipHostFree(ctx->arena[q]));
+    if (ctx->arena[q] && !ctx->arena_pageable[q]) GXY_HIP(hipHostFree(ctx->arena[q]));
     ctx->arena[q] = nullptr;
     ctx->arena_bytes[q] = 0;
-    GXY_HIP(hipHostMalloc(&ctx->arena[q], need, hipHostMallocDefault));
+    ctx->arena_pageable[q] = false;
+    if (hipHostMalloc(&ctx->arena[q], need, hipHostMallocDefault) != hipSuccess) {
+      // pinned memory exhausted (many worker contexts): pageable host
+      // memory, whose copies the runtime completes before returning
+      (void)hipGetLastError();
+      ctx->arena_host[q].resize(need + 256);
+      char *b = ctx->arena_host[q].data();
+      ctx->arena[q] = b + ((256 - ((uintptr_t)b & 255)) & 255);
+      ctx->arena_pageable[q] = true;
+    }
     ctx->arena_bytes[q] = need;
   }
   A.base = (char *)ctx->arena[q];
@@ -1118,6 +1137,9 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
     // buffers of this step's parity; the impurity stream read them last in
     // step n - 2
     const int par = n & 1;
+    // host arena of the step's tables: by parity with the impurity stream,
+    // else one (single-stream runs drain it before reuse)
+    const int aq = pl.overlap ? par : 0;
     b.P = b.Pb[par];
     b.X = b.Xb[par];
     b.T2 = b.T2b[par];
@@ -1284,9 +1306,13 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
       // soon as it is ready, so the device runs one launch while the host
       // plans the next.
       ProjArena arena;
-      proj_stage_begin(ctx, par, arena, pl.proj_bytes, pl.maxW, s);
+      proj_stage_begin(ctx, aq, arena, pl.proj_bytes, pl.maxW, s);
       if (!ctx->copy_stream && !single_stream(ctx))
         GXY_HIP(hipStreamCreateWithFlags(&ctx->copy_stream, hipStreamNonBlocking));
+      // this step's table copies overwrite slices of the device area that
+      // earlier launches of the compute stream read (the same area every
+      // step without the impurity stream): the copy stream starts after them
+      if (!single_stream(ctx)) stream_after(ctx, ctx->copy_stream, s, 6);
       // (proj_stage_begin has seen the last launches that read this
       // parity's device slices complete, two steps ago, so the side stream
       // may overwrite them)
@@ -1455,7 +1481,7 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
     }
     // the step's tables have been read by both streams' launches once the
     // impurity stream gets here
-    if (sym != SYM_NONE) proj_stage_done(ctx, par, si);
+    if (sym != SYM_NONE) proj_stage_done(ctx, aq, si);
     lh = new_lh;
     if (sd.xstep) {
       launch_swap_pairs(b.T, b.Tn, Dh, Dh, Dv, Dv, s);
@@ -1656,7 +1682,7 @@ gxy_status gxy_destroy(gxy_ctx *ctx) {
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   for (int q = 0; q < 2; ++q) {
     if (ctx->arena_ev[q]) (void)hipEventDestroy(ctx->arena_ev[q]);
-    if (ctx->arena[q]) (void)hipHostFree(ctx->arena[q]);
+    if (ctx->arena[q] && !ctx->arena_pageable[q]) (void)hipHostFree(ctx->arena[q]);
   }
   for (hipEvent_t e : ctx->pipe_ev)
     if (e) (void)hipEventDestroy(e);
