@@ -49,6 +49,8 @@
  *                          tile fill); results do not depend on it
  *   GXY_BATCH_WORKERS      default worker count of gxy_run_batch (4)
  *   GXY_TIMING             phase timers (gxy_phase_times)
+ *   GXY_INJECT_NAN_STEP    test hook of the failure path: one NaN is put into
+ *                          the site tensor after step n's normalisation
  *   GXY_HOT_EVENTS         events around every launch of the D^7 product
  *                          (gxy_hot_kernel_stats)
  */
@@ -124,7 +126,9 @@ typedef struct {
   double min_cut_gap;   /* min over steps of (lam_D - lam_{D+1}) / lam_1     */
   int32_t near_ties;    /* number of tie-rule activations                   */
   int32_t status;       /* gxy_status of this run                            */
-  int32_t fail_step;    /* step at which it failed, -1 if none               */
+  int32_t fail_step;    /* -1 if none; GXY_ENUMERIC: the step whose
+                           environments or norm were first not finite, or
+                           nsteps if only the final trace failed            */
   int32_t nsteps_done;
   double msq_cos1;      /* <m^2>, m = (1/V) sum_i cos theta_i (GXY_IMP_COS1_SQ;
                            else NaN); V = 2^nsteps                          */

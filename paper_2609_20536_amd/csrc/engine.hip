@@ -1132,6 +1132,7 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
   res.min_cut_gap = INFINITY;
 
   int32_t *hp = ctx->noalloc ? (int32_t *)ctx->noalloc_host : (int32_t *)ctx->pinned;
+  const int inject_nan_step = (int)env_size("GXY_INJECT_NAN_STEP", 0);
   for (int n = 1; n <= p.nsteps; ++n) {
     const StepDims &sd = pl.steps[n - 1];
     // buffers of this step's parity; the impurity stream read them last in
@@ -1256,6 +1257,13 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
       info.ties = (int)hd[5];
       info.truncated = 1;
       const double trE = hd[6];
+      if (!isfinite(info.lam_max) || !isfinite(trE) || !isfinite(info.eps_l) ||
+          !isfinite(info.eps_r)) {
+        // the environments of this step are not finite: the run stops here
+        res.fail_step = n;
+        res.nsteps_done = n - 1;
+        fail(GXY_ENUMERIC, "non-finite environment spectrum at step " + std::to_string(n));
+      }
       const double eps = info.side ? info.eps_r : info.eps_l;
       if (trE > 0) res.max_trunc_err = std::max(res.max_trunc_err, eps / trE);
       res.min_cut_gap = std::min(res.min_cut_gap, info.cut_gap);
@@ -1473,6 +1481,9 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
     nT = (int64_t)Dh * Dh * Dv * Dv;
     launch_fro_norm(b.Tn, nT, b.partial, b.nrm + 3 * n, s);
     launch_scale(b.Tn, nT, b.nrm + 3 * n + 2, s);
+    // test hook of the failure path: one NaN planted after step n's
+    // normalisation (GXY_INJECT_NAN_STEP = n)
+    if (inject_nan_step == n) launch_fill(b.Tn, 1, NAN, s);
     std::swap(b.T, b.Tn);
     stream_after(ctx, si, s, 2);
     for (int k = 0; k < nimp; ++k) {
@@ -1524,11 +1535,21 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
   res.m_cos1 = hd[1];
   res.m_cos2 = hd[2];
   res.status = (int32_t)hd[3];
+  if (res.status) {
+    // the first step whose norm is not finite, else the final trace
+    res.fail_step = p.nsteps;
+    for (int n = 1; n <= p.nsteps; ++n)
+      if (!isfinite(hd[8 + n])) {
+        res.fail_step = n;
+        break;
+      }
+  } else {
+    res.fail_step = -1;
+  }
   res.msq_cos1 = hd[4];
   res.msq_cos2 = hd[5];
   res.chi0 = hd[6];
   res.chi0_n = hd[7];
-  res.fail_step = res.status ? p.nsteps : -1;
   res.nsteps_done = p.nsteps;
   if (!isfinite(res.min_cut_gap)) res.min_cut_gap = 0.0;
   for (int n = 1; n <= p.nsteps; ++n) log.steps[n - 1].lnc = hd[8 + n];
@@ -1755,8 +1776,20 @@ gxy_status gxy_run(gxy_ctx *ctx, const gxy_point *pt, gxy_result *out) {
   gxy_result r{};
   r.status = GXY_OK;
   r.fail_step = -1;
-  gxy::run_one(ctx, *pt, r, ctx->logs[0]);
+  try {
+    gxy::run_one(ctx, *pt, r, ctx->logs[0]);
+  } catch (const Error &e) {
+    if (e.status != GXY_ENUMERIC) throw;
+    // a numerical failure during the run: the result names the step
+    r.status = e.status;
+    r.lnz_per_site = r.m_cos1 = r.m_cos2 = NAN;
+    r.msq_cos1 = r.msq_cos2 = r.chi0 = r.chi0_n = NAN;
+    *out = r;
+    throw;
+  }
   *out = r;
+  if (r.status) ctx->last_error = "non-finite result (first failing step " +
+                                  std::to_string(r.fail_step) + ")";
   return (gxy_status)r.status;
   GXY_API_END(ctx)
 }

@@ -270,7 +270,7 @@ __global__ void select_side_wide_kernel(SelectArgs a, double *side_res,
 
   // 2. greedy picks with the tie rule
   double lam1 = -DBL_MAX;
-  int ties = 0;
+  int ties = 0, bad = 0;
   for (int p = 0; p < a.dcut; ++p) {
     double v = -DBL_MAX;
     for (int c = threadIdx.x; c < nc; c += kSelThreads)
@@ -290,6 +290,16 @@ __global__ void select_side_wide_kernel(SelectArgs a, double *side_res,
     kbest = block_min_u64(kbest, redu);
     cnt = block_sum_i(cnt, redi);
     if (cnt > 1) ++ties;
+    if (cnt == 0) {
+      // no finite candidate left (a non-finite spectrum): a valid state
+      // stands in and the side's lambda_1 becomes NaN for the host to see
+      bad = 1;
+      if (threadIdx.x == 0) {
+        side_pick_sec[side * a.dcut + p] = 0;
+        side_pick_col[side * a.dcut + p] = 0;
+        side_pick_rank[side * a.dcut + p] = 0;
+      }
+    }
     for (int c = threadIdx.x; c < nc; c += kSelThreads) {
       if (!taken[c] && lam[c] >= top - tol &&
           tie_key(a.d_sec_label[csec[c]], crank[c]) == kbest) {
@@ -320,7 +330,7 @@ __global__ void select_side_wide_kernel(SelectArgs a, double *side_res,
   if (threadIdx.x == 0) {
     side_res[side * 8 + 0] = eps;
     side_res[side * 8 + 1] = tr;
-    side_res[side * 8 + 2] = lam1;
+    side_res[side * 8 + 2] = bad ? NAN : lam1;
     side_res[side * 8 + 3] = lam1 > 0.0 ? (minkept - maxdisc) / lam1 : 0.0;
     side_res[side * 8 + 4] = (double)ties;
   }
@@ -416,7 +426,7 @@ __global__ __launch_bounds__(kSelThreads) void select_side_kernel(
 
   // 2. greedy picks with the tie rule
   double lam1 = -DBL_MAX;
-  int ties = 0;
+  int ties = 0, bad = 0;
   for (int p = 0; p < a.dcut; ++p) {
     double v = -DBL_MAX;
 #pragma unroll
@@ -454,6 +464,16 @@ __global__ __launch_bounds__(kSelThreads) void select_side_kernel(
       cnt += wcnt[w];
     }
     if (cnt > 1) ++ties;
+    if (cnt == 0) {
+      // no finite candidate left (a non-finite spectrum): a valid state
+      // stands in and the side's lambda_1 becomes NaN for the host to see
+      bad = 1;
+      if (tid == 0) {
+        side_pick_sec[side * a.dcut + p] = 0;
+        side_pick_col[side * a.dcut + p] = 0;
+        side_pick_rank[side * a.dcut + p] = 0;
+      }
+    }
     int kw = -1;   // the one candidate with the winning key, if this thread holds it
 #pragma unroll
     for (int k = 0; k < kSelPer; ++k)
@@ -490,7 +510,7 @@ __global__ __launch_bounds__(kSelThreads) void select_side_kernel(
   if (tid == 0) {
     side_res[side * 8 + 0] = eps;
     side_res[side * 8 + 1] = tr;
-    side_res[side * 8 + 2] = lam1;
+    side_res[side * 8 + 2] = bad ? NAN : lam1;
     side_res[side * 8 + 3] = lam1 > 0.0 ? (minkept - maxdisc) / lam1 : 0.0;
     side_res[side * 8 + 4] = (double)ties;
   }
@@ -501,7 +521,9 @@ __global__ void select_final_kernel(SelectArgs a, const double *side_res,
                                     const int32_t *side_pick_col,
                                     const int32_t *side_pick_rank) {
   const double epsL = side_res[0], epsR = side_res[8];
-  const double lmax = fmax(side_res[2], side_res[10]);
+  // (a NaN lambda_1 marks a side without enough finite states: kept)
+  const double lmax = (isnan(side_res[2]) || isnan(side_res[10])) ? NAN
+                                                                   : fmax(side_res[2], side_res[10]);
   const int side = (epsR < epsL - a.side_tol * lmax) ? 1 : 0;
   const int D = a.dcut;
   const int32_t *ps = side_pick_sec + side * D;

@@ -27,3 +27,22 @@ def test_charge_plans_match_dense_contractions(tmp_path):
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stdout[-4000:]
     assert "fails 0" in r.stdout
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="g++ not available")
+def test_charge_plans_under_address_and_undefined_behaviour_sanitizers(tmp_path):
+    """The same checker built with AddressSanitizer and UBSan (host code
+    only): the planner's table construction makes no out-of-bounds access,
+    use after free or undefined arithmetic on these cases."""
+    exe = tmp_path / "plan_check_san"
+    cmd = ["g++", "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer",
+           "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-I", CSRC,
+           os.path.join(HERE, "host", "plan_check.cpp"),
+           "-x", "c++", os.path.join(CSRC, "plan.hip"), "-o", str(exe)]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-4000:]
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0")
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=600, env=env)
+    assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-4000:])
+    assert "fails 0" in r.stdout
