@@ -18,6 +18,9 @@ More legs ride on the same line (each skippable):
   and against the stored oracle values, |d <cos 2 theta>| at h1 = 1.1e-3;
 * "susceptibility": the workload with the second-moment chains (zero-field
   chi and chi_n from one run);
+* "d96": the same model at Dcut = 96: 40-step FP64, FP32 and BF16x3 runs
+  (steps/s, |d ln Z/V| against FP64) and FP64 against the stored oracle
+  values (3 and 20 steps);
 * "harmonic", "transition": the harmonic q = 3, 4 and the transition-
   temperature procedure;
 * "batched": a stratified 16-point subset of the 16 x 16 (beta, Delta) grid
@@ -130,6 +133,36 @@ def precision_leg(ctx, pt, r64):
                 row["abs_dm_cos2_h1_vs_oracle"] = abs(g.m_cos2 - gm["m_cos2"])
             rows[f"k{k}"] = row
         out[name] = rows
+    return out
+
+
+def d96_leg(ctx, note):
+    """The precision workload at Dcut = 96 (beta = 1.2, Delta = 0.7, |n| <= 10):
+    steps/s of 40-step FP64, FP32 and BF16x3 runs (first 16 steps FP64) and
+    their |d ln Z/V| against FP64; the 3- and 20-step FP64 runs against the
+    stored oracle values."""
+    from paper_2609_20536_amd import workloads as W
+    out = {}
+    base = W.precision_point(96, impurities=0)
+    for name, n in (("prec_d96_first3", 3), ("prec_d96_pure_n20", 20)):
+        g = stored_oracle(name)
+        if g:
+            r = ctx.run(base.with_(nsteps=n))
+            out[f"fp64_n{n}_abs_dlnz_vs_oracle"] = abs(r.lnz_per_site - g["lnz_per_site"])
+    r64 = None
+    for name, prec, k in (("fp64", W.PREC_FP64, 0), ("fp32", W.PREC_FP32, 16),
+                          ("bf16x3", W.PREC_BF16X3, 16)):
+        q = base.with_(prec=prec, fp64_steps=k)
+        t0 = time.perf_counter()
+        r = ctx.run(q)
+        el = time.perf_counter() - t0
+        row = {"fp64_steps": k, "steps_per_s": q.nsteps / el, "lnz_per_site": r.lnz_per_site}
+        if r64 is None:
+            r64 = r
+        else:
+            row["abs_dlnz_vs_fp64_gpu"] = abs(r.lnz_per_site - r64.lnz_per_site)
+        out[name] = row
+        note(f"bench: Dcut=96 {name} done in {el:.1f}s")
     return out
 
 
@@ -297,6 +330,7 @@ def main():
     ap.add_argument("--no-harmonic", action="store_true")
     ap.add_argument("--no-transition", action="store_true")
     ap.add_argument("--no-susceptibility", action="store_true")
+    ap.add_argument("--no-d96", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="one plain 1 GiB device copy first (known HBM bytes for counter scaling)")
     ap.add_argument("--phases", action="store_true", help="one extra untimed run with phase timers")
@@ -402,6 +436,8 @@ def main():
     if not args.no_susceptibility:
         line["susceptibility"] = susceptibility_leg(ctx, pt)
         note("bench: susceptibility leg done")
+    if not args.no_d96:
+        line["d96"] = d96_leg(ctx, note)
     if not args.no_harmonic:
         line["harmonic"] = harmonic_leg(ctx, pt)
         note("bench: harmonic-q leg done")
