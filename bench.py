@@ -23,6 +23,8 @@ More legs ride on the same line (each skippable):
   values (3 and 20 steps);
 * "harmonic", "transition": the harmonic q = 3, 4 and the transition-
   temperature procedure;
+* "surrogate": the surrogate's gain in locating the C_v peak at reduced
+  size (the full-size refinement is `paper_2609_20536_amd.scan --refine`);
 * "batched": a stratified 16-point subset of the 16 x 16 (beta, Delta) grid
   (4 points per Dcut in {24, 32, 48, 64}) by the zero-field route, three
   runs per point (beta -+ db for C_v, beta with the second-moment chains for
@@ -164,6 +166,22 @@ def d96_leg(ctx, note):
         out[name] = row
         note(f"bench: Dcut=96 {name} done in {el:.1f}s")
     return out
+
+
+def surrogate_leg(ctx):
+    """The surrogate's gain at reduced size: C_v peak location along beta at
+    Delta = 0.6 and 0.9 from six HOTRG points spread uniformly against six
+    placed around the surrogate's proposal (trained on a 21 x 6 grid of
+    Dcut = 16 runs, |n| <= 5, 24 steps), against a 41-point reference scan.
+    The full-size refinement (256-point grid, 512 proposals verified at
+    Dcut = 64) is `python -m paper_2609_20536_amd.scan --refine`."""
+    from paper_2609_20536_amd import surrogate as S
+    t0 = time.perf_counter()
+    out = S.gain_experiment(ctx, deltas=(0.6, 0.9), dcut=16, nmax=5, nsteps=24,
+                            train_grid=(21, 6), workers=16)
+    return {"seconds": time.perf_counter() - t0, "gain": out["gain"],
+            "mean_err_uniform": out["mean_err_uniform"],
+            "mean_err_guided": out["mean_err_guided"], "final_loss": out["final_loss"]}
 
 
 def susceptibility_leg(ctx, pt):
@@ -331,6 +349,7 @@ def main():
     ap.add_argument("--no-transition", action="store_true")
     ap.add_argument("--no-susceptibility", action="store_true")
     ap.add_argument("--no-d96", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="one plain 1 GiB device copy first (known HBM bytes for counter scaling)")
     ap.add_argument("--phases", action="store_true", help="one extra untimed run with phase timers")
@@ -438,6 +457,9 @@ def main():
         note("bench: susceptibility leg done")
     if not args.no_d96:
         line["d96"] = d96_leg(ctx, note)
+    if not args.no_surrogate:
+        line["surrogate"] = surrogate_leg(ctx)
+        note("bench: surrogate leg done")
     if not args.no_harmonic:
         line["harmonic"] = harmonic_leg(ctx, pt)
         note("bench: harmonic-q leg done")
