@@ -12,6 +12,9 @@ covers every step of the path.
 
 Prints one JSON line. value = coarse-graining steps per second (40 per run).
 More legs ride on the same line (each skippable):
+* "direct_lds": the workload with the FP64 projection products staged by
+  direct global -> LDS loads (GXY_GEMM_DMA=1): steps/s, the D^7 product's
+  launch time and MFMA fraction, |d ln Z/V| against the default staging;
 * "precision": the same workload with the projection contractions in FP32
   and in split-BF16x3, with every step reduced and with the first 12 / 16
   steps in FP64: steps/s, |d ln Z/V| and |d C_v| against the FP64 GPU runs
@@ -277,6 +280,37 @@ def batched_leg(ctx, note):
     return out
 
 
+def direct_lds_leg(ctx, pt, r, steps, note):
+    """The bench workload with the FP64 projection products staged by direct
+    global -> LDS loads (GXY_GEMM_DMA=1): steps/s, the D^7 product's launch
+    time and MFMA fraction, and ln Z/V against the default staging."""
+    import torch
+
+    os.environ["GXY_GEMM_DMA"] = "1"
+    try:
+        ctx.run(pt)
+        os.environ["GXY_HOT_EVENTS"] = "1"
+        ctx.hot_kernel_stats(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            rd = ctx.run(pt)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        os.environ.pop("GXY_HOT_EVENTS", None)
+        launches, ms, flops, _ = ctx.hot_kernel_stats(reset=True)
+    finally:
+        os.environ.pop("GXY_GEMM_DMA", None)
+        os.environ.pop("GXY_HOT_EVENTS", None)
+    avg = ms / max(launches, 1)
+    tf = (flops / max(launches, 1)) / (avg * 1e-3) / 1e12 if ms > 0 else 0.0
+    note("bench: direct-LDS leg done")
+    return {"kernel": "ggemm_dma_kernel (FP64, operands by global_load_lds)",
+            "steps_per_s": pt.nsteps * steps / el, "avg_launch_ms": avg, "achieved": tf,
+            "frac": tf / PEAK_FP64_TFLOPS,
+            "abs_dlnz_vs_default": abs(rd.lnz_per_site - r.lnz_per_site)}
+
+
 def cpu_baseline(dcut: int, nimp: int, frac_cols: int = 8):
     """Time the CPU oracle on a bounded sample of one coarse-graining step.
 
@@ -350,6 +384,7 @@ def main():
     ap.add_argument("--no-susceptibility", action="store_true")
     ap.add_argument("--no-d96", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-direct-lds", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="one plain 1 GiB device copy first (known HBM bytes for counter scaling)")
     ap.add_argument("--phases", action="store_true", help="one extra untimed run with phase timers")
@@ -434,7 +469,7 @@ def main():
         },
         "roofline": {
             "bound": "mfma",
-            "kernel": "projection D^7 grouped GEMM (ggemm_kernel, Y = X T, FP64)",
+            "kernel": "projection D^7 grouped GEMM (ggemm_contig_kernel, Y = X T, FP64)",
             "achieved": hot_tflops,
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
@@ -449,6 +484,8 @@ def main():
     }
     if phases:
         line["phases_ms"] = phases
+    if not args.no_direct_lds:
+        line["direct_lds"] = direct_lds_leg(ctx, pt, r, args.steps, note)
     if not args.no_precision:
         line["precision"] = precision_leg(ctx, pt, r)
         note("bench: precision leg done")

@@ -47,6 +47,11 @@
  *   GXY_PROJ_TILE          64 | 128 | 256: projection tile for every run
  *                          (else the autotuned one for the Dcut, else by
  *                          tile fill); results do not depend on it
+ *   GXY_GEMM_DMA           1: the FP64 projection products stage their
+ *                          operands by direct global -> LDS loads (faster
+ *                          products, another summation order: results agree
+ *                          with the default to rounding, and across tiles
+ *                          bit for bit)
  *   GXY_BATCH_WORKERS      default worker count of gxy_run_batch (4)
  *   GXY_TIMING             phase timers (gxy_phase_times)
  *   GXY_INJECT_NAN_STEP    test hook of the failure path: one NaN is put into

@@ -470,8 +470,9 @@ static void send_plan(gxy_ctx *ctx, const ProjArena &A, ProjJob &j, char *d_area
 
 static void run_launch(const Launch &L, const GGroup *d_grp, const int64_t *d_tab,
                        const double *A, const double *B, double *C, double alpha, double beta,
-                       hipStream_t s, int prec = GXY_PREC_FP64) {
+                       hipStream_t s, int prec = GXY_PREC_FP64, bool dma = false) {
   GroupedGemm g{};
+  g.dma = dma;
   g.prec = prec;
   g.ngroups = L.ngroups;
   g.total_tiles = L.total_tiles;
@@ -1019,6 +1020,7 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
   // batch workers keep to their one stream: many workers already fill the
   // device, and every extra stream shares the few hardware queues
   const Plan pl = make_plan(p, chunk_bytes, !single_stream(ctx));
+  const bool gemm_dma = env_flag("GXY_GEMM_DMA");
   Buffers b{};
   {
     Carver c0;
@@ -1439,7 +1441,7 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
         const int64_t *dt = reinterpret_cast<const int64_t *>(b.proj_tab + j.off +
                                                               j.ngrp * (int64_t)sizeof(GGroup));
         if (hot) hot_begin(ctx, st, j.L.flops, j.L.bytes + (beta != 0.0 ? j.L.c_bytes : 0.0));
-        run_launch(j.L, dg, dt, A, B, C, alpha, beta, st, sprec);
+        run_launch(j.L, dg, dt, A, B, C, alpha, beta, st, sprec, gemm_dma);
         if (hot) hot_end(ctx, st);
       };
       // (with chunks, both streams are the main one: the next chunk's X

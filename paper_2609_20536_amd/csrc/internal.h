@@ -112,6 +112,9 @@ struct GroupedGemm {
   // A(m, k) = A[tab[ar + m] + ac + k], B(k, n) = B[br + k bc + n],
   // C(m, n) = C[tab[ar + m] + cc + n]
   bool contig;
+  // FP64 contiguous launches: stage operands by direct global -> LDS loads
+  // (another summation order than the register-staged kernel)
+  bool dma;
 };
 
 void grouped_gemm(const GroupedGemm &g, hipStream_t s);

@@ -469,6 +469,167 @@ __global__ __launch_bounds__(64 * WGM * WGN) void ggemm_contig_kernel(GroupedGem
                                                     g.C, g.alpha, g.beta, sa, sb);
 }
 
+// FP64 contiguous groups with direct global -> LDS loads (global_load_lds).
+//
+// A k-slice of 8 is staged as 1 KiB chunks, one per 16 rows of A or 16
+// columns of B. Byte 16 l of a chunk holds the two values lane l feeds to
+// two consecutive matrix-core steps: A(m, k0 + 2g) and A(m, k0 + 2g + 1) for
+// row m = l % 16 of the chunk and lane group g = l / 16, likewise
+// B(k0 + 2g, n) and B(k0 + 2g + 1, n). The first step of a slice thus sums
+// the even k of the slice and the second the odd ones, and one 16-byte LDS
+// read per lane feeds both. The values never pass through registers on the
+// way in: an A pair is contiguous in its row and arrives by one 16-byte
+// load per lane; a B pair spans two rows, so a B chunk is four 4-byte loads
+// per lane (lane i of load j fetches half i % 2 of B(k0 + 2j + (i % 4) / 2,
+// n0 + i / 4)). Two stages: the loads of slice t + 1 fly while slice t is
+// multiplied. When K is not a multiple of 8 the last slice goes through
+// registers, with zeros past K; rows past M and columns past N load the
+// last valid row or column (their results are never stored), so every load
+// stays inside the group's operands. Every tile shape uses the same slices
+// and step order, so the tile does not change the bits.
+typedef double double2_t __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+template <int BM, int BN, int WGM, int WGN>
+__global__ __launch_bounds__(64 * WGM * WGN) void ggemm_dma_kernel(GroupedGemm g) {
+  constexpr int NW = WGM * WGN, WM = BM / WGM, WN = BN / WGN, FM = WM / 16, FN = WN / 16;
+  constexpr int BK = 8, CA = BM / 16, CB = BN / 16;   // chunks of A and of B per slice
+  constexpr int PA = CA / NW, PB = CB / NW;           // chunks each wave fills
+  static_assert(CA % NW == 0 && CB % NW == 0 && PA >= 1 && PB >= 1, "chunks per wave");
+  static_assert(WM % 16 == 0 && WN % 16 == 0, "wave tile");
+  __shared__ __attribute__((aligned(1024))) double lds[2][CA + CB][128];
+  const int t = xcd_remap(blockIdx.x, g.total_tiles);
+  int lo = 0, hi = g.ngroups - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (g.groups[mid].tile_start <= t)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const GGroup G = g.groups[lo];
+  const int local = t - G.tile_start;
+  const int tiles_n = (G.N + BN - 1) / BN;
+  const int m0 = (local / tiles_n) * BM, n0 = (local % tiles_n) * BN;
+  const int M = G.M, N = G.N, K = G.K;
+  const int64_t *rows = g.tab + G.ar;
+  const int64_t ldb = G.bc;
+  const double *B = g.B + G.br;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm0 = (wave / WGN) * WM, wn0 = (wave % WGN) * WN;
+  const int li = lane & 15, lg = lane >> 4;
+
+  const double *arow[PA];
+#pragma unroll
+  for (int p = 0; p < PA; ++p) {
+    const int m = min(m0 + 16 * (wave + NW * p) + li, M - 1);
+    arow[p] = g.A + rows[m] + G.ac + 2 * lg;
+  }
+  const char *bsrc[PB];
+  int bcol[PB];
+#pragma unroll
+  for (int p = 0; p < PB; ++p) {
+    const int c = wave + NW * p;
+    bsrc[p] = reinterpret_cast<const char *>(B + ((lane & 3) >> 1) * ldb +
+                                             min(n0 + 16 * c + (lane >> 2), N - 1)) +
+              4 * (lane & 1);
+    bcol[p] = min(n0 + 16 * c + li, N - 1);
+  }
+  const int ktiles = (K + BK - 1) / BK, kfull = K / BK;
+  auto issue = [&](int kt, int st) {
+    const int k0 = kt * BK;
+    if (kt < kfull) {
+#pragma unroll
+      for (int p = 0; p < PA; ++p)
+        __builtin_amdgcn_global_load_lds((const void *)(arow[p] + k0),
+                                         (lds_void_t *)&lds[st][wave + NW * p][0],
+                                         16, 0, 0);
+#pragma unroll
+      for (int p = 0; p < PB; ++p) {
+        const char *b = bsrc[p] + (int64_t)k0 * ldb * 8;
+        char *dst = reinterpret_cast<char *>(&lds[st][CA + wave + NW * p][0]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          __builtin_amdgcn_global_load_lds((const void *)(b + j * 16 * ldb),
+                                           (lds_void_t *)(dst + 256 * j), 4, 0, 0);
+      }
+    } else {
+      const int k = k0 + 2 * lg;
+#pragma unroll
+      for (int p = 0; p < PA; ++p) {
+        const double *a = arow[p] + k0;
+        *reinterpret_cast<double2_t *>(&lds[st][wave + NW * p][2 * lane]) =
+            double2_t{k < K ? a[0] : 0.0, k + 1 < K ? a[1] : 0.0};
+      }
+#pragma unroll
+      for (int p = 0; p < PB; ++p) {
+        const double *b = B + (int64_t)k * ldb + bcol[p];
+        *reinterpret_cast<double2_t *>(&lds[st][CA + wave + NW * p][2 * lane]) =
+            double2_t{k < K ? b[0] : 0.0, k + 1 < K ? b[ldb] : 0.0};
+      }
+    }
+  };
+
+  double4_t acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = double4_t{0, 0, 0, 0};
+  if (ktiles > 0) issue(0, 0);
+  for (int kt = 0; kt < ktiles; ++kt) {
+    // every load of slice kt (own and register-path LDS writes) has landed,
+    // and every wave is done reading the stage the next loads overwrite
+    __builtin_amdgcn_s_waitcnt(0x70);   // vmcnt(0) lgkmcnt(0)
+    asm volatile("s_barrier" ::: "memory");
+    if (kt + 1 < ktiles) issue(kt + 1, (kt + 1) & 1);
+    const int st = kt & 1;
+    double2_t fa[FM], fb[FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+      fa[i] = *reinterpret_cast<const double2_t *>(&lds[st][wm0 / 16 + i][2 * lane]);
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+      fb[j] = *reinterpret_cast<const double2_t *>(&lds[st][CA + wn0 / 16 + j][2 * lane]);
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i].x, fb[j].x, acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i].y, fb[j].y, acc[i][j], 0, 0, 0);
+  }
+
+  // register r of lane l: row l / 16 + 4 r, column l % 16 of the 16 x 16 block
+  const double alpha = g.alpha, beta = g.beta;
+  double *C = g.C + G.cc;
+#pragma unroll
+  for (int j = 0; j < FN; ++j) {
+    const int n = n0 + wn0 + 16 * j + li;
+    if (n >= N) continue;
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm0 + 16 * i + lg + 4 * r;
+        if (m >= M) continue;
+        double *dst = C + rows[m] + n;
+        const double v = alpha * acc[i][j][r];
+        *dst = (beta == 0.0) ? v : v + beta * (*dst);
+      }
+    }
+  }
+}
+
+template <int BM, int BN, int WGM, int WGN>
+void launch_dma(const GroupedGemm &g, hipStream_t s) {
+  hipLaunchKernelGGL((ggemm_dma_kernel<BM, BN, WGM, WGN>), dim3(g.total_tiles),
+                     dim3(64 * WGM * WGN), 0, s, g);
+}
+
+
 template <int BM, int BN, int BK, int WGM, int WGN, int PREC>
 void launch_tile(const GemmDesc &g, hipStream_t s) {
   const int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
@@ -501,9 +662,14 @@ void launch_tile_prec(const GemmDesc &g, hipStream_t s) {
 template <int BM, int BN, int BK, int WGM, int WGN, int PREC>
 void launch_grouped(const GroupedGemm &g, hipStream_t s) {
   dim3 grid(g.total_tiles), block(64 * WGM * WGN);
-  if (g.contig)
-    hipLaunchKernelGGL((ggemm_contig_kernel<BM, BN, BK, WGM, WGN, PREC>), grid, block, 0, s, g);
-  else if (g.kfast_a && g.nfast_b)
+  if (g.contig) {
+    bool dma = false;
+    if constexpr (PREC == kF64) dma = g.dma;
+    if (dma)
+      launch_dma<BM, BN, WGM, WGN>(g, s);
+    else
+      hipLaunchKernelGGL((ggemm_contig_kernel<BM, BN, BK, WGM, WGN, PREC>), grid, block, 0, s, g);
+  } else if (g.kfast_a && g.nfast_b)
     hipLaunchKernelGGL((ggemm_kernel<BM, BN, BK, WGM, WGN, true, true, PREC>), grid, block, 0, s,
                        g);
   else if (g.kfast_a)

@@ -79,14 +79,16 @@ def test_autotune_picks_a_tile_and_keeps_results(ctx):
     assert after.lnz_per_site == before.lnz_per_site
 
 
+@pytest.mark.parametrize("dma", ["0", "1"])
 @pytest.mark.parametrize("chunk_mb", [8, 96])
-def test_projection_chunks_do_not_change_results(ctx, chunk_mb, monkeypatch):
+def test_projection_chunks_do_not_change_results(ctx, chunk_mb, dma, monkeypatch):
     """Splitting the projection over the output index a (several chunks, each
     with its own planned launches) gives the same bits as one chunk: every
     element of X, Y and T' belongs to exactly one chunk and is reduced in the
     same order."""
     pts = [W.Point(beta=1.1, delta=0.6, nmax=5, dcut=24, nsteps=8, impurities=3),
            W.Point(beta=0.9, delta=0.4, nmax=4, dcut=20, nsteps=7, h1=0.05, impurities=3)]
+    monkeypatch.setenv("GXY_GEMM_DMA", dma)
     whole = [ctx.run(p) for p in pts]
     monkeypatch.setenv("GXY_CHUNK_BYTES", str(chunk_mb << 20))
     for p, w in zip(pts, whole):
@@ -94,11 +96,13 @@ def test_projection_chunks_do_not_change_results(ctx, chunk_mb, monkeypatch):
         assert _same(r, w), (p, r, w)
 
 
-@pytest.mark.parametrize("prec,k", [(W.PREC_FP64, 0), (W.PREC_FP32, 3), (W.PREC_BF16X3, 3)])
-def test_projection_tiles_give_the_same_bits(ctx, prec, k, monkeypatch):
+@pytest.mark.parametrize("prec,k,dma", [(W.PREC_FP64, 0, "0"), (W.PREC_FP64, 0, "1"),
+                                        (W.PREC_FP32, 3, "0"), (W.PREC_BF16X3, 3, "0")])
+def test_projection_tiles_give_the_same_bits(ctx, prec, k, dma, monkeypatch):
     """64 x 64, 128 x 128 and 256 x 128 projection tiles accumulate every
     output element over the same k-slices in the same order, in each
-    arithmetic form."""
+    arithmetic form and with either operand staging of the FP64 products."""
+    monkeypatch.setenv("GXY_GEMM_DMA", dma)
     pts = [W.Point(beta=1.1, delta=0.6, nmax=6, dcut=32, nsteps=8, impurities=3, prec=prec,
                    fp64_steps=k),
            W.Point(beta=0.9, delta=0.4, nmax=5, dcut=24, nsteps=7, h1=0.05, impurities=3,

@@ -140,6 +140,12 @@ def test_run_matches_oracle(ctx, pt):
     _compare(ctx.run(pt), o.run_point(**pt), pt)
 
 
+@pytest.mark.parametrize("pt", LIVE, ids=lambda p: ",".join(f"{k}={v}" for k, v in p.items()))
+def test_run_with_direct_lds_products_matches_oracle(ctx, pt, monkeypatch):
+    monkeypatch.setenv("GXY_GEMM_DMA", "1")
+    _compare(ctx.run(pt), o.run_point(**pt), pt)
+
+
 @pytest.mark.parametrize("pt", [LIVE[0], LIVE[5], LIVE[7]],
                          ids=lambda p: ",".join(f"{k}={v}" for k, v in p.items()))
 def test_run_with_block_jacobi_matches_oracle(ctx, pt, monkeypatch):
@@ -271,6 +277,19 @@ def _goldens():
 
 @pytest.mark.parametrize("path", _goldens(), ids=lambda p: os.path.basename(p)[:-5])
 def test_golden_runs(ctx, path):
+    _check_golden(ctx, path)
+
+
+@pytest.mark.parametrize("path", _goldens(), ids=lambda p: os.path.basename(p)[:-5])
+def test_golden_runs_direct_lds_products(ctx, path, monkeypatch):
+    """The same gates with the FP64 projection products staged by direct
+    global -> LDS loads (GXY_GEMM_DMA=1: even and odd k of each slice of 8 in
+    separate matrix-core steps, another rounding order)."""
+    monkeypatch.setenv("GXY_GEMM_DMA", "1")
+    _check_golden(ctx, path)
+
+
+def _check_golden(ctx, path):
     gd = json.load(open(path))
     pt = gd["point"]
     n = len(gd["cut_gap"])
