@@ -65,13 +65,13 @@ def workload_point(dcut: int):
     return W.precision_point(dcut=dcut, prec=W.PREC_FP64, impurities=W.IMP_COS1 | W.IMP_COS2)
 
 
-def measured_traffic():
+def measured_traffic(name="ygemm_d64_chains_fp64_traffic.json"):
     """HBM bytes per launch of the D^7 GEMM from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary, if the sources it names (kernel, planner
     and the engine that issues the launches) are unchanged since the counters
     were taken (else None)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "ygemm_d64_chains_fp64_traffic.json")
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -308,6 +308,8 @@ def direct_lds_leg(ctx, pt, r, steps, note):
     return {"kernel": "ggemm_dma_kernel (FP64, operands by global_load_lds)",
             "steps_per_s": pt.nsteps * steps / el, "avg_launch_ms": avg, "achieved": tf,
             "frac": tf / PEAK_FP64_TFLOPS,
+            "traffic": (measured_traffic("ygemm_dma_d64_chains_fp64_traffic.json")
+                        if pt.dcut == 64 else None),
             "abs_dlnz_vs_default": abs(rd.lnz_per_site - r.lnz_per_site)}
 
 
