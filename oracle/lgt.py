@@ -64,8 +64,13 @@ def shift(a: np.ndarray, d: int, mu: int, k: int = 1) -> np.ndarray:
 
 
 def plaquettes(theta: np.ndarray):
-    """[(mu, nu, theta_{mu nu}(n) as a site array)] for mu < nu."""
+    """[(mu, nu, theta_{mu nu}(n) as a site array)] for mu < nu. Every
+    extent must be at least 2, so that the four links of a plaquette are
+    distinct (with an extent of 1, theta_nu(n + mu) is theta_nu(n) and the
+    per-plaquette Hessian terms below would count a link twice)."""
     d = theta.shape[0]
+    if min(theta.shape[1:]) < 2:
+        raise ValueError("every lattice extent must be at least 2")
     out = []
     for mu, nu in itertools.combinations(range(d), 2):
         t = theta[mu] + shift(theta[nu], d, mu) - shift(theta[mu], d, nu) - theta[nu]

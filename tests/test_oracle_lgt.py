@@ -38,7 +38,7 @@ def _gauge(theta, alpha):
     return np.stack([theta[mu] + alpha - L.shift(alpha, d, mu) for mu in range(d)])
 
 
-CASES = [(2, (3, 4)), (3, (2, 3, 4)), (4, (2, 3, 2, 3)), (2, (1, 3))]
+CASES = [(2, (3, 4)), (3, (2, 3, 4)), (4, (2, 3, 2, 3)), (2, (2, 3))]
 
 
 @pytest.mark.parametrize("d,dims", CASES)
@@ -282,3 +282,8 @@ def test_thesis_table_two_dimensional_plaquette():
         if r["beta"] in (0.5, 1.0):
             P, _, _ = _heatbath(r["beta"], (8, 8), 100, 800, seed=7)
             assert abs(np.mean(P) - r["P"]) < 5 * (_err(P) + r["P_err"])
+
+
+def test_extents_below_two_are_refused():
+    with pytest.raises(ValueError):
+        L.plaquettes(np.zeros((2, 3, 1)))
