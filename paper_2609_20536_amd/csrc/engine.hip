@@ -2024,6 +2024,50 @@ gxy_status gxy_observables(gxy_ctx *ctx, int32_t npts, const double *beta, const
   GXY_API_END(ctx)
 }
 
+static bool lgt_args_ok(int32_t ndim, const int32_t *dims, int64_t nconf, uint32_t flags) {
+  if (!dims || ndim < 2 || ndim > 4 || nconf < 0 || nconf > GXY_LGT_MAX_CONF ||
+      (flags & ~(uint32_t)GXY_LGT_FULL) != 0)
+    return false;
+  int64_t V = 1;
+  for (int mu = 0; mu < ndim; ++mu) {
+    if (dims[mu] < 2) return false;   // a plaquette needs four distinct links
+    V *= dims[mu];
+    if (V > INT32_MAX) return false;
+  }
+  return true;
+}
+
+gxy_status gxy_lgt_workspace_bytes(int32_t ndim, const int32_t *dims, int64_t nconf,
+                                   uint32_t flags, size_t *out) {
+  if (!out || !lgt_args_ok(ndim, dims, nconf, flags)) return GXY_EINVAL;
+  *out = gxy::lgt_workspace_doubles(ndim, dims, nconf, (flags & GXY_LGT_FULL) != 0) *
+             sizeof(double) + 1024;
+  return GXY_OK;
+}
+
+gxy_status gxy_lgt_estimator(gxy_ctx *ctx, const double *theta, int32_t ndim,
+                             const int32_t *dims, int64_t nconf, uint32_t flags,
+                             gxy_lgt_result *out) {
+  if (!ctx || !lgt_args_ok(ndim, dims, nconf, flags) || (nconf > 0 && (!theta || !out)))
+    return GXY_EINVAL;
+  if (nconf == 0) return GXY_OK;
+  GXY_API_BEGIN
+  GXY_HIP(hipSetDevice(ctx->device));
+  const bool full = (flags & GXY_LGT_FULL) != 0;
+  const size_t nd = gxy::lgt_workspace_doubles(ndim, dims, nconf, full);
+  gxy::ensure_workspace(ctx, nd * sizeof(double) + 1024);
+  double *ws = (double *)ctx->ws;
+  double *dres = ws + nd - (size_t)nconf * 14;
+  hipStream_t s = ctx->stream;
+  gxy::lgt_estimate(theta, ndim, dims, nconf, full, ws, dres, s);
+  static_assert(sizeof(gxy_lgt_result) == 14 * sizeof(double), "result layout");
+  GXY_HIP(hipMemcpyAsync(out, dres, (size_t)nconf * sizeof(gxy_lgt_result),
+                         hipMemcpyDeviceToHost, s));
+  GXY_HIP(hipStreamSynchronize(s));
+  return GXY_OK;
+  GXY_API_END(ctx)
+}
+
 const char *gxy_status_string(gxy_status s) {
   switch (s) {
     case GXY_OK: return "ok";

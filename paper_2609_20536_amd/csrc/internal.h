@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/gxy_hotrg.h"
+#include "../../include/gxy_lgt.h"
 
 namespace gxy {
 
@@ -118,6 +119,14 @@ struct GroupedGemm {
 };
 
 void grouped_gemm(const GroupedGemm &g, hipStream_t s);
+
+// --------------------------------------------------------------------------
+// configurational-temperature estimator, compact U(1) gauge theory (lgt.hip)
+// --------------------------------------------------------------------------
+// workspace (doubles) of one call; results: 14 doubles per configuration
+size_t lgt_workspace_doubles(int d, const int32_t *dims, int64_t nconf, bool full);
+void lgt_estimate(const double *theta, int d, const int32_t *dims, int64_t nconf, bool full,
+                  double *ws, double *dres, hipStream_t s);
 // raw register layout of one v_mfma_f64_16x16x4_f64 (a[64], b[64] -> out[256])
 void launch_mfma_probe(const double *a, const double *b, double *out, hipStream_t s);
 // kind 0: f32 16x16x4 (a[64], b[64]); kind 1: bf16 16x16x32 (a[512], b[512])

@@ -44,6 +44,23 @@ class Result(C.Structure):
                 ("msq_cos2", C.c_double), ("chi0", C.c_double), ("chi0_n", C.c_double)]
 
 
+class LgtResult(C.Structure):
+    """gxy_lgt_result (include/gxy_lgt.h)."""
+    _fields_ = [("sum_g2", C.c_double), ("sum_h", C.c_double), ("g_h_g", C.c_double),
+                ("plaquette", C.c_double), ("beta_diag", C.c_double),
+                ("beta_full", C.c_double), ("sum_g2_dir", C.c_double * 4),
+                ("sum_h_dir", C.c_double * 4)]
+
+    def as_dict(self, ndim: int = 4) -> dict:
+        out = {f: getattr(self, f) for f, _ in self._fields_[:6]}
+        out["sum_g2_dir"] = list(self.sum_g2_dir)[:ndim]
+        out["sum_h_dir"] = list(self.sum_h_dir)[:ndim]
+        return out
+
+
+LGT_FULL = 1
+
+
 class StepInfo(C.Structure):
     _fields_ = [("lnc", C.c_double), ("eps_l", C.c_double), ("eps_r", C.c_double),
                 ("lam_max", C.c_double), ("cut_gap", C.c_double), ("side", C.c_int32),
@@ -95,6 +112,10 @@ def load_library(path: str = LIB_PATH):
                             P(C.c_double), P(C.c_double), C.c_double, C.c_double,
                             C.c_double, P(C.c_double)],
         "gxy_phase_times": [C.c_void_p, P(C.c_double)],
+        "gxy_lgt_workspace_bytes": [C.c_int32, P(C.c_int32), C.c_int64, C.c_uint32,
+                                    P(C.c_size_t)],
+        "gxy_lgt_estimator": [C.c_void_p, C.c_void_p, C.c_int32, P(C.c_int32), C.c_int64,
+                              C.c_uint32, P(LgtResult)],
         "gxy_mlp_create": [C.c_void_p, C.c_uint64, P(C.c_void_p)],
         "gxy_mlp_destroy": [C.c_void_p],
         "gxy_mlp_params": [C.c_void_p, P(C.c_float), P(C.c_float)],
@@ -328,6 +349,29 @@ class Context:
         self._check(self.lib.gxy_observables(self.handle, n, dp(beta), dp(lnz), dp(m_h),
                                              dp(m_h1), dbeta, dh, dh1, dp(out)), self.handle)
         return out
+
+    def lgt_estimator(self, theta, full: bool = True):
+        """Configurational-temperature estimator (include/gxy_lgt.h) of a batch
+        of link configurations: theta is a float64 device tensor of shape
+        (nconf, d, L_{d-1}, ..., L_0) (x_0 fastest), on this context's
+        device; returns one gxy_lgt_result dict per configuration."""
+        t = self.torch
+        if not (isinstance(theta, t.Tensor) and theta.is_cuda and theta.dtype == t.float64):
+            raise TypeError("theta must be a float64 device tensor")
+        if not theta.is_contiguous():
+            raise ValueError("theta must be contiguous")
+        nconf, d = theta.shape[0], theta.shape[1]
+        if theta.dim() != d + 2:
+            raise ValueError("theta must have shape (nconf, d, L_{d-1}, ..., L_0)")
+        dims = (C.c_int32 * d)(*[int(n) for n in reversed(theta.shape[2:])])
+        flags = LGT_FULL if full else 0
+        nb = C.c_size_t()
+        self._check(self.lib.gxy_lgt_workspace_bytes(d, dims, nconf, flags, C.byref(nb)))
+        self._reserve_bytes(nb.value)
+        out = (LgtResult * max(nconf, 1))()
+        self._check(self.lib.gxy_lgt_estimator(self.handle, C.c_void_p(theta.data_ptr()), d,
+                                               dims, nconf, flags, out), self.handle)
+        return [out[i].as_dict(d) for i in range(nconf)]
 
     # -- single-kernel checks (include/gxy_hotrg_testing.h) -------------------
     def test_gemm(self, A, B, a_trans=False, b_trans=False, prec=None):

@@ -15,6 +15,10 @@ gXY Hamiltonian with J = Delta, J1 = 1 - Delta, q = 2):
 * ``grid``     16x16 (beta, Delta) grid, beta in [0.5,1.5], Delta in [0,1]
                (endpoints included), nmax=10, 40 steps, Dcut per point drawn
                from {24,32,48,64} by SplitMix64 (seed 20536).
+* ``lgt``      link configurations of compact U(1) lattice gauge theory for
+               the configurational-temperature estimator (Ch. 4-5): seeded
+               uniform or gauge-transformed Gaussian angles; the throughput
+               batch is 16 configurations of 32^4.
 """
 
 from __future__ import annotations
@@ -212,3 +216,47 @@ def mlp_split(n: int, seed: int = MLP_SEED, train_frac: float = 0.9):
         perm[i], perm[j] = perm[j], perm[i]
     ntr = int(round(train_frac * n))
     return perm[:ntr], perm[ntr:]
+
+
+# ---------------------------------------------------------------------------
+# compact U(1) lattice gauge theory: link configurations for the
+# configurational-temperature estimator (include/gxy_lgt.h)
+# ---------------------------------------------------------------------------
+# The thesis's four-dimensional study runs on 8^4 lattices (Ch. 5, Sec.
+# "Four-Dimensional Theory"); the throughput workload is a batch of larger
+# lattices of the same theory.
+LGT_BENCH_DIMS = (32, 32, 32, 32)
+LGT_BENCH_CONF = 16
+LGT_SEED = 0x5EED_1A77
+
+
+def lgt_configs(nconf: int, dims, seed: int = LGT_SEED, kind: str = "gauge_noise",
+                sigma: float = 0.52):
+    """Seeded link angles as a numpy array of shape (nconf, d, L_{d-1}, ...,
+    L_0) (x_0 fastest, the library's layout), d = len(dims).
+
+    kind "uniform": independent angles uniform on (-pi, pi] (the
+    configurations of infinite temperature, beta = 0).
+    kind "gauge_noise": theta_mu(x) = alpha(x) + eps_mu(x) - alpha(x + mu),
+    alpha uniform on (-pi, pi] and eps Gaussian of width sigma, mapped to
+    (-pi, pi]: every link looks uniformly random while the plaquettes stay
+    near e^{-2 sigma^2} on average (0.58 at sigma = 0.52, the thesis's 8^4
+    plaquette near beta = 1), a synthetic stand-in for thermalised
+    configurations (no Monte Carlo is run)."""
+    import numpy as np
+
+    rng = np.random.default_rng(seed)
+    d = len(dims)
+    shape = (nconf, d) + tuple(reversed(dims))
+    if kind == "uniform":
+        th = rng.uniform(-np.pi, np.pi, size=shape)
+    elif kind == "gauge_noise":
+        alpha = rng.uniform(-np.pi, np.pi, size=(nconf,) + tuple(reversed(dims)))
+        eps = rng.normal(0.0, sigma, size=shape)
+        th = np.empty(shape)
+        for mu in range(d):
+            # alpha(x + mu): x_mu is array axis 1 + (d - 1 - mu) of alpha
+            th[:, mu] = alpha + eps[:, mu] - np.roll(alpha, -1, axis=1 + (d - 1 - mu))
+    else:
+        raise ValueError(kind)
+    return np.pi - np.mod(np.pi - th, 2.0 * np.pi)

@@ -1,0 +1,153 @@
+"""Configurational-temperature estimator on the GPU (C ABI, include/gxy_lgt.h)
+against the CPU oracle (oracle/lgt.py).
+
+Sums and estimators per configuration are compared at relative 1e-12 (the
+sums add 1e3-1e7 terms of unit size; the GPU forms each plaquette as a
+product of unit complex numbers, the oracle from the angle sum: both are
+within a few ulp per term). At the benchmark's size (16 configurations of
+32^4) the oracle's diagonal sums are compared for sampled configurations,
+and the full estimator through properties that hold at any size: gauge
+invariance and translation invariance of every output.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle.lgt as L
+from paper_2609_20536_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2609_20536_amd import hotrg as H
+    c = H.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(th):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(th)).to("cuda:0")
+
+
+def _cmp(g, o, full):
+    for k in ("sum_g2", "sum_h", "beta_diag"):
+        assert g[k] == pytest.approx(o[k], rel=REL), k
+    assert g["plaquette"] == pytest.approx(o["plaquette"], rel=REL, abs=1e-14)
+    for a, b in zip(g["sum_g2_dir"], o["sum_g2_dir"]):
+        assert a == pytest.approx(b, rel=REL)
+    for a, b in zip(g["sum_h_dir"], o["sum_h_dir"]):
+        assert a == pytest.approx(b, rel=REL, abs=1e-12)
+    if full:
+        assert g["g_h_g"] == pytest.approx(o["g_h_g"], rel=REL)
+        assert g["beta_full"] == pytest.approx(o["beta_full"], rel=REL)
+    else:
+        assert math.isnan(g["g_h_g"]) and math.isnan(g["beta_full"])
+
+
+CASES = [
+    (2, (5, 3), 3, "uniform"),
+    (2, (32, 32), 2, "gauge_noise"),       # the thesis's 2D lattice
+    (3, (3, 4, 5), 2, "gauge_noise"),
+    (4, (8, 8, 8, 8), 2, "gauge_noise"),   # the thesis's 4D lattice
+    (4, (2, 3, 4, 5), 1, "uniform"),       # ragged extents
+    (4, (17, 3, 5, 7), 1, "gauge_noise"),  # sites not a multiple of the workgroup
+    (2, (2, 2), 1, "uniform"),             # the smallest lattice
+    (4, (2, 2, 2, 2), 3, "gauge_noise"),
+]
+
+
+@pytest.mark.parametrize("full", [True, False])
+@pytest.mark.parametrize("d,dims,nconf,kind", CASES,
+                         ids=lambda x: "x".join(map(str, x)) if isinstance(x, tuple) else str(x))
+def test_estimator_matches_oracle(ctx, d, dims, nconf, kind, full):
+    th = W.lgt_configs(nconf, dims, seed=17 + d, kind=kind)
+    res = ctx.lgt_estimator(_dev(th), full=full)
+    assert len(res) == nconf
+    for c in range(nconf):
+        _cmp(res[c], L.estimator(th[c], full=full), full)
+
+
+def test_full_and_diagonal_calls_agree(ctx):
+    th = _dev(W.lgt_configs(3, (6, 4, 5, 3), seed=3))
+    a = ctx.lgt_estimator(th, full=True)
+    b = ctx.lgt_estimator(th, full=False)
+    for x, y in zip(a, b):
+        for k in ("sum_g2", "sum_h", "plaquette", "beta_diag"):
+            assert x[k] == y[k]
+
+
+def test_bench_size_against_oracle_samples(ctx):
+    """16 configurations of 32^4: diagonal sums of two sampled
+    configurations against the oracle; bitwise repeatable."""
+    th = W.lgt_configs(W.LGT_BENCH_CONF, W.LGT_BENCH_DIMS)
+    dth = _dev(th)
+    a = ctx.lgt_estimator(dth, full=True)
+    b = ctx.lgt_estimator(dth, full=True)
+    assert a == b
+    for c in (0, W.LGT_BENCH_CONF - 1):
+        o = L.estimator(th[c], full=False)
+        for k in ("sum_g2", "sum_h", "beta_diag", "plaquette"):
+            assert a[c][k] == pytest.approx(o[k], rel=REL), k
+    for r in a:
+        assert 0.5 < r["plaquette"] < 0.65
+        assert math.isfinite(r["beta_full"]) and abs(r["beta_full"] - r["beta_diag"]) < 0.01
+
+
+def test_bench_size_gauge_and_translation_invariance(ctx):
+    """Every output is invariant under a random gauge transformation
+    theta_mu(x) -> theta_mu(x) + a(x) - a(x + mu) and under a translation of
+    the lattice (to rounding)."""
+    dims = W.LGT_BENCH_DIMS
+    th = W.lgt_configs(4, dims, seed=5)
+    rng = np.random.default_rng(6)
+    alpha = rng.uniform(-np.pi, np.pi, size=(4,) + tuple(reversed(dims)))
+    tg = np.stack([th[:, mu] + alpha - np.roll(alpha, -1, axis=1 + (3 - mu))
+                   for mu in range(4)], axis=1)
+    tt = np.roll(th, (3, -5), axis=(2, 5))
+    r0 = ctx.lgt_estimator(_dev(th))
+    for other in (tg, tt):
+        r1 = ctx.lgt_estimator(_dev(other))
+        for a, b in zip(r0, r1):
+            for k in ("sum_g2", "sum_h", "g_h_g", "plaquette", "beta_diag", "beta_full"):
+                assert a[k] == pytest.approx(b[k], rel=1e-12), k
+
+
+def test_degenerate_configurations(ctx):
+    """All links zero: every plaquette is 1, g = 0 and h = 2 (d - 1) on every
+    link, so the estimators are +inf (IEEE division of a positive trace by
+    |g|^2 = 0)."""
+    for d, dims in ((2, (4, 6)), (4, (3, 3, 2, 4))):
+        th = np.zeros((1, d) + tuple(reversed(dims)))
+        r = ctx.lgt_estimator(_dev(th))[0]
+        V = int(np.prod(dims))
+        assert r["sum_g2"] == 0.0 and r["g_h_g"] == 0.0
+        assert r["sum_h"] == 2 * (d - 1) * d * V and r["plaquette"] == 1.0
+        assert r["beta_diag"] == math.inf
+
+
+def test_invalid_arguments_are_rejected(ctx):
+    import ctypes as C
+    from paper_2609_20536_amd import hotrg as H
+    lib = ctx.lib
+    dims = (C.c_int32 * 4)(4, 4, 4, 4)
+    out = (H.LgtResult * 1)()
+    th = _dev(np.zeros((1, 4, 4, 4, 4, 4)))
+    ptr = C.c_void_p(th.data_ptr())
+    assert lib.gxy_lgt_estimator(ctx.handle, ptr, 5, dims, 1, 1, out) == 1
+    assert lib.gxy_lgt_estimator(ctx.handle, ptr, 1, dims, 1, 1, out) == 1
+    assert lib.gxy_lgt_estimator(ctx.handle, ptr, 4, dims, 1, 2, out) == 1
+    assert lib.gxy_lgt_estimator(ctx.handle, ptr, 4, dims, -1, 1, out) == 1
+    assert lib.gxy_lgt_estimator(ctx.handle, ptr, 4, dims, 70000, 1, out) == 1
+    assert lib.gxy_lgt_estimator(ctx.handle, None, 4, dims, 1, 1, out) == 1
+    for bad in ((C.c_int32 * 4)(4, 0, 4, 4), (C.c_int32 * 4)(4, 4, 1, 4)):
+        assert lib.gxy_lgt_estimator(ctx.handle, ptr, 4, bad, 1, 1, out) == 1
+    big = (C.c_int32 * 4)(2048, 2048, 1024, 1)
+    assert lib.gxy_lgt_estimator(ctx.handle, ptr, 4, big, 1, 1, out) == 1
+    assert lib.gxy_lgt_estimator(ctx.handle, ptr, 4, dims, 0, 1, out) == 0

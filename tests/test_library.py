@@ -66,8 +66,10 @@ def test_binding_structs_match_the_header_layout(tmp_path):
     ctypes structures of the binding."""
     import subprocess
     from paper_2609_20536_amd import hotrg as H
-    structs = {"gxy_point": H.Point, "gxy_result": H.Result, "gxy_step_info": H.StepInfo}
-    src = ["#include <stdio.h>", "#include <stddef.h>", '#include "gxy_hotrg.h"', "int main(void) {"]
+    structs = {"gxy_point": H.Point, "gxy_result": H.Result, "gxy_step_info": H.StepInfo,
+               "gxy_lgt_result": H.LgtResult}
+    src = ["#include <stdio.h>", "#include <stddef.h>", '#include "gxy_hotrg.h"',
+           '#include "gxy_lgt.h"', "int main(void) {"]
     for cname, cls in structs.items():
         src.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
         for f, _ in cls._fields_:
