@@ -28,6 +28,10 @@ More legs ride on the same line (each skippable):
   temperature procedure;
 * "surrogate": the surrogate's gain in locating the C_v peak at reduced
   size (the full-size refinement is `paper_2609_20536_amd.scan --refine`);
+* "lgt": the configurational-temperature estimator of compact U(1) lattice
+  gauge theory (the thesis's second workload, Ch. 4-5) on 16 configurations
+  of 32^4: configurations/s, the gradient kernel's HBM roofline, the mean
+  estimators and plaquette;
 * "batched": a stratified 16-point subset of the 16 x 16 (beta, Delta) grid
   (4 points per Dcut in {24, 32, 48, 64}) by the zero-field route, three
   runs per point (beta -+ db for C_v, beta with the second-moment chains for
@@ -313,6 +317,55 @@ def direct_lds_leg(ctx, pt, r, steps, note):
             "abs_dlnz_vs_default": abs(rd.lnz_per_site - r.lnz_per_site)}
 
 
+def lgt_leg(ctx, note, reps: int = 10):
+    """Configurational-temperature estimator of compact U(1) lattice gauge
+    theory (Ch. 4-5) on the throughput batch, 16 configurations of 32^4
+    (gauge-transformed Gaussian angles, plaquette near 0.58), full form
+    (Tr h, |g|^2 and g^T h g): configurations/s; the gradient kernel's
+    algorithmic HBM bytes per launch (every link's e^{i theta} read once and
+    its g written once, 24 bytes per link) over its event-timed duration; and
+    the whole call's rate on the 8 bytes per link of angles it must read."""
+    import numpy as np
+    import torch
+    from paper_2609_20536_amd import workloads as W
+
+    dims, nconf = W.LGT_BENCH_DIMS, W.LGT_BENCH_CONF
+    th = torch.from_numpy(W.lgt_configs(nconf, dims)).to("cuda:0")
+    ctx.lgt_estimator(th)
+    os.environ["GXY_HOT_EVENTS"] = "1"
+    try:
+        ctx.hot_kernel_stats(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            res = ctx.lgt_estimator(th)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+    finally:
+        os.environ.pop("GXY_HOT_EVENTS", None)
+    launches, ms, _, nbytes = ctx.hot_kernel_stats(reset=True)
+    V = int(np.prod(dims))
+    links = nconf * len(dims) * V
+    avg = ms / max(launches, 1)
+    gbs = (nbytes / max(launches, 1)) / (avg * 1e-3) / 1e9 if ms > 0 else 0.0
+    note("bench: U(1) estimator leg done")
+    return {
+        "workload": (f"{nconf} configurations of {'x'.join(map(str, dims))} compact U(1), "
+                     "full estimator (Tr h, |g|^2, g^T h g), FP64"),
+        "configs_per_s": nconf * reps / el,
+        "ms_per_call": 1000.0 * el / reps,
+        "plaquette_mean": float(np.mean([r["plaquette"] for r in res])),
+        "beta_diag_mean": float(np.mean([r["beta_diag"] for r in res])),
+        "beta_full_mean": float(np.mean([r["beta_full"] for r in res])),
+        "roofline": {"bound": "hbm", "kernel": "lgt_grad_kernel<4>", "achieved": gbs,
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
+                     "traffic": measured_traffic("lgt_grad_32x4_traffic.json"),
+                     "launches": int(launches), "avg_launch_ms": avg,
+                     "algorithmic_bytes_per_launch": nbytes / max(launches, 1)},
+        "end_to_end_angle_GBs": 8.0 * links / (el / reps) / 1e9,
+    }
+
+
 def cpu_baseline(dcut: int, nimp: int, frac_cols: int = 8):
     """Time the CPU oracle on a bounded sample of one coarse-graining step.
 
@@ -372,6 +425,28 @@ def cpu_baseline(dcut: int, nimp: int, frac_cols: int = 8):
     }
 
 
+def cpu_baseline_lgt():
+    """The U(1) estimator's oracle on the host: the diagonal form on one
+    32^4 configuration and the full form (explicit sparse Hessian) on one
+    16^4 configuration, each as configurations/s at its size."""
+    import oracle.lgt as ol
+    from paper_2609_20536_amd import workloads as W
+    th = W.lgt_configs(1, W.LGT_BENCH_DIMS)[0]
+    t0 = time.perf_counter()
+    ol.estimator(th, full=False)
+    t_diag = time.perf_counter() - t0
+    th16 = W.lgt_configs(1, (16, 16, 16, 16))[0]
+    t0 = time.perf_counter()
+    ol.estimator(th16, full=True)
+    t_full = time.perf_counter() - t0
+    return {"unit": "configurations/s", "kind": "oracle",
+            "diag_32^4_configs_per_s": 1.0 / t_diag,
+            "full_16^4_configs_per_s": 1.0 / t_full,
+            "full_scaled_to_32^4_configs_per_s": 1.0 / (t_full * 16.0),
+            "sample": "one 32^4 configuration (diagonal form) and one 16^4 configuration "
+                      "(full form, scaled by volume to 32^4)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -387,6 +462,7 @@ def main():
     ap.add_argument("--no-d96", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-direct-lds", action="store_true")
+    ap.add_argument("--no-lgt", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="one plain 1 GiB device copy first (known HBM bytes for counter scaling)")
     ap.add_argument("--phases", action="store_true", help="one extra untimed run with phase timers")
@@ -507,9 +583,13 @@ def main():
         note("bench: transition leg done")
     if not args.no_batched:
         line["batched"] = batched_leg(ctx, note)
+    if not args.no_lgt:
+        line["lgt"] = lgt_leg(ctx, note)
     if not args.no_cpu_baseline:
         note("bench: timing the CPU oracle sample")
         line["cpu_baseline"] = cpu_baseline(pt.dcut, 2)
+        if not args.no_lgt:
+            line["cpu_baseline"]["lgt"] = cpu_baseline_lgt()
     print(json.dumps(line), flush=True)
     ctx.close()
 

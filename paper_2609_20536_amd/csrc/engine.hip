@@ -2024,6 +2024,12 @@ gxy_status gxy_observables(gxy_ctx *ctx, int32_t npts, const double *beta, const
   GXY_API_END(ctx)
 }
 
+static int64_t lgt_links_of(int32_t ndim, const int32_t *dims, int64_t nconf) {
+  int64_t V = 1;
+  for (int mu = 0; mu < ndim; ++mu) V *= dims[mu];
+  return nconf * ndim * V;
+}
+
 static bool lgt_args_ok(int32_t ndim, const int32_t *dims, int64_t nconf, uint32_t flags) {
   if (!dims || ndim < 2 || ndim > 4 || nconf < 0 || nconf > GXY_LGT_MAX_CONF ||
       (flags & ~(uint32_t)GXY_LGT_FULL) != 0)
@@ -2059,11 +2065,28 @@ gxy_status gxy_lgt_estimator(gxy_ctx *ctx, const double *theta, int32_t ndim,
   double *ws = (double *)ctx->ws;
   double *dres = ws + nd - (size_t)nconf * 14;
   hipStream_t s = ctx->stream;
-  gxy::lgt_estimate(theta, ndim, dims, nconf, full, ws, dres, s);
+  // GXY_HOT_EVENTS: events around the gradient kernel, with its algorithmic
+  // bytes (every link's U read once, g written once with GXY_LGT_FULL)
+  ctx->hot_on = !ctx->noalloc && gxy::env_flag("GXY_HOT_EVENTS");
+  struct HotArg {
+    gxy_ctx *ctx;
+    double bytes;
+  } ha{ctx, (double)lgt_links_of(ndim, dims, nconf) * (full ? 24.0 : 16.0)};
+  gxy::LgtHooks hooks{[](void *a, hipStream_t st) {
+                        auto *h = static_cast<HotArg *>(a);
+                        gxy::hot_begin(h->ctx, st, 0.0, h->bytes);
+                      },
+                      [](void *a, hipStream_t st) {
+                        gxy::hot_end(static_cast<HotArg *>(a)->ctx, st);
+                      },
+                      &ha};
+  gxy::lgt_estimate(theta, ndim, dims, nconf, full, ws, dres, s, ctx->hot_on ? &hooks : nullptr);
   static_assert(sizeof(gxy_lgt_result) == 14 * sizeof(double), "result layout");
   GXY_HIP(hipMemcpyAsync(out, dres, (size_t)nconf * sizeof(gxy_lgt_result),
                          hipMemcpyDeviceToHost, s));
   GXY_HIP(hipStreamSynchronize(s));
+  gxy::hot_collect(ctx);
+  ctx->hot_on = false;
   return GXY_OK;
   GXY_API_END(ctx)
 }

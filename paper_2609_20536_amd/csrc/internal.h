@@ -125,8 +125,15 @@ void grouped_gemm(const GroupedGemm &g, hipStream_t s);
 // --------------------------------------------------------------------------
 // workspace (doubles) of one call; results: 14 doubles per configuration
 size_t lgt_workspace_doubles(int d, const int32_t *dims, int64_t nconf, bool full);
+// called on the stream right before and after the gradient kernel (the
+// estimator's dominant launch), e.g. to time it with events
+struct LgtHooks {
+  void (*begin)(void *arg, hipStream_t s);
+  void (*end)(void *arg, hipStream_t s);
+  void *arg;
+};
 void lgt_estimate(const double *theta, int d, const int32_t *dims, int64_t nconf, bool full,
-                  double *ws, double *dres, hipStream_t s);
+                  double *ws, double *dres, hipStream_t s, const LgtHooks *hooks = nullptr);
 // raw register layout of one v_mfma_f64_16x16x4_f64 (a[64], b[64] -> out[256])
 void launch_mfma_probe(const double *a, const double *b, double *out, hipStream_t s);
 // kind 0: f32 16x16x4 (a[64], b[64]); kind 1: bf16 16x16x32 (a[512], b[512])

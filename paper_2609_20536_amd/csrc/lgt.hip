@@ -42,7 +42,7 @@ constexpr int kLgtParts = 3 + 2 * 4;   // g2, h, plaquette, g2 per direction, h 
 
 struct LgtGeom {
   int L[4];
-  int64_t stride[4];   // stride[mu] = L_0 ... L_{mu-1}
+  int st[4];           // st[mu] = L_0 ... L_{mu-1}
   int64_t V;
   int64_t nblk;        // site blocks per configuration
 };
@@ -62,31 +62,30 @@ __device__ __forceinline__ double2_t plaq(double2_t ua, double2_t ub_a, double2_
   return cmulc(cmulc(cmul(ua, ub_a), ua_b), ub);
 }
 
+// Coordinates of one site; sites of a configuration fit int32 (the entry
+// point refuses lattices of 2^31 sites or more), so neighbour indices are
+// 32-bit.
 template <int D>
 struct Site {
-  int64_t x;
+  int x;
   int c[D];
-  __device__ Site(const LgtGeom &G, int64_t x_) : x(x_) {
-    int64_t r = x_;
+  __device__ Site(const LgtGeom &G, int x_) : x(x_) {
+    unsigned r = (unsigned)x_;
 #pragma unroll
     for (int mu = 0; mu < D; ++mu) {
-      c[mu] = (int)(r % G.L[mu]);
-      r /= G.L[mu];
+      c[mu] = (int)(r % (unsigned)G.L[mu]);
+      r /= (unsigned)G.L[mu];
     }
   }
+  __device__ static int wrap(int cc, int L) { return cc < 0 ? cc + L : (cc >= L ? cc - L : cc); }
   // site index of x + k mu (k = +-1), periodic
-  __device__ int64_t nb(const LgtGeom &G, int mu, int k) const {
-    int cc = c[mu] + k;
-    const int64_t base = x - (int64_t)c[mu] * G.stride[mu];
-    cc = cc < 0 ? cc + G.L[mu] : (cc >= G.L[mu] ? cc - G.L[mu] : cc);
-    return base + (int64_t)cc * G.stride[mu];
+  __device__ int nb(const LgtGeom &G, int mu, int k) const {
+    return x + (wrap(c[mu] + k, G.L[mu]) - c[mu]) * G.st[mu];
   }
   // site index of x + k1 mu + k2 nu (mu != nu)
-  __device__ int64_t nb2(const LgtGeom &G, int mu, int k1, int nu, int k2) const {
-    int c1 = c[mu] + k1, c2 = c[nu] + k2;
-    c1 = c1 < 0 ? c1 + G.L[mu] : (c1 >= G.L[mu] ? c1 - G.L[mu] : c1);
-    c2 = c2 < 0 ? c2 + G.L[nu] : (c2 >= G.L[nu] ? c2 - G.L[nu] : c2);
-    return x + (int64_t)(c1 - c[mu]) * G.stride[mu] + (int64_t)(c2 - c[nu]) * G.stride[nu];
+  __device__ int nb2(const LgtGeom &G, int mu, int k1, int nu, int k2) const {
+    return x + (wrap(c[mu] + k1, G.L[mu]) - c[mu]) * G.st[mu] +
+           (wrap(c[nu] + k2, G.L[nu]) - c[nu]) * G.st[nu];
   }
 };
 
@@ -97,6 +96,14 @@ __global__ void lgt_links_kernel(const double *theta, double2_t *U, int64_t n) {
     sincos(theta[i], &s, &c);
     U[i] = double2_t{c, s};
   }
+}
+
+// Site block of this workgroup: workgroups go to the 8 XCDs in turn, so
+// block b is renumbered to give each XCD (own L2) a contiguous band of sites,
+// whose neighbours in the slowest directions then mostly sit in the same L2.
+__device__ __forceinline__ int64_t lgt_block(int64_t nblk) {
+  const int64_t b = blockIdx.x;
+  return (nblk & 7) == 0 ? (b & 7) * (nblk >> 3) + (b >> 3) : b;
 }
 
 // sum of v over the workgroup into out (thread 0), fixed order
@@ -118,22 +125,28 @@ __global__ __launch_bounds__(kLgtThreads) void lgt_grad_kernel(const double2_t *
                                                                double *partial) {
   __shared__ double red[kLgtThreads / 64];
   const int64_t cf = blockIdx.y;
-  const int64_t x = blockIdx.x * (int64_t)kLgtThreads + threadIdx.x;
-  const bool act = x < G.V;
+  const int64_t blk = lgt_block(G.nblk);
+  const int64_t x64 = blk * kLgtThreads + threadIdx.x;
+  const bool act = x64 < G.V;
+  const int x = (int)x64;
   const double2_t *Uc = U + cf * D * G.V;
   double g[D], h[D], pl = 0.0;
 #pragma unroll
   for (int mu = 0; mu < D; ++mu) g[mu] = h[mu] = 0.0;
   if (act) {
     const Site<D> s(G, x);
+    const double2_t *Ud[D];
     double2_t u[D];
 #pragma unroll
-    for (int mu = 0; mu < D; ++mu) u[mu] = Uc[mu * G.V + x];
+    for (int mu = 0; mu < D; ++mu) {
+      Ud[mu] = Uc + mu * G.V;
+      u[mu] = Ud[mu][x];
+    }
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
       for (int b = a + 1; b < D; ++b) {
-        const double2_t *Ua = Uc + a * G.V, *Ub = Uc + b * G.V;
+        const double2_t *Ua = Ud[a], *Ub = Ud[b];
         // own plaquette theta_ab(x): link (x, a) with +, link (x, b) with -
         const double2_t p0 = plaq(u[a], Ub[s.nb(G, a, 1)], Ua[s.nb(G, b, 1)], u[b]);
         g[a] += p0.y;
@@ -142,19 +155,19 @@ __global__ __launch_bounds__(kLgtThreads) void lgt_grad_kernel(const double2_t *
         h[b] += p0.x;
         pl += p0.x;
         // theta_ab(x - b): link (x, a) is its theta_a(n + b), with -
-        const int64_t yb = s.nb(G, b, -1);
+        const int yb = s.nb(G, b, -1);
         const double2_t p1 = plaq(Ua[yb], Ub[s.nb2(G, b, -1, a, 1)], u[a], Ub[yb]);
         g[a] -= p1.y;
         h[a] += p1.x;
         // theta_ab(x - a): link (x, b) is its theta_b(n + a), with +
-        const int64_t ya = s.nb(G, a, -1);
+        const int ya = s.nb(G, a, -1);
         const double2_t p2 = plaq(Ua[ya], u[b], Ua[s.nb2(G, a, -1, b, 1)], Ub[ya]);
         g[b] += p2.y;
         h[b] += p2.x;
       }
     if (gout) {
 #pragma unroll
-      for (int mu = 0; mu < D; ++mu) gout[(cf * D + mu) * G.V + x] = g[mu];
+      for (int mu = 0; mu < D; ++mu) gout[(cf * D + mu) * G.V + x64] = g[mu];
     }
   }
   double vals[kLgtParts];
@@ -174,7 +187,7 @@ __global__ __launch_bounds__(kLgtThreads) void lgt_grad_kernel(const double2_t *
     vals[3 + mu] = g[mu] * g[mu];
     vals[7 + mu] = h[mu];
   }
-  double *po = partial + (cf * G.nblk + blockIdx.x) * (kLgtParts + 1);
+  double *po = partial + (cf * G.nblk + blk) * (kLgtParts + 1);
 #pragma unroll
   for (int k = 0; k < kLgtParts; ++k) {
     const double t = lgt_block_sum(vals[k], red);
@@ -187,26 +200,31 @@ __global__ __launch_bounds__(kLgtThreads) void lgt_ghg_kernel(const double2_t *U
                                                               LgtGeom G, double *partial) {
   __shared__ double red[kLgtThreads / 64];
   const int64_t cf = blockIdx.y;
-  const int64_t x = blockIdx.x * (int64_t)kLgtThreads + threadIdx.x;
-  const double2_t *Uc = U + cf * D * G.V;
-  const double *gc = g + cf * D * G.V;
+  const int64_t blk = lgt_block(G.nblk);
+  const int64_t x64 = blk * kLgtThreads + threadIdx.x;
   double acc = 0.0;
-  if (x < G.V) {
+  if (x64 < G.V) {
+    const int x = (int)x64;
     const Site<D> s(G, x);
+    const double2_t *Ud[D];
+    const double *gd[D];
+#pragma unroll
+    for (int mu = 0; mu < D; ++mu) {
+      Ud[mu] = U + (cf * D + mu) * G.V;
+      gd[mu] = g + (cf * D + mu) * G.V;
+    }
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
       for (int b = a + 1; b < D; ++b) {
-        const int64_t xa = s.nb(G, a, 1), xb = s.nb(G, b, 1);
-        const double2_t p = plaq(Uc[a * G.V + x], Uc[b * G.V + xa], Uc[a * G.V + xb],
-                                 Uc[b * G.V + x]);
-        const double curl = gc[a * G.V + x] + gc[b * G.V + xa] - gc[a * G.V + xb] -
-                            gc[b * G.V + x];
+        const int xa = s.nb(G, a, 1), xb = s.nb(G, b, 1);
+        const double2_t p = plaq(Ud[a][x], Ud[b][xa], Ud[a][xb], Ud[b][x]);
+        const double curl = gd[a][x] + gd[b][xa] - gd[a][xb] - gd[b][x];
         acc += p.x * curl * curl;
       }
   }
   const double t = lgt_block_sum(acc, red);
-  if (threadIdx.x == 0) partial[(cf * G.nblk + blockIdx.x) * (kLgtParts + 1) + kLgtParts] = t;
+  if (threadIdx.x == 0) partial[(cf * G.nblk + blk) * (kLgtParts + 1) + kLgtParts] = t;
 }
 
 // out[c] = {sum_g2, sum_h, g_h_g, plaquette, beta_diag, beta_full,
@@ -243,12 +261,12 @@ __global__ __launch_bounds__(kLgtThreads) void lgt_reduce_kernel(const double *p
 
 template <int D>
 void lgt_launch(const double *theta, const int32_t *dims, int64_t nconf, bool full, double *ws,
-                double *dres, hipStream_t s) {
+                double *dres, hipStream_t s, const LgtHooks *hooks) {
   LgtGeom G{};
   int64_t V = 1;
   for (int mu = 0; mu < 4; ++mu) {
     G.L[mu] = mu < D ? dims[mu] : 1;
-    G.stride[mu] = V;
+    G.st[mu] = (int)V;
     if (mu < D) V *= dims[mu];
   }
   G.V = V;
@@ -262,9 +280,11 @@ void lgt_launch(const double *theta, const int32_t *dims, int64_t nconf, bool fu
                      nlinks);
   GXY_CHECK_LAUNCH();
   const dim3 grid((unsigned)G.nblk, (unsigned)nconf);
+  if (hooks) hooks->begin(hooks->arg, s);
   hipLaunchKernelGGL((lgt_grad_kernel<D>), grid, dim3(kLgtThreads), 0, s, U, G, nconf, g,
                      partial);
   GXY_CHECK_LAUNCH();
+  if (hooks) hooks->end(hooks->arg, s);
   if (full) {
     hipLaunchKernelGGL((lgt_ghg_kernel<D>), grid, dim3(kLgtThreads), 0, s, U, g, G, partial);
     GXY_CHECK_LAUNCH();
@@ -285,11 +305,11 @@ size_t lgt_workspace_doubles(int d, const int32_t *dims, int64_t nconf, bool ful
 }
 
 void lgt_estimate(const double *theta, int d, const int32_t *dims, int64_t nconf, bool full,
-                  double *ws, double *dres, hipStream_t s) {
+                  double *ws, double *dres, hipStream_t s, const LgtHooks *hooks) {
   switch (d) {
-    case 2: lgt_launch<2>(theta, dims, nconf, full, ws, dres, s); break;
-    case 3: lgt_launch<3>(theta, dims, nconf, full, ws, dres, s); break;
-    case 4: lgt_launch<4>(theta, dims, nconf, full, ws, dres, s); break;
+    case 2: lgt_launch<2>(theta, dims, nconf, full, ws, dres, s, hooks); break;
+    case 3: lgt_launch<3>(theta, dims, nconf, full, ws, dres, s, hooks); break;
+    case 4: lgt_launch<4>(theta, dims, nconf, full, ws, dres, s, hooks); break;
     default: fail(GXY_EINVAL, "lattice dimension must be 2, 3 or 4");
   }
 }
