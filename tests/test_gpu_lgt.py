@@ -151,3 +151,44 @@ def test_invalid_arguments_are_rejected(ctx):
     big = (C.c_int32 * 4)(2048, 2048, 1024, 1)
     assert lib.gxy_lgt_estimator(ctx.handle, ptr, 4, big, 1, 1, out) == 1
     assert lib.gxy_lgt_estimator(ctx.handle, ptr, 4, dims, 0, 1, out) == 0
+
+
+def _heatbath_2d(beta, n, ntherm, nmeas, every, seed):
+    rng = np.random.default_rng(seed)
+    th = rng.uniform(-np.pi, np.pi, size=(2, n, n))
+    for _ in range(ntherm):
+        L.heatbath_sweep(th, beta, rng)
+    out = []
+    for i in range(nmeas):
+        L.heatbath_sweep(th, beta, rng)
+        if i % every == 0:
+            out.append(th.copy())
+    return np.stack(out)
+
+
+@pytest.mark.parametrize("beta", [0.5, 1.0, 2.0])
+def test_equilibrium_two_dimensional_beta_m(ctx, beta):
+    """The thesis's claim for the 2D theory on 32 x 32 (Ch. 5, table
+    tab:2d_u1_l32_l32): on configurations drawn from exp(-S), the mean of the
+    per-configuration estimator, beta_M, equals beta. Configurations from the
+    oracle's heat bath (test infrastructure: exact conditional law of each
+    link); the GPU's estimator per configuration against the oracle's, and
+    its mean against beta within five batch-mean errors (the estimator's
+    finite-volume bias on 2048 links is far below that)."""
+    confs = _heatbath_2d(beta, 32, 200, 1200, 6, seed=int(100 * beta))
+    res = ctx.lgt_estimator(_dev(confs))
+    for c in (0, len(confs) // 2, len(confs) - 1):
+        o = L.estimator(confs[c])
+        assert res[c]["beta_full"] == pytest.approx(o["beta_full"], rel=REL)
+    bm = np.array([r["beta_full"] for r in res])
+    nb = 10
+    means = np.array([np.mean(b) for b in np.array_split(bm, nb)])
+    err = np.std(means, ddof=1) / np.sqrt(nb)
+    assert abs(np.mean(bm) - beta) < 5 * err + 1e-3, (np.mean(bm), err)
+    plaq = np.mean([r["plaquette"] for r in res])
+    assert abs(plaq - iv_ratio(beta)) < 0.01
+
+
+def iv_ratio(beta):
+    from scipy.special import iv
+    return iv(1, beta) / iv(0, beta)
