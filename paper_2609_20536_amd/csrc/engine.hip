@@ -821,12 +821,12 @@ struct SectorSolve {
   // tridiagonal path: eigenvalues are on diag(eb.A); the vectors are formed by
   // vectors(d_side) once the side is known (d_side null: both sides)
   bool vectors_pending = false;
-  int nmat = 0, nsec = 0, kmax = 0;
+  int nmat = 0, nsec = 0, kmax = 0, maxn = 0;
   double *Y = nullptr, *work = nullptr;
   void vectors(const double *d_side, hipStream_t s) const {
     if (!vectors_pending) return;
-    launch_tri_vectors(nmat, nsec, d_n, eb.d_npad, eb.d_off, eb.A, eb.V, Y, work, kmax, d_side,
-                       s);
+    launch_tri_vectors(nmat, nsec, maxn, d_n, eb.d_npad, eb.d_off, eb.A, eb.V, Y, work, kmax,
+                       d_side, s);
   }
 };
 
@@ -934,6 +934,7 @@ static SectorSolve solve_sectors(gxy_ctx *ctx, hipStream_t s, const double *E, i
     r.vectors_pending = true;
     r.nmat = nmat;
     r.nsec = nsec;
+    r.maxn = maxn;
     r.kmax = std::max(1, kmax);
     r.Y = m.B1;
     r.work = m.B2;

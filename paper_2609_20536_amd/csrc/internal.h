@@ -239,14 +239,15 @@ void launch_eig_scaled_copy(int64_t n, double a, const double *x, double *y, hip
 // leading min(n, kmax) eigenvectors into V (row-major, column c = c-th
 // largest), for the matrices of side *d_side (0: the first nsec, 1: the
 // rest) or for all if d_side is null; Y is scratch.
-constexpr int kTriMaxN = 1024;
+constexpr int kTriMaxN = 2048;
 constexpr int kTriMaxVecs = 128;   // eigenvectors formed per matrix
 void launch_tri_values(int nmat, int nsec, const int *h_sec_n, const int32_t *d_sec_n,
                        const int32_t *d_npad, const int64_t *d_off, double *A, double *Y,
                        double *X, double *work, bool allow_multi, hipStream_t s);
-void launch_tri_vectors(int nmat, int nsec, const int32_t *d_sec_n, const int32_t *d_npad,
-                        const int64_t *d_off, const double *A, double *V, double *Y,
-                        const double *work, int kmax, const double *d_side, hipStream_t s);
+void launch_tri_vectors(int nmat, int nsec, int maxn, const int32_t *d_sec_n,
+                        const int32_t *d_npad, const int64_t *d_off, const double *A, double *V,
+                        double *Y, const double *work, int kmax, const double *d_side,
+                        hipStream_t s);
 
 // --------------------------------------------------------------------------
 // selection and projector

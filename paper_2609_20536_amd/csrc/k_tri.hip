@@ -1,4 +1,4 @@
-// Batched FP64 symmetric eigensolver for sector matrices of up to 1024 rows:
+// Batched FP64 symmetric eigensolver for sector matrices of up to 2048 rows:
 // Householder tridiagonalisation, bisection for every eigenvalue, inverse
 // iteration for the leading eigenvectors, back-transformation.
 //
@@ -47,7 +47,6 @@ namespace {
 // through them (bench: 31.5 -> 39.7 steps/s).
 constexpr int kRedThreads = 512;
 constexpr int kRedWaves = kRedThreads / 64;
-constexpr int kMvCols = kTriMaxN / 64;   // row segments of 64 per lane in A22 v
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
@@ -84,6 +83,19 @@ __device__ __forceinline__ void mv_partial(const double *A22, int np, int m, int
     const double *ra = A22 + (int64_t)k * np;
 #pragma unroll
     for (int q = 0; q < Q; ++q) acc[q] += ra[idx[q]] * vk;
+  }
+}
+
+// mv_partial<q> for q = nq (1 <= nq <= MAXN / 64), a chain of uniform tests
+template <int MAXN, int Q = 1>
+__device__ __forceinline__ void mv_dispatch(int nq, const double *A22, int np, int m, int k_lo,
+                                            int k_hi, const double *v, int lane, double *acc) {
+  if constexpr (Q <= MAXN / 64) {
+    if (nq == Q) {
+      mv_partial<Q>(A22, np, m, k_lo, k_hi, v, lane, acc);
+      return;
+    }
+    mv_dispatch<MAXN, Q + 1>(nq, A22, np, m, k_lo, k_hi, v, lane, acc);
   }
 }
 
@@ -147,15 +159,17 @@ __device__ void matrix_barrier(int32_t *cnt, int G, int b, double *fail_mark) {
 // barrier of the matrix's workgroups, from a buffer that alternates between
 // columns; the trailing update's tiles are split between them too, followed
 // by a second barrier.
-template <bool MULTI>
+template <bool MULTI, int MAXN>
 __device__ void tri_reduce_body(int nmat, int nsec, const int32_t *sec_n, const int32_t *npad,
                                 const int64_t *off, double *A, double *work, double *panel,
                                 double *xch, bool grouped) {
-  __shared__ double v[kTriMaxN];
-  __shared__ double w[kTriMaxN];
+  // row segments of 64 per lane in A22 v, per pass over the output rows
+  constexpr int kAcc = MAXN / 64 < 16 ? MAXN / 64 : 16;
+  __shared__ double v[MAXN];
+  __shared__ double w[MAXN];
   __shared__ double red[kRedWaves];
   __shared__ double q1[kNb], q2[kNb], vj_s[kNb], wj_s[kNb];
-  __shared__ double red_w[kRedWaves / 2][kTriMaxN];
+  __shared__ double red_w[kRedWaves / 2][MAXN];
   __shared__ double s_tau, s_scal;
   int mi = blockIdx.x, g = 0, G = 1;
   if (MULTI) {
@@ -285,35 +299,64 @@ __device__ void tri_reduce_body(int nmat, int nsec, const int32_t *sec_n, const 
         const double *A22 = Am + (int64_t)(j + 1) * np + (j + 1);
         for (int hh = 0; hh < Gl; ++hh) {
           const int h = MULTI ? g : hh;
-          double acc[kMvCols];
           const int part_id = h * kRedWaves + wave, nparts = Gt * kRedWaves;
           const int k_lo = (int)(((int64_t)part_id * m) / nparts);
           const int k_hi = (int)(((int64_t)(part_id + 1) * m) / nparts);
-          switch ((m + 63) >> 6) {
+          if constexpr (MAXN <= 1024) {
+            double acc[kAcc];
+            switch ((m + 63) >> 6) {
 #define GXY_MV(Q) \
   case Q: mv_partial<Q>(A22, np, m, k_lo, k_hi, v, lane, acc); break;
-            GXY_MV(1) GXY_MV(2) GXY_MV(3) GXY_MV(4) GXY_MV(5) GXY_MV(6) GXY_MV(7) GXY_MV(8)
-            GXY_MV(9) GXY_MV(10) GXY_MV(11) GXY_MV(12) GXY_MV(13) GXY_MV(14) GXY_MV(15)
-            GXY_MV(16)
+              GXY_MV(1) GXY_MV(2) GXY_MV(3) GXY_MV(4) GXY_MV(5) GXY_MV(6) GXY_MV(7) GXY_MV(8)
+              GXY_MV(9) GXY_MV(10) GXY_MV(11) GXY_MV(12) GXY_MV(13) GXY_MV(14) GXY_MV(15)
+              GXY_MV(16)
 #undef GXY_MV
-            default: break;
-          }
-          if (wave >= kRedWaves / 2) {
+              default: break;
+            }
+            if (wave >= kRedWaves / 2) {
 #pragma unroll
-            for (int q = 0; q < kMvCols; ++q) {
-              const int i = lane + 64 * q;
-              if (64 * q < m && i < m) red_w[wave - kRedWaves / 2][i] = acc[q];
+              for (int q = 0; q < kAcc; ++q) {
+                const int i = lane + 64 * q;
+                if (64 * q < m && i < m) red_w[wave - kRedWaves / 2][i] = acc[q];
+              }
+            }
+            __syncthreads();
+            if (wave < kRedWaves / 2) {
+#pragma unroll
+              for (int q = 0; q < kAcc; ++q) {
+                const int i = lane + 64 * q;
+                if (64 * q < m && i < m) red_w[wave][i] = acc[q] + red_w[wave][i];
+              }
+            }
+            __syncthreads();
+          } else {
+            // output rows in passes of 1024 (64 kAcc): the same sums per row
+            // as one pass, with half the accumulators per lane (a pass only
+            // decides which lanes hold which rows)
+            for (int r0 = 0; r0 < m; r0 += 64 * kAcc) {
+              const int mr = min(m - r0, 64 * kAcc);
+              double acc[kAcc];
+              mv_dispatch<64 * kAcc>((mr + 63) >> 6, A22 + r0, np, mr, k_lo, k_hi, v, lane,
+                                     acc);
+              if (wave >= kRedWaves / 2) {
+#pragma unroll
+                for (int q = 0; q < kAcc; ++q) {
+                  const int i = lane + 64 * q;
+                  if (64 * q < mr && i < mr) red_w[wave - kRedWaves / 2][r0 + i] = acc[q];
+                }
+              }
+              __syncthreads();
+              if (wave < kRedWaves / 2) {
+#pragma unroll
+                for (int q = 0; q < kAcc; ++q) {
+                  const int i = lane + 64 * q;
+                  if (64 * q < mr && i < mr)
+                    red_w[wave][r0 + i] = acc[q] + red_w[wave][r0 + i];
+                }
+              }
+              __syncthreads();
             }
           }
-          __syncthreads();
-          if (wave < kRedWaves / 2) {
-#pragma unroll
-            for (int q = 0; q < kMvCols; ++q) {
-              const int i = lane + 64 * q;
-              if (64 * q < m && i < m) red_w[wave][i] = acc[q] + red_w[wave][i];
-            }
-          }
-          __syncthreads();
           double *xo = xm + ((int64_t)(j & 1) * G + g) * n;
           for (int i = tid; i < m; i += kRedThreads) {
             double x = 0.0;
@@ -432,16 +475,19 @@ __device__ void tri_reduce_body(int nmat, int nsec, const int32_t *sec_n, const 
   }
 }
 
+template <int MAXN>
 __global__ __launch_bounds__(kRedThreads) void tri_reduce_kernel(
     int nmat, int nsec, const int32_t *sec_n, const int32_t *npad, const int64_t *off,
     double *A, double *work, double *panel, int grouped) {
-  tri_reduce_body<false>(nmat, nsec, sec_n, npad, off, A, work, panel, nullptr, grouped != 0);
+  tri_reduce_body<false, MAXN>(nmat, nsec, sec_n, npad, off, A, work, panel, nullptr,
+                               grouped != 0);
 }
 
+template <int MAXN>
 __global__ __launch_bounds__(kRedThreads) void tri_reduce_multi_kernel(
     int nmat, int nsec, const int32_t *sec_n, const int32_t *npad, const int64_t *off,
     double *A, double *work, double *panel, double *xch) {
-  tri_reduce_body<true>(nmat, nsec, sec_n, npad, off, A, work, panel, xch, true);
+  tri_reduce_body<true, MAXN>(nmat, nsec, sec_n, npad, off, A, work, panel, xch, true);
 }
 
 // zero the barrier counter of every matrix
@@ -490,12 +536,13 @@ __device__ int sturm_below(const double *d, const double *e2, int n, double x, d
   return cnt;
 }
 
+template <int MAXN>
 __global__ __launch_bounds__(kBisThreads) void tri_bisect_kernel(int nmat, int nsec,
                                                                  const int32_t *sec_n,
                                                                  const int32_t *npad,
                                                                  const int64_t *off,
                                                                  double *work) {
-  __shared__ double ds[kTriMaxN], e2s[kTriMaxN];
+  __shared__ double ds[MAXN], e2s[MAXN];
   __shared__ double red_s[3][kBisThreads / 64];
   const int mi = blockIdx.y;
   if (mi >= nmat) return;
@@ -596,13 +643,14 @@ __global__ __launch_bounds__(kBisThreads) void tri_bisect_kernel(int nmat, int n
 }
 
 constexpr int kValThreads = 256;
-constexpr int kValPer = kTriMaxN / kValThreads;
 
 // Make the eigenvalues non-increasing and put them on diag(A) (padding -1),
 // where the selection reads them. The reflectors lie right of the diagonal.
+template <int MAXN>
 __global__ __launch_bounds__(kValThreads) void tri_values_kernel(
     int nmat, int nsec, const int32_t *sec_n, const int32_t *npad, const int64_t *off,
     double *work, double *A) {
+  constexpr int kValPer = MAXN / kValThreads;
   const int mi = blockIdx.x;
   if (mi >= nmat) return;
   const int n = sec_n[mi % nsec];
@@ -664,6 +712,7 @@ __device__ __forceinline__ double start_value(int i, int c) {
   return (double)(z >> 11) * 0x1.0p-53 * 2.0 - 1.0;
 }
 
+template <int MAXN>
 __global__ __launch_bounds__(kInvThreads) void tri_invit_kernel(int nmat, int nsec,
                                                                 const int32_t *sec_n,
                                                                 const int32_t *npad,
@@ -671,7 +720,7 @@ __global__ __launch_bounds__(kInvThreads) void tri_invit_kernel(int nmat, int ns
                                                                 const double *work, double *U,
                                                                 double *Y, int kmax,
                                                                 const double *side) {
-  __shared__ double ds[kTriMaxN], es[kTriMaxN];
+  __shared__ double ds[MAXN], es[MAXN];
   __shared__ double mu[kMaxKq];
   __shared__ double tnorm_s;
   const int mi = blockIdx.x;
@@ -827,12 +876,13 @@ __global__ __launch_bounds__(kInvThreads) void tri_invit_kernel(int nmat, int ns
 // Classical Gram-Schmidt, twice, over the inverse-iteration vectors of a
 // matrix, in order c = 0, 1, ...; the vector being orthogonalised stays in
 // LDS over its two passes; 16 waves take the dot products.
+template <int MAXN>
 __global__ __launch_bounds__(kCgsThreads) void tri_cgs_kernel(int nmat, int nsec,
                                                              const int32_t *sec_n,
                                                              const int32_t *npad,
                                                              const int64_t *off, double *Y,
                                                              int kmax, const double *side) {
-  __shared__ double xs[kTriMaxN];
+  __shared__ double xs[MAXN];
   __shared__ double dot[kMaxKq];
   __shared__ double red[kCgsThreads / 64];
   const int mi = blockIdx.x;
@@ -884,18 +934,25 @@ __global__ __launch_bounds__(kCgsThreads) void tri_cgs_kernel(int nmat, int nsec
 // H = H_0 H_1 ... H_{n-3} (the last reflector applied first), written to V.
 // Columns are independent: workgroup (x, mi) takes columns x*16 .. x*16+15,
 // one per wave, so the waves never wait for each other.
-constexpr int kBackThreads = 1024;
-constexpr int kBackCols = kBackThreads / 64;
+// Workgroup shape by size: up to 1024 rows 1024 threads and blocks of 16
+// reflectors; up to 2048 rows 512 threads (a wave then holds 2 x 32 values
+// per lane) and blocks of 4 (the LDS stage stays at 64 KB). The blocking
+// only stages the reflectors: each column goes through them one by one in
+// the same order either way.
+template <int MAXN> struct BackShape {
+  static constexpr int threads = MAXN <= 1024 ? 1024 : 512;
+  static constexpr int blk = MAXN <= 1024 ? 16 : 4;
+  static constexpr int cols = threads / 64;
+};
 
 // One wave's column y (held in registers: lane l keeps rows l + 64 q, q < Q)
-// through the reflectors j = n-3 .. 0, in blocks of kBackBlk staged in LDS
-// by the whole workgroup (vb[t][r] = v_j[r] for r > j, else 0).
-constexpr int kBackBlk = 16;
-
-template <int Q>
+// through the reflectors j = n-3 .. 0, in blocks of BackShape::blk staged in
+// LDS by the whole workgroup (vb[t][r] = v_j[r] for r > j, else 0).
+template <int Q, int MAXN>
 __device__ __forceinline__ void back_column(const double *Am, const double *tau, int n, int np,
-                                            double *yc, bool active, double (*vb)[kTriMaxN],
+                                            double *yc, bool active, double (*vb)[MAXN],
                                             int lane, int tid) {
+  constexpr int kBackBlk = BackShape<MAXN>::blk, kBackThreads = BackShape<MAXN>::threads;
   double y[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
@@ -937,10 +994,24 @@ __device__ __forceinline__ void back_column(const double *Am, const double *tau,
   }
 }
 
-__global__ __launch_bounds__(kBackThreads) void tri_back_kernel(
+template <int Q, int MAXN>
+__device__ void back_dispatch(int nq, const double *Am, const double *tau, int n, int np,
+                              double *yc, bool active, double (*vb)[MAXN], int lane, int tid) {
+  if constexpr (Q <= MAXN / 64) {
+    if (nq == Q) {
+      back_column<Q, MAXN>(Am, tau, n, np, yc, active, vb, lane, tid);
+      return;
+    }
+    back_dispatch<Q + 1, MAXN>(nq, Am, tau, n, np, yc, active, vb, lane, tid);
+  }
+}
+
+template <int MAXN>
+__global__ __launch_bounds__(BackShape<MAXN>::threads) void tri_back_kernel(
     int nmat, int nsec, const int32_t *sec_n, const int32_t *npad, const int64_t *off,
     const double *A, const double *work, double *V, double *Y, int kmax, const double *side) {
-  __shared__ double vb[kBackBlk][kTriMaxN];
+  constexpr int kBackThreads = BackShape<MAXN>::threads, kBackCols = BackShape<MAXN>::cols;
+  __shared__ double vb[BackShape<MAXN>::blk][MAXN];
   const int mi = blockIdx.y;
   if (mi >= nmat) return;
   if (side && (int)*side != mi / nsec) return;
@@ -955,14 +1026,7 @@ __global__ __launch_bounds__(kBackThreads) void tri_back_kernel(
   const int c = blockIdx.x * kBackCols + wave;
   const bool active = c < kq;
   double *yc = Ym + (int64_t)(active ? c : 0) * np;
-  switch ((n + 63) >> 6) {
-#define GXY_BK(Q) \
-  case Q: back_column<Q>(Am, tau, n, np, yc, active, vb, lane, tid); break;
-    GXY_BK(1) GXY_BK(2) GXY_BK(3) GXY_BK(4) GXY_BK(5) GXY_BK(6) GXY_BK(7) GXY_BK(8)
-    GXY_BK(9) GXY_BK(10) GXY_BK(11) GXY_BK(12) GXY_BK(13) GXY_BK(14) GXY_BK(15) GXY_BK(16)
-#undef GXY_BK
-    default: break;
-  }
+  back_dispatch<1, MAXN>((n + 63) >> 6, Am, tau, n, np, yc, active, vb, lane, tid);
   __syncthreads();
   if (active)
     for (int r = lane; r < n; r += 64) Vm[(int64_t)r * np + c] = yc[r];
@@ -975,11 +1039,26 @@ __global__ __launch_bounds__(kBackThreads) void tri_back_kernel(
   }
 }
 
-}  // namespace
+// co-resident workgroups of the multi-workgroup kernel (per process, one
+// device type; 0 without cooperative launch)
+template <int MAXN>
+int co_resident() {
+  static const int n = []() {
+    int dev = 0, per_cu = 0, cus = 0, coop = 0;
+    GXY_HIP(hipGetDevice(&dev));
+    GXY_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+    GXY_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    GXY_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void *>(tri_reduce_multi_kernel<MAXN>), kRedThreads, 0));
+    return coop ? per_cu * cus : 0;
+  }();
+  return n;
+}
 
-void launch_tri_values(int nmat, int nsec, const int *h_sec_n, const int32_t *d_sec_n,
-                       const int32_t *d_npad, const int64_t *d_off, double *A, double *Y,
-                       double *X, double *work, bool allow_multi, hipStream_t s) {
+template <int MAXN>
+void tri_values_impl(int nmat, int nsec, const int *h_sec_n, const int32_t *d_sec_n,
+                     const int32_t *d_npad, const int64_t *d_off, double *A, double *Y,
+                     double *X, double *work, bool allow_multi, hipStream_t s) {
   // Y serves as the panel scratch of the reduction (G private panels of
   // 2 n kNb values per matrix <= npad^2), X as the exchange of partial
   // matrix-vector products (2 G n <= npad^2)
@@ -989,17 +1068,6 @@ void launch_tri_values(int nmat, int nsec, const int *h_sec_n, const int32_t *d_
     blocks += tri_groups(n);
     ncols = std::max(ncols, n - 2);
   }
-  // co-resident workgroups of the multi-workgroup kernel (per process, one
-  // device type; 0 without cooperative launch)
-  static const int co_resident = []() {
-    int dev = 0, per_cu = 0, cus = 0, coop = 0;
-    GXY_HIP(hipGetDevice(&dev));
-    GXY_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
-    GXY_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    GXY_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, reinterpret_cast<const void *>(tri_reduce_multi_kernel), kRedThreads, 0));
-    return coop ? per_cu * cus : 0;
-  }();
   const char *env = getenv("GXY_TRI_MULTI");
   // (a launch whose largest sector qualifies groups the sums the shared way
   // even on one workgroup per matrix, so the bits do not depend on whether
@@ -1008,42 +1076,78 @@ void launch_tri_values(int nmat, int nsec, const int *h_sec_n, const int32_t *d_
   const int min_rows = env_min ? atoi(env_min) : kMultiMinRows;
   const bool grouped = ncols + 2 >= min_rows;
   const bool multi = allow_multi && !(env && env[0] == '0') && grouped && blocks > nmat &&
-                     blocks <= co_resident;
+                     blocks <= co_resident<MAXN>();
   if (multi) {
     hipLaunchKernelGGL(tri_counters_kernel, dim3((nmat + 255) / 256), dim3(256), 0, s, nmat,
                        d_npad, d_off, work);
     GXY_CHECK_LAUNCH();
     void *args[] = {&nmat, &nsec, &d_sec_n, &d_npad, &d_off, &A, &work, &Y, &X};
-    GXY_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(tri_reduce_multi_kernel),
-                                       dim3(blocks), dim3(kRedThreads), args, 0, s));
+    GXY_HIP(hipLaunchCooperativeKernel(
+        reinterpret_cast<const void *>(tri_reduce_multi_kernel<MAXN>), dim3(blocks),
+        dim3(kRedThreads), args, 0, s));
   } else {
-    hipLaunchKernelGGL(tri_reduce_kernel, dim3(nmat), dim3(kRedThreads), 0, s, nmat, nsec,
+    hipLaunchKernelGGL(tri_reduce_kernel<MAXN>, dim3(nmat), dim3(kRedThreads), 0, s, nmat, nsec,
                        d_sec_n, d_npad, d_off, A, work, Y, grouped ? 1 : 0);
     GXY_CHECK_LAUNCH();
   }
-  hipLaunchKernelGGL(tri_bisect_kernel, dim3(kTriMaxN / kBisPerBlock, nmat), dim3(kBisThreads),
-                     0, s, nmat, nsec, d_sec_n, d_npad, d_off, work);
+  hipLaunchKernelGGL(tri_bisect_kernel<MAXN>, dim3(MAXN / kBisPerBlock, nmat),
+                     dim3(kBisThreads), 0, s, nmat, nsec, d_sec_n, d_npad, d_off, work);
   GXY_CHECK_LAUNCH();
-  hipLaunchKernelGGL(tri_values_kernel, dim3(nmat), dim3(kValThreads), 0, s, nmat, nsec, d_sec_n,
-                     d_npad, d_off, work, A);
+  hipLaunchKernelGGL(tri_values_kernel<MAXN>, dim3(nmat), dim3(kValThreads), 0, s, nmat, nsec,
+                     d_sec_n, d_npad, d_off, work, A);
   GXY_CHECK_LAUNCH();
 }
 
-void launch_tri_vectors(int nmat, int nsec, const int32_t *d_sec_n, const int32_t *d_npad,
-                        const int64_t *d_off, const double *A, double *V, double *Y,
-                        const double *work, int kmax, const double *d_side, hipStream_t s) {
-  if (kmax > kMaxKq) fail(GXY_EUNSUPPORTED, "tridiagonal path: more than 128 vectors");
+template <int MAXN>
+void tri_vectors_impl(int nmat, int nsec, const int32_t *d_sec_n, const int32_t *d_npad,
+                      const int64_t *d_off, const double *A, double *V, double *Y,
+                      const double *work, int kmax, const double *d_side, hipStream_t s) {
   // V serves as the factor scratch of the inverse iteration until tri_back
-  hipLaunchKernelGGL(tri_invit_kernel, dim3(nmat), dim3(kInvThreads), 0, s, nmat, nsec,
+  hipLaunchKernelGGL(tri_invit_kernel<MAXN>, dim3(nmat), dim3(kInvThreads), 0, s, nmat, nsec,
                      d_sec_n, d_npad, d_off, work, V, Y, kmax, d_side);
   GXY_CHECK_LAUNCH();
-  hipLaunchKernelGGL(tri_cgs_kernel, dim3(nmat), dim3(kCgsThreads), 0, s, nmat, nsec, d_sec_n,
-                     d_npad, d_off, Y, kmax, d_side);
+  hipLaunchKernelGGL(tri_cgs_kernel<MAXN>, dim3(nmat), dim3(kCgsThreads), 0, s, nmat, nsec,
+                     d_sec_n, d_npad, d_off, Y, kmax, d_side);
   GXY_CHECK_LAUNCH();
-  const int nx = (std::min(kmax, kMaxKq) + kBackCols - 1) / kBackCols;
-  hipLaunchKernelGGL(tri_back_kernel, dim3(std::max(nx, 1), nmat), dim3(kBackThreads), 0, s,
-                     nmat, nsec, d_sec_n, d_npad, d_off, A, work, V, Y, kmax, d_side);
+  constexpr int cols = BackShape<MAXN>::cols;
+  const int nx = (std::min(kmax, kMaxKq) + cols - 1) / cols;
+  hipLaunchKernelGGL(tri_back_kernel<MAXN>, dim3(std::max(nx, 1), nmat),
+                     dim3(BackShape<MAXN>::threads), 0, s, nmat, nsec, d_sec_n, d_npad, d_off, A,
+                     work, V, Y, kmax, d_side);
   GXY_CHECK_LAUNCH();
+}
+
+}  // namespace
+
+// The kernels are instantiated for matrices of up to 1024 and up to
+// kTriMaxN = 2048 rows; a launch takes the smaller instantiation that holds
+// its largest sector (the arithmetic is the same in both, so the choice
+// changes no value).
+void launch_tri_values(int nmat, int nsec, const int *h_sec_n, const int32_t *d_sec_n,
+                       const int32_t *d_npad, const int64_t *d_off, double *A, double *Y,
+                       double *X, double *work, bool allow_multi, hipStream_t s) {
+  int maxn = 0;
+  for (int k = 0; k < nsec; ++k) maxn = std::max(maxn, h_sec_n[k]);
+  if (maxn > kTriMaxN) fail(GXY_EUNSUPPORTED, "tridiagonal path: sector above 2048 rows");
+  if (maxn <= 1024)
+    tri_values_impl<1024>(nmat, nsec, h_sec_n, d_sec_n, d_npad, d_off, A, Y, X, work,
+                          allow_multi, s);
+  else
+    tri_values_impl<kTriMaxN>(nmat, nsec, h_sec_n, d_sec_n, d_npad, d_off, A, Y, X, work,
+                              allow_multi, s);
+}
+
+void launch_tri_vectors(int nmat, int nsec, int maxn, const int32_t *d_sec_n,
+                        const int32_t *d_npad, const int64_t *d_off, const double *A, double *V,
+                        double *Y, const double *work, int kmax, const double *d_side,
+                        hipStream_t s) {
+  if (kmax > kMaxKq) fail(GXY_EUNSUPPORTED, "tridiagonal path: more than 128 vectors");
+  if (maxn > kTriMaxN) fail(GXY_EUNSUPPORTED, "tridiagonal path: sector above 2048 rows");
+  if (maxn <= 1024)
+    tri_vectors_impl<1024>(nmat, nsec, d_sec_n, d_npad, d_off, A, V, Y, work, kmax, d_side, s);
+  else
+    tri_vectors_impl<kTriMaxN>(nmat, nsec, d_sec_n, d_npad, d_off, A, V, Y, work, kmax, d_side,
+                               s);
 }
 
 }  // namespace gxy

@@ -181,6 +181,16 @@ def test_eigh_above_tridiagonal_limit_uses_jacobi(ctx):
     assert ctx.last_sweeps > 0
 
 
+def test_eigh_above_2048_rows_uses_jacobi(ctx):
+    rng = np.random.default_rng(2049)
+    X = rng.standard_normal((2049, 2060))
+    A = X @ X.T
+    w, V = ctx.test_eigh(A, 2, kmax=32)
+    assert ctx.last_sweeps > 0
+    wr = np.sort(np.linalg.eigvalsh(A))[::-1]
+    assert np.max(np.abs(np.sort(w)[::-1] - wr)) <= 5e-15 * 2049 * wr[0]
+
+
 @pytest.mark.parametrize("method", EIG_METHODS)
 def test_eigh_graded_spectrum(ctx, method):
     """Spectrum over 14 decades, like the HOTRG environments: eigenvalues to
@@ -222,10 +232,12 @@ def test_eigh_diagonal_and_block(ctx, method):
     _check_eig(B, w, V)
 
 
-@pytest.mark.parametrize("n,kmax", [(300, 64), (513, 48), (777, 128), (1024, 64)])
+@pytest.mark.parametrize("n,kmax", [(300, 64), (513, 48), (777, 128), (1024, 64), (1025, 96),
+                                    (1500, 96), (2048, 128)])
 def test_tridiagonal_leading_vectors_of_large_sectors(ctx, n, kmax):
-    """Sector sizes of Dcut = 64 runs: all eigenvalues, the kmax leading
-    eigenvectors (residual and orthogonality at eps ||A||), graded spectrum."""
+    """Sector sizes of Dcut = 64 and 96 runs (above 1024 rows the kernels'
+    2048-row instantiation): all eigenvalues, the kmax leading eigenvectors
+    (residual and orthogonality at eps ||A||), graded spectrum."""
     rng = np.random.default_rng(n)
     Q = np.linalg.qr(rng.standard_normal((n, n)))[0]
     lam = np.exp(-np.linspace(0.0, 30.0, n))
@@ -243,7 +255,7 @@ def test_tridiagonal_leading_vectors_of_large_sectors(ctx, n, kmax):
     assert not np.any(V[:, kmax:])
 
 
-@pytest.mark.parametrize("n", [800, 1024])
+@pytest.mark.parametrize("n", [800, 1024, 1600])
 def test_tridiagonal_shared_reduction_same_bits(ctx, n, monkeypatch):
     """Sectors of at least 384 rows are reduced by several workgroups of one
     cooperative launch (a barrier of the matrix's workgroups per column); the
