@@ -473,6 +473,8 @@ static void run_launch(const Launch &L, const GGroup *d_grp, const int64_t *d_ta
                        hipStream_t s, int prec = GXY_PREC_FP64, bool dma = false) {
   GroupedGemm g{};
   g.dma = dma;
+  g.sym = L.sym;
+  if (L.sym && beta != 0.0) fail(GXY_EDEVICE, "symmetric launch with beta != 0");
   g.prec = prec;
   g.ngroups = L.ngroups;
   g.total_tiles = L.total_tiles;

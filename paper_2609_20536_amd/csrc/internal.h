@@ -116,6 +116,10 @@ struct GroupedGemm {
   // FP64 contiguous launches: stage operands by direct global -> LDS loads
   // (another summation order than the register-staged kernel)
   bool dma;
+  // symmetric groups (C = A A^T, square tiles, beta = 0): tile t of a group
+  // is (tm, tn) with tm >= tn in row-major triangular order, and each
+  // off-diagonal tile also writes its transpose
+  bool sym;
 };
 
 void grouped_gemm(const GroupedGemm &g, hipStream_t s);

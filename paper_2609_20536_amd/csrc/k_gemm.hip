@@ -119,7 +119,7 @@ template <int BM, int BN, int BK, int WGM, int WGN, int PREC, class Addr, class 
 __device__ __forceinline__ void gemm_mainloop(const Addr &ad, int M, int N, int K, int m0,
                                               int n0, double *C, double alpha, double beta,
                                               Stage<BK, BM, PREC> &sa, Stage<BK, BN, PREC> &sb,
-                                              LoadF &load, StoreF &store) {
+                                              LoadF &load, StoreF &store, bool mirror = false) {
   constexpr int WM = BM / WGM, WN = BN / WGN;
   constexpr int FM = WM / 16, FN = WN / 16;
   const int lane = threadIdx.x & 63;
@@ -207,6 +207,10 @@ __device__ __forceinline__ void gemm_mainloop(const Addr &ad, int M, int N, int 
         double *dst = C + ad.c_m(m) + noff;
         const double v = alpha * (double)acc[i][j][r];
         *dst = (beta == 0.0) ? v : v + beta * (*dst);
+        // symmetric launches (beta = 0, M = N): the transposed element, which
+        // the tile across the diagonal would compute from the same products
+        // in the same order
+        if (mirror) C[ad.c_m(n) + ad.c_n(m)] = v;
       }
     }
   }
@@ -218,7 +222,7 @@ __device__ __forceinline__ void gemm_tile(const Addr &ad, int M, int N, int K, i
                                           const double *__restrict__ A,
                                           const double *__restrict__ B, double *C,
                                           double alpha, double beta, Stage<BK, BM, PREC> &sa,
-                                          Stage<BK, BN, PREC> &sb) {
+                                          Stage<BK, BN, PREC> &sb, bool mirror = false) {
   constexpr int NT = 64 * WGM * WGN;
   constexpr int WM = BM / WGM, WN = BN / WGN;
   constexpr int FM = WM / 16, FN = WN / 16;
@@ -392,7 +396,7 @@ __device__ __forceinline__ void gemm_tile(const Addr &ad, int M, int N, int K, i
   };
   if (K > 0) load_offsets(0);
   gemm_mainloop<BM, BN, BK, WGM, WGN, PREC>(ad, M, N, K, m0, n0, C, alpha, beta, sa, sb,
-                                            load_slice, store);
+                                            load_slice, store, mirror);
   }
 }
 
@@ -437,11 +441,20 @@ __global__ __launch_bounds__(64 * WGM * WGN) void ggemm_kernel(GroupedGemm g) {
   const GGroup G = g.groups[lo];
   const int local = t - G.tile_start;
   const int tiles_n = (G.N + BN - 1) / BN;
-  const int tm = local / tiles_n, tn = local % tiles_n;
+  int tm = local / tiles_n, tn = local % tiles_n;
+  if (g.sym) {
+    // row-major lower triangle: tile (tm, tn), tn <= tm, is number
+    // tm (tm + 1) / 2 + tn
+    tm = (int)((sqrt(8.0 * local + 1.0) - 1.0) * 0.5);
+    while (tm * (tm + 1) / 2 > local) --tm;
+    while ((tm + 1) * (tm + 2) / 2 <= local) ++tm;
+    tn = local - tm * (tm + 1) / 2;
+  }
   TableAddr ad{g.tab + G.ar, g.tab + G.ac, g.tab + G.br, g.tab + G.bc, g.tab + G.cr,
                g.tab + G.cc};
   gemm_tile<BM, BN, BK, WGM, WGN, KFA, NFB, PREC>(ad, G.M, G.N, G.K, tm * BM, tn * BN, g.A, g.B,
-                                                  g.C, g.alpha, g.beta, sa, sb);
+                                                  g.C, g.alpha, g.beta, sa, sb,
+                                                  g.sym && tm != tn);
 }
 
 // Grouped launch of contiguous charge blocks (GroupedGemm::contig): group
@@ -661,6 +674,8 @@ void launch_tile_prec(const GemmDesc &g, hipStream_t s) {
 
 template <int BM, int BN, int BK, int WGM, int WGN, int PREC>
 void launch_grouped(const GroupedGemm &g, hipStream_t s) {
+  if (g.sym && (BM != BN || g.contig || g.beta != 0.0))
+    fail(GXY_EDEVICE, "symmetric grouped GEMM: square tiles, table addressing, beta = 0");
   dim3 grid(g.total_tiles), block(64 * WGM * WGN);
   if (g.contig) {
     bool dma = false;

@@ -36,6 +36,10 @@ struct Launch {
   int32_t first_group = 0, ngroups = 0, total_tiles = 0, tile = 64;
   bool kfast_a = false, nfast_b = false;
   bool contig = false;  // groups of contiguous ranges (GroupedGemm::contig)
+  // symmetric groups: C = A A^T (M = N, the rows' and columns' tables the
+  // same, B read through A's tables transposed); only the tiles on and below
+  // the diagonal run, each off-diagonal one writing its transpose as well
+  bool sym = false;
   double flops = 0.0;  // algorithmic 2 M N K summed over groups
   double bytes = 0.0;  // algorithmic FP64 bytes: A, B read once, C written once
   double c_bytes = 0.0;  // 8 M N over the groups: C read once more when beta != 0

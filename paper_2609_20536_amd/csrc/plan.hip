@@ -84,13 +84,16 @@ int choose_tile(const std::vector<GSpec> &gs) {
 }
 
 Launch finish_launch(TablePlan &tp, const std::vector<GSpec> &gs, bool kfa, bool nfb,
-                     int force_tile = 0, bool contig = false) {
+                     int force_tile = 0, bool contig = false, bool sym = false) {
   Launch L;
   L.first_group = (int32_t)tp.groups.size();
   L.kfast_a = kfa;
   L.nfast_b = nfb;
   L.contig = contig;
+  L.sym = sym;
   L.tile = force_tile ? force_tile : choose_tile(gs);
+  if (sym && tile_rows(L.tile) != tile_cols(L.tile))
+    fail(GXY_EDEVICE, "symmetric launch needs square tiles");
   for (const auto &g : gs) {
     if (g.M <= 0 || g.N <= 0) continue;
     GGroup G;
@@ -105,7 +108,14 @@ Launch finish_launch(TablePlan &tp, const std::vector<GSpec> &gs, bool kfa, bool
     G.cr = g.cr;
     G.cc = g.cc;
     const int tm = tile_rows(L.tile), tn = tile_cols(L.tile);
-    L.total_tiles += ((g.M + tm - 1) / tm) * ((g.N + tn - 1) / tn);
+    if (sym) {
+      if (g.M != g.N || g.ar != g.bc || g.ac != g.br)
+        fail(GXY_EDEVICE, "symmetric launch: a group is not C = A A^T");
+      const int64_t t = (g.M + tm - 1) / tm;
+      L.total_tiles += (int32_t)(t * (t + 1) / 2);
+    } else {
+      L.total_tiles += ((g.M + tm - 1) / tm) * ((g.N + tn - 1) / tn);
+    }
     L.flops += 2.0 * g.M * g.N * (double)g.K;
     L.bytes += 8.0 * ((double)g.M * g.K + (double)g.K * g.N + (double)g.M * g.N);
     L.c_bytes += 8.0 * (double)g.M * g.N;
@@ -152,7 +162,9 @@ void plan_env(const StepLegs &S, bool right, TablePlan &tp, Launch out[3]) {
       g.cc = put(tp, cc);
       gs.push_back(g);
     }
-    out[0] = finish_launch(tp, gs, false, true);
+    // (C = A A^T: the output rows and columns are the same pairs, placed
+    // by cr and cc from one list)
+    out[0] = finish_launch(tp, gs, false, true, 0, false, true);
   }
   // --- bottom Gram: rows (x, i), reduction (y, d).  left: x = l2, y = r2,
   // key q_l2 - q_i = q_r2 - q_d.  right: x = r2, y = l2, key q_r2 + q_i =
@@ -185,7 +197,7 @@ void plan_env(const StepLegs &S, bool right, TablePlan &tp, Launch out[3]) {
       g.cc = put(tp, cc);
       gs.push_back(g);
     }
-    out[1] = finish_launch(tp, gs, true, false);
+    out[1] = finish_launch(tp, gs, true, false, 0, false, true);
   }
   // --- E[(x1,x2),(x1',x2')] = sum_{i,i'} envA[x1,i,x1',i'] envB[x2,i,x2',i']
   // kappa = q_i - q_i'.  left: rows (l1,l1') with q_l1' - q_l1 = kappa, cols

@@ -24,7 +24,13 @@ void emulate(const TablePlan &tp, const Launch &L, const std::vector<double> &A,
     auto offA = [&](int m, int k) { return L.contig ? T(g.ar, m) + g.ac + k : T(g.ar, m) + T(g.ac, k); };
     auto offB = [&](int k, int n) { return L.contig ? g.br + (int64_t)k * g.bc + n : T(g.br, k) + T(g.bc, n); };
     auto offC = [&](int m, int n) { return L.contig ? T(g.ar, m) + g.cc + n : T(g.cr, m) + T(g.cc, n); };
+    // symmetric launches (Launch::sym): only tiles on and below the diagonal
+    // run; an off-diagonal one also writes the transposed element
+    const int tsz = L.tile == 256 ? 128 : L.tile;
+    CHECK(!L.sym || (g.M == g.N && L.tile != 256 && beta == 0.0), "sym launch shape");
     for (int m = 0; m < g.M; ++m) for (int n = 0; n < g.N; ++n) {
+      if (L.sym && m / tsz < n / tsz) continue;
+      const bool mirror = L.sym && m / tsz > n / tsz;
       double acc = 0;
       for (int k = 0; k < g.K; ++k) {
         int64_t ia = offA(m, k), ib = offB(k, n);
@@ -37,6 +43,14 @@ void emulate(const TablePlan &tp, const Launch &L, const std::vector<double> &A,
       if (ic >= 0 && ic < (int64_t)C.size()) {
         C[ic] = alpha * acc + (beta == 0.0 ? 0.0 : beta * C[ic]);
         if (hits) (*hits)[ic]++;
+      }
+      if (mirror) {
+        int64_t it = offC(n, m);
+        CHECK(it >= 0 && it < (int64_t)C.size(), "C off (mirror)");
+        if (it >= 0 && it < (int64_t)C.size()) {
+          C[it] = alpha * acc;
+          if (hits) (*hits)[it]++;
+        }
       }
     }
   }
