@@ -10,7 +10,8 @@ computed once with this script and stored.
 
     python tests/golden/make_golden.py <job> [<job> ...]
     python tests/golden/make_golden.py --sector-gaps <job> ...   (re-run, add gaps)
-    python tests/golden/make_golden.py --spread <job> ...        (also the spread)
+    python tests/golden/make_golden.py --spread <job> ...        (also the spread;
+                                                   GOLDEN_JOBS=3: runs in parallel)
     python tests/golden/make_golden.py --list
 """
 
@@ -78,7 +79,22 @@ def _sector_gaps(r):
     return [s.sector_gap if math.isfinite(s.sector_gap) else None for s in r.steps]
 
 
-def spread_of(pt, runs=2, base=None):
+def _run_seeded(args):
+    pt, seed = args
+    return o.run_point(**pt) if seed == 0 else o.run_point(**pt, basis_seed=seed)
+
+
+def _runs(pt, seeds, jobs):
+    """Oracle runs of one point for the given basis seeds (0: the default
+    eigensolve), in up to `jobs` worker processes."""
+    if jobs <= 1 or len(seeds) <= 1:
+        return [_run_seeded((pt, s)) for s in seeds]
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(min(jobs, len(seeds))) as ex:
+        return list(ex.map(_run_seeded, [(pt, s) for s in seeds]))
+
+
+def spread_of(pt, runs=2, base=None, others=None):
     """Largest |d ln Z/V| and |d m| of the oracle between its default run and
     runs whose sector eigensolves use a random orthogonal basis (an equally
     valid FP64 backward-stable eigensolve with a different rounding pattern).
@@ -86,9 +102,10 @@ def spread_of(pt, runs=2, base=None):
     vectors -- and so the run -- are fixed by the FP64 eigensolve only to this
     level."""
     base = base or o.run_point(**pt)
+    if others is None:
+        others = [o.run_point(**pt, basis_seed=seed) for seed in range(1, runs + 1)]
     sp, spm = 0.0, 0.0
-    for seed in range(1, runs + 1):
-        r = o.run_point(**pt, basis_seed=seed)
+    for r in others:
         sp = max(sp, abs(r.lnz_per_site - base.lnz_per_site))
         for a, b in ((r.m_cos1, base.m_cos1), (r.m_cos2, base.m_cos2)):
             if a == a and b == b:
@@ -96,14 +113,16 @@ def spread_of(pt, runs=2, base=None):
     return sp, spm
 
 
-def annotate(name, spread_runs=0):
+def annotate(name, spread_runs=0, jobs=1):
     """Re-run a stored job with the current oracle and add the per-step
     within-sector cut gaps (and, with spread_runs > 0, the spread over
     equally valid eigensolves). The re-run must reproduce the stored
-    ln Z/V; the stored values are kept."""
+    ln Z/V; the stored values are kept. The runs are independent: with
+    jobs > 1 they go to that many worker processes."""
     path = os.path.join(HERE, name + ".json")
     gd = json.load(open(path))
-    base = o.run_point(**gd["point"])
+    allruns = _runs(gd["point"], list(range(spread_runs + 1)), jobs)
+    base, others = allruns[0], allruns[1:]
     d = abs(base.lnz_per_site - gd["lnz_per_site"])
     bound = max(1e-12, 10 * gd.get("spread", 0.0))
     if d > bound and spread_runs == 0:
@@ -113,7 +132,7 @@ def annotate(name, spread_runs=0):
         raise SystemExit(f"{name}: re-run differs from the stored ln Z/V by {d:.2e}")
     gd["sector_gap"] = _sector_gaps(base)
     if spread_runs > 0:
-        sp, spm = spread_of(gd["point"], spread_runs, base)
+        sp, spm = spread_of(gd["point"], spread_runs, base, others)
         gd["spread"] = max(sp, d)
         dm = [abs(getattr(base, k) - gd[k]) for k in ("m_cos1", "m_cos2")
               if gd[k] is not None]
@@ -162,8 +181,9 @@ if __name__ == "__main__":
         # --sector-gaps: add the within-sector cut gaps; --spread: also the
         # spread over two re-rotated eigensolves (--spread1: over one)
         runs = {"--spread": 2, "--spread1": 1}.get(sys.argv[1], 0)
+        jobs_env = int(os.environ.get("GOLDEN_JOBS", "1"))   # worker processes
         for name in sys.argv[2:]:
-            print(name, "spread", annotate(name, runs), flush=True)
+            print(name, "spread", annotate(name, runs, jobs_env), flush=True)
         sys.exit(0)
     for name in sys.argv[1:]:
         r = run_job(name, J[name])
