@@ -1081,10 +1081,23 @@ void tri_values_impl(int nmat, int nsec, const int *h_sec_n, const int32_t *d_se
     hipLaunchKernelGGL(tri_counters_kernel, dim3((nmat + 255) / 256), dim3(256), 0, s, nmat,
                        d_npad, d_off, work);
     GXY_CHECK_LAUNCH();
-    void *args[] = {&nmat, &nsec, &d_sec_n, &d_npad, &d_off, &A, &work, &Y, &X};
-    GXY_HIP(hipLaunchCooperativeKernel(
-        reinterpret_cast<const void *>(tri_reduce_multi_kernel<MAXN>), dim3(blocks),
-        dim3(kRedThreads), args, 0, s));
+    // The cooperative launch makes every workgroup of the grid resident
+    // together, also next to other contexts' reductions. A regular launch of
+    // the same grid (GXY_TRI_COOP=0) gets there as long as no other
+    // multi-workgroup reduction competes for the device (the grid fits an
+    // idle device; other kernels' workgroups end by themselves): the same
+    // values and speed, for tools that fail on cooperative launches.
+    const char *coop = getenv("GXY_TRI_COOP");
+    if (coop && coop[0] == '0') {
+      hipLaunchKernelGGL(tri_reduce_multi_kernel<MAXN>, dim3(blocks), dim3(kRedThreads), 0, s,
+                         nmat, nsec, d_sec_n, d_npad, d_off, A, work, Y, X);
+      GXY_CHECK_LAUNCH();
+    } else {
+      void *args[] = {&nmat, &nsec, &d_sec_n, &d_npad, &d_off, &A, &work, &Y, &X};
+      GXY_HIP(hipLaunchCooperativeKernel(
+          reinterpret_cast<const void *>(tri_reduce_multi_kernel<MAXN>), dim3(blocks),
+          dim3(kRedThreads), args, 0, s));
+    }
   } else {
     hipLaunchKernelGGL(tri_reduce_kernel<MAXN>, dim3(nmat), dim3(kRedThreads), 0, s, nmat, nsec,
                        d_sec_n, d_npad, d_off, A, work, Y, grouped ? 1 : 0);

@@ -256,17 +256,19 @@ def test_tridiagonal_leading_vectors_of_large_sectors(ctx, n, kmax):
 
 
 @pytest.mark.parametrize("n", [800, 1024, 1600])
-def test_tridiagonal_shared_reduction_same_bits(ctx, n, monkeypatch):
+@pytest.mark.parametrize("other", ["GXY_TRI_MULTI", "GXY_TRI_COOP"])
+def test_tridiagonal_shared_reduction_same_bits(ctx, n, other, monkeypatch):
     """Sectors of at least 384 rows are reduced by several workgroups of one
     cooperative launch (a barrier of the matrix's workgroups per column); the
     matrix-vector sums are
     grouped the same way as when one workgroup runs the groups in turn, so
-    both give the same eigenvalues and vectors bit for bit."""
+    both give the same eigenvalues and vectors bit for bit; so does the same
+    grid launched as a regular (not cooperative) one."""
     rng = np.random.default_rng(n + 1)
     X = rng.standard_normal((n, n + 7))
     A = X @ X.T
     w1, V1 = ctx.test_eigh(A, 2, kmax=64)
-    monkeypatch.setenv("GXY_TRI_MULTI", "0")
+    monkeypatch.setenv(other, "0")
     w0, V0 = ctx.test_eigh(A, 2, kmax=64)
     assert np.array_equal(w0, w1)
     assert np.array_equal(V0, V1)
