@@ -45,10 +45,9 @@
  *   GXY_TRI_MULTI_MIN      smallest sector (rows) shared between workgroups
  *                          (default 384)
  *   GXY_TRI_COOP           0: launch the shared reduction as a regular grid
- *                          instead of a cooperative one (same results; only
- *                          for a context whose reductions never run next to
- *                          another context's, e.g. under profilers that
- *                          fail on cooperative launches)
+ *                          instead of a cooperative one (same results and
+ *                          speed; for profilers that fail on cooperative
+ *                          launches)
  *   GXY_PROJ_TILE          64 | 128 | 256: projection tile for every run
  *                          (else the autotuned one for the Dcut, else by
  *                          tile fill); results do not depend on it

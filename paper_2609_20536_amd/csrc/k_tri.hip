@@ -1081,12 +1081,13 @@ void tri_values_impl(int nmat, int nsec, const int *h_sec_n, const int32_t *d_se
     hipLaunchKernelGGL(tri_counters_kernel, dim3((nmat + 255) / 256), dim3(256), 0, s, nmat,
                        d_npad, d_off, work);
     GXY_CHECK_LAUNCH();
-    // The cooperative launch makes every workgroup of the grid resident
-    // together, also next to other contexts' reductions. A regular launch of
-    // the same grid (GXY_TRI_COOP=0) gets there as long as no other
-    // multi-workgroup reduction competes for the device (the grid fits an
-    // idle device; other kernels' workgroups end by themselves): the same
-    // values and speed, for tools that fail on cooperative launches.
+    // The workgroups of a matrix wait for each other, so the whole grid must
+    // be resident at once: the cooperative launch has the runtime promise
+    // that. The grid is sized to fit an idle device (co_resident), and the
+    // other kernels' workgroups end by themselves, so a regular launch of the
+    // same grid (GXY_TRI_COOP=0) gets there too, with the same values and
+    // speed, for tools that fail on cooperative launches. (Neither form is
+    // meant for two such reductions at once: batch workers never share.)
     const char *coop = getenv("GXY_TRI_COOP");
     if (coop && coop[0] == '0') {
       hipLaunchKernelGGL(tri_reduce_multi_kernel<MAXN>, dim3(blocks), dim3(kRedThreads), 0, s,
