@@ -489,6 +489,9 @@ class RunResult:
     msq_cos2: float = float("nan")   # the same for cos q theta
     chi0: float = float("nan")       # beta V (<m^2> - <m>^2), cos theta
     chi0_n: float = float("nan")     # the same for cos q theta
+    # (keep_tensor) the final normalised tensor and its leg labels
+    tensor: Optional[np.ndarray] = None
+    labels_hv: Optional[Tuple[np.ndarray, np.ndarray]] = None
 
 
 def _norm(T: np.ndarray, kind: str) -> float:
@@ -502,7 +505,8 @@ def _norm(T: np.ndarray, kind: str) -> float:
 def hotrg_run(T: np.ndarray, imps: Dict[int, np.ndarray], lab_h: np.ndarray,
               lab_v: np.ndarray, sym: int, dcut: int, nsteps: int,
               first: str = "y", norm: str = "fro",
-              basis_seed: Optional[int] = None, q: int = 2) -> RunResult:
+              basis_seed: Optional[int] = None, q: int = 2,
+              keep_tensor: bool = False) -> RunResult:
     """Coarse-grain T (and impurity tensors) nsteps times; ln Z per site.
 
     ln Z / 2^N = ln c_0 + sum_n ln c_n / 2^n + ln Tr T_N / 2^N, where c_n is
@@ -575,15 +579,18 @@ def hotrg_run(T: np.ndarray, imps: Dict[int, np.ndarray], lab_h: np.ndarray,
     lnz = acc + math.log(tr) / 2.0 ** nsteps
     m = {k: float(np.einsum("llUU->", v)) / tr for k, v in imps.items()}
     nan = float("nan")
-    return RunResult(lnz, m.get(IMP_COS1, nan), m.get(IMP_COS2, nan),
-                     logs, math.log(c0), tr, m.get(IMP_COS1_SQ, nan), m.get(IMP_COS2_SQ, nan))
+    out = RunResult(lnz, m.get(IMP_COS1, nan), m.get(IMP_COS2, nan),
+                    logs, math.log(c0), tr, m.get(IMP_COS1_SQ, nan), m.get(IMP_COS2_SQ, nan))
+    if keep_tensor:
+        out.tensor, out.labels_hv = T, (lab_h, lab_v)
+    return out
 
 
 def run_point(beta: float, delta: float, h: float = 0.0, h1: float = 0.0,
               nmax: int = 3, dcut: int = 12, nsteps: int = 30,
               nquad: int = 4096, impurities: int = IMP_COS1 | IMP_COS2,
               first: str = "y", norm: str = "fro", basis_seed: Optional[int] = None,
-              q: int = 2, **_ignored) -> RunResult:
+              q: int = 2, keep_tensor: bool = False, **_ignored) -> RunResult:
     """One HOTRG run from the gXY parameters (the full problem statement)."""
     q = 2 if q == 0 else int(q)
     sym = symmetry_of(h, h1)
@@ -595,7 +602,7 @@ def run_point(beta: float, delta: float, h: float = 0.0, h1: float = 0.0,
     T, imps = initial_tensors(beta, delta, h, h1, nmax, nquad, impurities, q)
     lab = leg_labels(nmax, sym, q)
     r = hotrg_run(T, imps, lab, lab, sym, dcut, nsteps, first=first, norm=norm,
-                  basis_seed=basis_seed, q=q)
+                  basis_seed=basis_seed, q=q, keep_tensor=keep_tensor)
     # susceptibility from the fluctuation of the site average (Ch. 3, eq. susc
     # as beta V (<m^2> - <m>^2) at the field of the run), V = 2^nsteps
     V = 2.0 ** nsteps
