@@ -264,19 +264,37 @@ LegLabels leg_labels(const std::vector<int> &lab, int mod) {
   return L;
 }
 
-// Offset lists keyed by (integer key in [lo, hi], label slot).
-struct KeyedLists {
+// Offset lists keyed by (integer key in [lo, hi], label slot), stored flat
+// (one array per list kind, slot s spanning [start[s], start[s + 1])):
+// filled by a counting pass and a filling pass that visit the entries in
+// the same order, so each slot keeps the order in which its entries were
+// produced.
+struct FlatLists {
   int lo = 0, nk = 0, nl = 0;
-  std::vector<std::vector<int64_t>> first, second;
-  KeyedLists(int lo_, int hi_, int nl_) : lo(lo_), nk(hi_ - lo_ + 1), nl(nl_) {
+  std::vector<int64_t> start, first, second;
+  FlatLists(int lo_, int hi_, int nl_) : lo(lo_), nk(hi_ - lo_ + 1), nl(nl_) {
     if (nk < 0) nk = 0;
-    first.resize((size_t)nk * nl);
-    second.resize((size_t)nk * nl);
+    start.assign((size_t)nk * nl + 1, 0);
   }
   int at(int key, int slot) const {
     return (key < lo || key >= lo + nk) ? -1 : (key - lo) * nl + slot;
   }
+  int64_t size(int s) const { return s < 0 ? 0 : start[s + 1] - start[s]; }
+  // after the counts are in start[s + 1]: offsets, storage, fill cursors
+  std::vector<int64_t> finish_counts() {
+    for (size_t s = 1; s < start.size(); ++s) start[s] += start[s - 1];
+    first.resize(start.back());
+    second.resize(start.back());
+    return std::vector<int64_t>(start.begin(), start.end() - 1);
+  }
 };
+
+// Appends [b, e) to the table and returns where it starts.
+int64_t put_range(TablePlan &tp, const int64_t *b, const int64_t *e) {
+  const int64_t at = (int64_t)tp.tab.size();
+  tp.tab.insert(tp.tab.end(), b, e);
+  return at;
+}
 
 }  // namespace
 
@@ -303,17 +321,36 @@ Launch plan_proj_x(const StepLegs &S, int a0, int a1, const QSet &sA, TablePlan 
         lo = std::min(lo, k);
         hi = std::max(hi, k);
       }
-  KeyedLists cols(lo, hi, nl);
+  FlatLists cols(lo, hi, nl);
+  for (int r1 = 0; r1 < Dh; ++r1)
+    for (int u = 0; u < Dv; ++u)
+      for (int li = 0; li < nl; ++li)
+        cols.start[cols.at(qnorm(S.lh[r1] + S.lv[u] - V.q[li], mod), li) + 1] +=
+            (int64_t)V.members[li].size();
+  std::vector<int64_t> cur = cols.finish_counts();
   for (int r1 = 0; r1 < Dh; ++r1)
     for (int u = 0; u < Dv; ++u)
       for (int li = 0; li < nl; ++li) {
-        const int at = cols.at(qnorm(S.lh[r1] + S.lv[u] - V.q[li], mod), li);
-        auto &bf = cols.first[at], &bs = cols.second[at];
+        int64_t &c = cur[cols.at(qnorm(S.lh[r1] + S.lv[u] - V.q[li], mod), li)];
         for (int i : V.members[li]) {
-          bf.push_back((int64_t)r1 * Dv * Dv + (int64_t)u * Dv + i);
-          bs.push_back((int64_t)r1 * Dv * W + (int64_t)u * W + S.vrank[i]);
+          cols.first[c] = (int64_t)r1 * Dv * Dv + (int64_t)u * Dv + i;
+          cols.second[c] = (int64_t)r1 * Dv * W + (int64_t)u * W + S.vrank[i];
+          ++c;
         }
       }
+  // table size of the groups below, so the table grows once
+  int64_t total = 0;
+  for (const auto &kv : rows) {
+    const int c = kv.first;
+    auto il = l1s.find(c);
+    const int64_t nk1 = il != l1s.end() ? (int64_t)il->second.size() : 0;
+    for (int li = 0; li < nl; ++li) {
+      int64_t nc = 0;
+      for (int sv : sA) nc += cols.size(cols.at(qnorm(c - sv, mod), li));
+      if (nc) total += 2 * (int64_t)kv.second.size() + 2 * nk1 + 2 * nc;
+    }
+  }
+  tp.tab.reserve(tp.tab.size() + total);
   std::vector<GSpec> gs;
   for (const auto &kv : rows) {
     const int c = kv.first;
@@ -327,26 +364,32 @@ Launch plan_proj_x(const StepLegs &S, int a0, int a1, const QSet &sA, TablePlan 
       }
     for (int li = 0; li < nl; ++li) {
       const int i0 = V.members[li][0];
-      std::vector<int64_t> bc, cc, cr;
-      for (int sv : sA) {
-        const int at = cols.at(qnorm(c - sv, mod), li);
-        if (at < 0) continue;
-        bc.insert(bc.end(), cols.first[at].begin(), cols.first[at].end());
-        cc.insert(cc.end(), cols.second[at].begin(), cols.second[at].end());
-      }
-      if (bc.empty()) continue;
-      for (const PI &p : kv.second)
-        cr.push_back((int64_t)(p.first - a0) * per_a + S.pos[(size_t)p.second * Dv + i0]);
+      int64_t nc = 0;
+      for (int sv : sA) nc += cols.size(cols.at(qnorm(c - sv, mod), li));
+      if (nc == 0) continue;
       GSpec g;
       g.M = (int32_t)ar.size();
-      g.N = (int32_t)bc.size();
+      g.N = (int32_t)nc;
       g.K = (int32_t)ac.size();
       g.ar = put(tp, ar);
       g.ac = put(tp, ac);
       g.br = put(tp, br);
-      g.bc = put(tp, bc);
-      g.cr = put(tp, cr);
-      g.cc = put(tp, cc);
+      g.bc = (int64_t)tp.tab.size();
+      for (int sv : sA) {
+        const int at = cols.at(qnorm(c - sv, mod), li);
+        if (at >= 0)
+          put_range(tp, cols.first.data() + cols.start[at], cols.first.data() + cols.start[at + 1]);
+      }
+      g.cr = (int64_t)tp.tab.size();
+      for (const PI &p : kv.second)
+        tp.tab.push_back((int64_t)(p.first - a0) * per_a + S.pos[(size_t)p.second * Dv + i0]);
+      g.cc = (int64_t)tp.tab.size();
+      for (int sv : sA) {
+        const int at = cols.at(qnorm(c - sv, mod), li);
+        if (at >= 0)
+          put_range(tp, cols.second.data() + cols.start[at],
+                    cols.second.data() + cols.start[at + 1]);
+      }
       gs.push_back(g);
     }
   }
@@ -376,12 +419,19 @@ Launch plan_proj_y(const StepLegs &S, int a0, int a1, const QSet &sA, const QSet
         lo = std::min(lo, k);
         hi = std::max(hi, k);
       }
-  KeyedLists rows_by_rho(lo, hi, 1);
+  FlatLists rows_by_rho(lo, hi, 1);
+  for (int a = a0; a < a1; ++a)
+    for (int r1 = 0; r1 < Dh; ++r1)
+      for (int li = 0; li < nl; ++li)
+        rows_by_rho.start[rows_by_rho.at(qnorm(S.ln[a] - S.lh[r1] - V.q[li], mod), 0) + 1] +=
+            (int64_t)V.members[li].size();
+  std::vector<int64_t> cur = rows_by_rho.finish_counts();
   for (int a = a0; a < a1; ++a)
     for (int r1 = 0; r1 < Dh; ++r1)
       for (int li = 0; li < nl; ++li) {
-        auto &v = rows_by_rho.first[rows_by_rho.at(qnorm(S.ln[a] - S.lh[r1] - V.q[li], mod), 0)];
-        for (int u : V.members[li]) v.push_back((((int64_t)(a - a0) * Dh + r1) * Dv + u) * W);
+        int64_t &c = cur[rows_by_rho.at(qnorm(S.ln[a] - S.lh[r1] - V.q[li], mod), 0)];
+        for (int u : V.members[li])
+          rows_by_rho.first[c++] = (((int64_t)(a - a0) * Dh + r1) * Dv + u) * W;
       }
   // (l2, i) and (r2, d) in block order: each kappa (nu) is one contiguous range
   std::map<int, std::vector<int64_t>> ks_by_kappa, cols_by_nu;
@@ -393,7 +443,7 @@ Launch plan_proj_y(const StepLegs &S, int a0, int a1, const QSet &sA, const QSet
       cols_by_nu[qnorm(S.lh[r2] - S.lv[d], mod)].push_back(S.pos[(size_t)r2 * Dv + d]);
   std::vector<int> kappas;
   for (int k = 0; k < rows_by_rho.nk; ++k)
-    if (!rows_by_rho.first[k].empty())
+    if (rows_by_rho.size(k) > 0)
       for (int s : sA) kappas.push_back(qnorm(lo + k - s, mod));
   std::sort(kappas.begin(), kappas.end());
   kappas.erase(std::unique(kappas.begin(), kappas.end()), kappas.end());
@@ -405,16 +455,15 @@ Launch plan_proj_y(const StepLegs &S, int a0, int a1, const QSet &sA, const QSet
     return (int32_t)v.size();
   };
   // One group per (kappa, nu): rows through the table, the reduction range
-  // of kappa and the column range of nu as bases (contiguous groups).
+  // of kappa and the column range of nu as bases (contiguous groups). The
+  // rows of a kappa enter the table once, before its first group.
   std::vector<GSpec> gs;
   for (int kappa : kappas) {
-    std::vector<int64_t> rows;
-    for (int k = 0; k < rows_by_rho.nk; ++k) {
-      const auto &v = rows_by_rho.first[k];
-      if (!v.empty() && in_set(qnorm(lo + k - kappa, mod), sA))
-        rows.insert(rows.end(), v.begin(), v.end());
-    }
-    if (rows.empty()) continue;
+    int64_t nrows = 0;
+    for (int k = 0; k < rows_by_rho.nk; ++k)
+      if (rows_by_rho.size(k) > 0 && in_set(qnorm(lo + k - kappa, mod), sA))
+        nrows += rows_by_rho.size(k);
+    if (nrows == 0) continue;
     int64_t k0 = 0;
     int32_t K = 0;
     auto ik = ks_by_kappa.find(kappa);
@@ -425,9 +474,15 @@ Launch plan_proj_y(const StepLegs &S, int a0, int a1, const QSet &sA, const QSet
       int64_t c0 = 0;
       const int32_t N = range_of(kv.second, c0);
       if (N == 0) continue;
-      if (rows_at < 0) rows_at = put(tp, rows);
+      if (rows_at < 0) {
+        rows_at = (int64_t)tp.tab.size();
+        for (int k = 0; k < rows_by_rho.nk; ++k)
+          if (rows_by_rho.size(k) > 0 && in_set(qnorm(lo + k - kappa, mod), sA))
+            put_range(tp, rows_by_rho.first.data() + rows_by_rho.start[k],
+                      rows_by_rho.first.data() + rows_by_rho.start[k + 1]);
+      }
       GSpec g;
-      g.M = (int32_t)rows.size();
+      g.M = (int32_t)nrows;
       g.N = N;
       g.K = K;
       g.ar = rows_at;
@@ -462,17 +517,36 @@ Launch plan_proj_t(const StepLegs &S, int a0, int a1, const QSet &sY, TablePlan 
         lo = std::min(lo, k);
         hi = std::max(hi, k);
       }
-  KeyedLists rows(lo, hi, nl);
+  FlatLists rows(lo, hi, nl);
+  for (int a = a0; a < a1; ++a)
+    for (int u = 0; u < Dv; ++u)
+      for (int li = 0; li < nl; ++li)
+        rows.start[rows.at(qnorm(S.ln[a] - S.lv[u] + V.q[li], mod), li) + 1] +=
+            (int64_t)V.members[li].size();
+  std::vector<int64_t> cur = rows.finish_counts();
   for (int a = a0; a < a1; ++a)
     for (int u = 0; u < Dv; ++u)
       for (int li = 0; li < nl; ++li) {
-        const int at = rows.at(qnorm(S.ln[a] - S.lv[u] + V.q[li], mod), li);
-        auto &rf = rows.first[at], &rs = rows.second[at];
+        int64_t &c = cur[rows.at(qnorm(S.ln[a] - S.lv[u] + V.q[li], mod), li)];
         for (int d : V.members[li]) {
-          rf.push_back((int64_t)(a - a0) * per_a + (int64_t)u * W + S.vrank[d]);
-          rs.push_back((int64_t)a * Dn * Dv * Dv + (int64_t)u * Dv + d);
+          rows.first[c] = (int64_t)(a - a0) * per_a + (int64_t)u * W + S.vrank[d];
+          rows.second[c] = (int64_t)a * Dn * Dv * Dv + (int64_t)u * Dv + d;
+          ++c;
         }
       }
+  // table size of the groups below, so the table grows once
+  int64_t total = 0;
+  for (const auto &kv : bs) {
+    const int sigma = kv.first;
+    auto ik = ks.find(sigma);
+    const int64_t nk = ik != ks.end() ? (int64_t)ik->second.size() : 0;
+    for (int li = 0; li < nl; ++li) {
+      int64_t nr = 0;
+      for (int sv : sY) nr += rows.size(rows.at(qnorm(sigma + sv, mod), li));
+      if (nr) total += 2 * nr + 2 * nk + 2 * (int64_t)kv.second.size();
+    }
+  }
+  tp.tab.reserve(tp.tab.size() + total);
   std::vector<GSpec> gs;
   for (const auto &kv : bs) {
     const int sigma = kv.first;
@@ -486,26 +560,32 @@ Launch plan_proj_t(const StepLegs &S, int a0, int a1, const QSet &sY, TablePlan 
     }
     for (int li = 0; li < nl; ++li) {
       const int d0 = V.members[li][0];
-      std::vector<int64_t> ar, cr, ac;
+      int64_t nr = 0;
+      for (int sv : sY) nr += rows.size(rows.at(qnorm(sigma + sv, mod), li));
+      if (nr == 0) continue;
+      GSpec g;
+      g.M = (int32_t)nr;
+      g.N = (int32_t)bc.size();
+      g.K = ik != ks.end() ? (int32_t)ik->second.size() : 0;
+      g.ar = (int64_t)tp.tab.size();
       for (int sv : sY) {
         const int at = rows.at(qnorm(sigma + sv, mod), li);
-        if (at < 0) continue;
-        ar.insert(ar.end(), rows.first[at].begin(), rows.first[at].end());
-        cr.insert(cr.end(), rows.second[at].begin(), rows.second[at].end());
+        if (at >= 0)
+          put_range(tp, rows.first.data() + rows.start[at], rows.first.data() + rows.start[at + 1]);
       }
-      if (ar.empty()) continue;
+      g.ac = (int64_t)tp.tab.size();
       if (ik != ks.end())
         for (const PI &p : ik->second)
-          ac.push_back((int64_t)p.first * Dv * W + S.pos[(size_t)p.second * Dv + d0]);
-      GSpec g;
-      g.M = (int32_t)ar.size();
-      g.N = (int32_t)bc.size();
-      g.K = (int32_t)ac.size();
-      g.ar = put(tp, ar);
-      g.ac = put(tp, ac);
+          tp.tab.push_back((int64_t)p.first * Dv * W + S.pos[(size_t)p.second * Dv + d0]);
       g.br = put(tp, br);
       g.bc = put(tp, bc);
-      g.cr = put(tp, cr);
+      g.cr = (int64_t)tp.tab.size();
+      for (int sv : sY) {
+        const int at = rows.at(qnorm(sigma + sv, mod), li);
+        if (at >= 0)
+          put_range(tp, rows.second.data() + rows.start[at],
+                    rows.second.data() + rows.start[at + 1]);
+      }
       g.cc = put(tp, cc);
       gs.push_back(g);
     }
