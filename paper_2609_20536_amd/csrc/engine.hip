@@ -1138,6 +1138,16 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
 
   int32_t *hp = ctx->noalloc ? (int32_t *)ctx->noalloc_host : (int32_t *)ctx->pinned;
   const int inject_nan_step = (int)env_size("GXY_INJECT_NAN_STEP", 0);
+  // the next step's environment tables, planned on a host thread as soon as
+  // this step's kept labels are known (used only if the legs it was planned
+  // for are the next step's)
+  struct EnvPlan {
+    int Dh = 0, Dv = 0;
+    std::vector<int> lh, lv;
+    TablePlan tp;
+    Launch le[3], re[3];
+  };
+  std::future<std::shared_ptr<EnvPlan>> env_next;
   for (int n = 1; n <= p.nsteps; ++n) {
     const StepDims &sd = pl.steps[n - 1];
     // buffers of this step's parity; the impurity stream read them last in
@@ -1186,11 +1196,16 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
         env_gemms(b.T, Dh, Dv, b.envA, b.envB, b.E, false, s);
         env_gemms(b.T, Dh, Dv, b.envA, b.envB, b.E + nf * nf, true, s);
       } else {
-        StepLegs SL{Dh, Dv, Dn, mod, lh, lv, {}};
-        TablePlan tp;
-        Launch le[3], re[3];
-        plan_env(SL, false, tp, le);
-        plan_env(SL, true, tp, re);
+        std::shared_ptr<EnvPlan> ep;
+        if (env_next.valid()) ep = env_next.get();
+        if (!ep || ep->Dh != Dh || ep->Dv != Dv || ep->lh != lh || ep->lv != lv) {
+          ep = std::make_shared<EnvPlan>();
+          StepLegs SL{Dh, Dv, Dn, mod, lh, lv, {}};
+          plan_env(SL, false, ep->tp, ep->le);
+          plan_env(SL, true, ep->tp, ep->re);
+        }
+        const TablePlan &tp = ep->tp;
+        const Launch *le = ep->le, *re = ep->re;
         upload_plan(ctx, 0, tp, b.tab_env, pl.tab_env, b.grp_env, pl.grp_env, s);
         run_launch(le[0], b.grp_env, b.tab_env, b.T, b.T, b.envA, 1.0, 0.0, s);
         run_launch(le[1], b.grp_env, b.tab_env, b.T, b.T, b.envB, 1.0, 0.0, s);
@@ -1275,6 +1290,45 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
       res.near_ties += info.ties;
       tm.end(3);
     }
+    if (sym != SYM_NONE && n < p.nsteps) {
+      // the legs the next step's environments will see: this step's output
+      // (back in y-orientation after an x-step), then the next step's own
+      // transposition
+      auto ep = std::make_shared<EnvPlan>();
+      ep->Dh = Dn;
+      ep->Dv = Dv;
+      ep->lh = new_lh;
+      ep->lv = lv;
+      if (sd.xstep) {
+        std::swap(ep->Dh, ep->Dv);
+        std::swap(ep->lh, ep->lv);
+      }
+      if (pl.steps[n].xstep) {
+        std::swap(ep->Dh, ep->Dv);
+        std::swap(ep->lh, ep->lv);
+      }
+      const int md = mod;
+      env_next = std::async(std::launch::async, [ep, md]() {
+        StepLegs SL{ep->Dh, ep->Dv, 0, md, ep->lh, ep->lv, {}};
+        plan_env(SL, false, ep->tp, ep->le);
+        plan_env(SL, true, ep->tp, ep->re);
+        return ep;
+      });
+    }
+    // the new pure tensor's norm and scaling, on the main stream: issued as
+    // soon as its last product is, so that the main stream goes on while the
+    // host issues the impurity stream's launches
+    bool normed = false;
+    auto normalise = [&]() {
+      if (normed) return;
+      normed = true;
+      const int64_t nTo = (int64_t)Dn * Dn * Dv * Dv;
+      launch_fro_norm(b.Tn, nTo, b.partial, b.nrm + 3 * n, s);
+      launch_scale(b.Tn, nTo, b.nrm + 3 * n + 2, s);
+      // test hook of the failure path: one NaN planted after step n's
+      // normalisation (GXY_INJECT_NAN_STEP = n)
+      if (inject_nan_step == n) launch_fill(b.Tn, 1, NAN, s);
+    };
     // ---- projection T' = P^T M P (and impurities), chunked over a ----
     tm.begin();
     // bottom operands of the D^7 product: dense path [l][u][r][d]; charge
@@ -1362,6 +1416,9 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
           pt.k = k;
           parts.push_back(pt);
         }
+      int last_pure = -1;   // the part with the pure tensor's last products
+      for (int i = 0; i < (int)parts.size(); ++i)
+        if (parts[i].k < 0) last_pure = i;
       // jobs in the order the stream consumes them
       std::vector<std::pair<int, int>> order;
       for (int i = 0; i < (int)parts.size(); ++i) {
@@ -1461,6 +1518,7 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
           // chains: the same steps/s either way, and the D^7 launches
           // average 3.3 ms instead of 4.0)
           if (nimp > 0) imp_start();
+          if (i == last_pure) normalise();
         } else {
           // (both Y products write the same blocks: those whose row and
           // column charges differ by a charge of the impurity)
@@ -1484,11 +1542,7 @@ static void run_one(gxy_ctx *ctx, const gxy_point &p, gxy_result &res, RunLog &l
     tm.begin();
     Dh = Dn;
     nT = (int64_t)Dh * Dh * Dv * Dv;
-    launch_fro_norm(b.Tn, nT, b.partial, b.nrm + 3 * n, s);
-    launch_scale(b.Tn, nT, b.nrm + 3 * n + 2, s);
-    // test hook of the failure path: one NaN planted after step n's
-    // normalisation (GXY_INJECT_NAN_STEP = n)
-    if (inject_nan_step == n) launch_fill(b.Tn, 1, NAN, s);
+    normalise();
     std::swap(b.T, b.Tn);
     stream_after(ctx, si, s, 2);
     for (int k = 0; k < nimp; ++k) {
